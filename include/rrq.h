@@ -1,0 +1,151 @@
+/*
+ * rrq.h - C ABI of the MI355X (gfx950) library for recursive reduction quadrature (RRQ):
+ * assembly of the sparse near-field quadrature-correction matrix of the Laplace single-layer
+ * (S), double-layer (D) and normal-derivative (S', D') potentials on quadrilateral patches.
+ *
+ * The operation is the one stated as the input/output of the algorithm in Sec. 4 of
+ * Jiang & Zhu, "Recursive reduction quadrature for the evaluation of Laplace layer potentials
+ * in three dimensions": patches with collocation nodes and boundary-edge nodes plus targets
+ * go in; with Step 2 skipped as in the remark that follows the algorithm, the library returns
+ * for every (target, near patch) pair the row of weights [w^T(x) A^+]_0 that maps nodal
+ * densities to the potential at the target, for S (Theorem thm:slpreduction), D
+ * (Lemma lem:dlpreduction, eq. wlmdef), S' (Sec. 3.6) and D' (Sec. 3.7).  With
+ * RRQ_F_CORRECTION the smooth-rule weights K(x, r_j) w_j are subtracted (the splitting
+ * D = D_smooth + D_RRQ of eq. dlpsplitting), giving the sparse correction matrix.
+ *
+ * Conventions
+ *  - Pointers are DEVICE pointers unless a comment says HOST.  Arrays of 3-vectors are
+ *    structure-of-arrays: x[0..n), y[0..n), z[0..n) at xyz, xyz + n, xyz + 2n.
+ *  - Patch P has order q_P (q_P x q_P tensor Gauss-Legendre nodes; basis order p = q_P),
+ *    nodes node_off[P] .. node_off[P+1] (node index a*q + b, parameter v = t_a, u = t_b), and
+ *    4 edges ordered counter-clockwise about the outward normal, each with ptilde_P =
+ *    2 q_P samples at increasing Gauss-Legendre parameters, stored at edge_off[P] + e*ptilde
+ *    + i.  Neighbouring patches are expected to share edge curves.
+ *  - Supported orders q: 4, 5, 6, 8, 10.  Other orders return RRQ_ERR_UNSUPPORTED.
+ *  - Near list: CSR by target (near_ptr[T+1], near_patch[nnz]).  Weight blocks are stored
+ *    target-major in near-list order: the block of pair k occupies [pair_off[k],
+ *    pair_off[k+1]) with pair_off[k+1] - pair_off[k] = q_P^2, entry j = node j of patch P.
+ *  - All calls are asynchronous on the caller's HIP stream (hipStream_t passed as void*;
+ *    NULL = the default stream) unless noted.  Argument errors are detected on the host and
+ *    returned before any launch.  Launch errors return RRQ_ERR_DEVICE.  No exception crosses
+ *    the ABI.
+ *  - A plan owns its device memory (maps, edge tables, frames); the caller owns every other
+ *    buffer.  A plan may be used from several streams at once for assembly; refit and
+ *    destroy must not overlap other calls on the same plan.
+ */
+#ifndef RRQ_H
+#define RRQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RRQ_OK = 0,
+  RRQ_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, bad option)       */
+  RRQ_ERR_DEVICE = -2,      /* a HIP call or kernel launch failed                           */
+  RRQ_ERR_OOM = -3,         /* device allocation failed                                     */
+  RRQ_ERR_UNSUPPORTED = -5, /* order or option outside what this build supports             */
+  RRQ_ERR_BUFFER = -6       /* a caller buffer is too small                                 */
+} rrq_status;
+
+/* kernel mask bits */
+enum { RRQ_K_S = 1, RRQ_K_D = 2, RRQ_K_SP = 4, RRQ_K_DP = 8, RRQ_K_ALL = 15 };
+
+/* assembly flags */
+enum {
+  RRQ_F_CORRECTION = 1, /* subtract the smooth rule K(x, r_j) w_j (self node skipped)        */
+  RRQ_F_ONSURF_PV = 2,  /* self targets: principal value for D and S' (else exterior limit) */
+  RRQ_F_PLAIN = 8,      /* one workgroup per pair (reference form) instead of the batched form */
+  RRQ_F_LEARNED = 16    /* batched form with the learned Newton initial guess (needs a model) */
+};
+
+typedef struct rrq_plan rrq_plan;
+
+typedef struct {
+  int32_t npatch;
+  const int32_t* order_host; /* HOST [P] order q_P of each patch                          */
+  const int32_t* order;      /* [P] same, on the device                                    */
+  const int64_t* node_off;   /* [P+1]                                                      */
+  const double* node_xyz;    /* [3][N] node coordinates                                    */
+  const double* node_nrm;    /* [3][N] unit outward normals                                */
+  const double* node_wt;     /* [N] smooth-rule weights (GL weights times area element)    */
+  const int64_t* edge_off;   /* [P+1] = prefix sum of 4 * ptilde_P                         */
+  const double* edge_xyz;    /* [3][E] edge samples                                        */
+  int64_t nnode;             /* N */
+  int64_t nedge;             /* E */
+} rrq_surface;
+
+typedef struct {
+  int64_t ntarget;           /* T */
+  int64_t nnz;               /* number of near pairs                                       */
+  const double* xyz;         /* [3][T] target points                                       */
+  const double* nrm;         /* [3][T] target unit normals nu' (used by S' and D')         */
+  const int32_t* self_patch; /* [T] patch whose node the target is, or -1                  */
+  const int32_t* self_node;  /* [T] local node index within self_patch, or -1              */
+  const int64_t* near_ptr;   /* [T+1] CSR row pointer                                      */
+  const int32_t* near_patch; /* [nnz] near patches of each target                          */
+} rrq_targets;
+
+typedef struct {
+  double rho_far;       /* Bernstein radius above which an edge uses the plain GL rule;
+                           <= 0 selects 10^(8/ptilde)                                       */
+  double newton_tol;    /* Newton step tolerance (relative); <= 0 selects 1e-14             */
+  int32_t newton_maxit; /* <= 0 selects 60                                                  */
+  int32_t tile_targets; /* batched form: targets per workgroup tile; <= 0 = autotuned     */
+} rrq_options;
+
+typedef struct {
+  int64_t pairs;          /* pairs assembled                                               */
+  int64_t near_edges;     /* (pair, edge) combinations integrated by singularity swap      */
+  int64_t newton_iters;   /* total Newton iterations                                       */
+  int64_t newton_fail;    /* edges whose Newton solve did not converge (plain rule used)   */
+  int64_t learned_accept; /* edges whose learned initial guess was accepted                */
+  int64_t newton_max;     /* largest iteration count of one edge                           */
+} rrq_stats;
+
+/* Create a plan for a surface: allocates the per-patch frames, coefficient maps and edge
+ * tables, then computes them (Steps 1-3: source-only) on `stream`.  `opts` may be NULL. */
+rrq_status rrq_plan_create(const rrq_surface* surf, const rrq_options* opts, void* stream,
+                           rrq_plan** out);
+
+/* Recompute the source-only data for a surface with the same patch count and orders
+ * (new node/edge coordinates) into the plan's existing buffers.  Allocates nothing. */
+rrq_status rrq_plan_refit(rrq_plan* plan, const rrq_surface* surf, void* stream);
+
+rrq_status rrq_plan_destroy(rrq_plan* plan);
+
+/* Bytes of caller-provided device workspace that rrq_assemble needs for this near list. */
+rrq_status rrq_workspace_size(const rrq_plan* plan, const rrq_targets* tg, size_t* bytes);
+
+/* pair_off[nnz+1] (device) = prefix sum of q_P^2 over the near list.  Synchronous: also
+ * returns the total number of weights per kernel in *nweights (HOST). */
+rrq_status rrq_pair_offsets(const rrq_plan* plan, const rrq_targets* tg, int64_t* pair_off,
+                            int64_t* nweights, void* stream);
+
+/* Assemble the weight blocks of every near pair.  out_* are [nweights] device arrays (NULL
+ * for a kernel not in kmask).  pair_off from rrq_pair_offsets.  `workspace` of at least
+ * rrq_workspace_size bytes.  If `stats` (HOST) is non-NULL the call synchronises the
+ * stream and fills it. */
+rrq_status rrq_assemble(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
+                        uint32_t flags, double* out_S, double* out_D, double* out_Sp,
+                        double* out_Dp, const int64_t* pair_off, void* workspace,
+                        size_t workspace_bytes, void* stream, rrq_stats* stats);
+
+/* pot[t] = sum over the near pairs of target t of W[block] . density[nodes of P]
+ * (the sparse correction applied to nodal densities).  pot_* are [T]. */
+rrq_status rrq_apply(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
+                     const double* w_S, const double* w_D, const double* w_Sp,
+                     const double* w_Dp, const int64_t* pair_off, const double* density,
+                     double* pot_S, double* pot_D, double* pot_Sp, double* pot_Dp,
+                     void* stream);
+
+const char* rrq_status_string(rrq_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RRQ_H */

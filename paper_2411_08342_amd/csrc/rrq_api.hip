@@ -1,0 +1,408 @@
+// Host runtime behind the C ABI of include/rrq.h: plan memory, constant tables, argument
+// validation and kernel launches.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "rrq_internal.h"
+
+using namespace rrq;
+
+namespace {
+
+bool supported_order(int q) {
+  for (int i = 0; i < kNumOrders; ++i)
+    if (kOrders[i] == q) return true;
+  return false;
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+}  // namespace
+
+struct rrq_plan {
+  int32_t P = 0;
+  int64_t N = 0, E = 0;
+  std::vector<int32_t> order_h;
+  std::vector<int64_t> node_off_h, edge_off_h;
+  rrq_options opt{};
+  // device copies / products
+  int32_t* order_d = nullptr;
+  int64_t* node_off_d = nullptr;
+  int64_t* edge_off_d = nullptr;
+  double* node_xyz_d = nullptr;   // [3][N]
+  double* node_nrm_d = nullptr;
+  double* node_wt_d = nullptr;
+  double* frame_d = nullptr;
+  double* node_loc_d = nullptr;
+  double* edge_loc_d = nullptr;
+  double* edge_tan_d = nullptr;
+  double* edge_coef_d = nullptr;
+  double* maps_d = nullptr;
+  int64_t* map_off_d = nullptr;
+  double* tabs_d = nullptr;
+  int64_t* tab_off_d = nullptr;
+  double* fit_ws_d = nullptr;
+  int64_t fit_ws_per_block = 0;
+  int fit_blocks = 0;
+  // per order
+  std::vector<int32_t> patches_h[kMaxQ + 1];
+  int32_t* patches_d[kMaxQ + 1] = {};
+  OrderDev od[kMaxQ + 1] = {};
+  std::vector<void*> const_bufs;
+  double rho_far[kMaxQ + 1] = {};
+
+  PlanDev dev() const {
+    PlanDev d;
+    d.npatch = P;
+    d.N = N;
+    d.E = E;
+    d.order = order_d;
+    d.node_off = node_off_d;
+    d.edge_off = edge_off_d;
+    d.node_xyz = node_xyz_d;
+    d.node_nrm = node_nrm_d;
+    d.node_wt = node_wt_d;
+    d.frame = frame_d;
+    d.node_loc = node_loc_d;
+    d.edge_loc = edge_loc_d;
+    d.edge_tan = edge_tan_d;
+    d.edge_coef = edge_coef_d;
+    d.maps = maps_d;
+    d.map_off = map_off_d;
+    d.tabs = tabs_d;
+    d.tab_off = tab_off_d;
+    return d;
+  }
+};
+
+static void plan_free(rrq_plan* p) {
+  if (!p) return;
+  void* ptrs[] = {p->order_d, p->node_off_d, p->edge_off_d, p->node_xyz_d, p->node_nrm_d,
+                  p->node_wt_d, p->frame_d, p->node_loc_d, p->edge_loc_d, p->edge_tan_d,
+                  p->edge_coef_d, p->maps_d, p->map_off_d, p->tabs_d, p->tab_off_d,
+                  p->fit_ws_d};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (int q = 0; q <= kMaxQ; ++q)
+    if (p->patches_d[q]) (void)hipFree(p->patches_d[q]);
+  for (void* b : p->const_bufs) (void)hipFree(b);
+  delete p;
+}
+
+static rrq_status upload_consts(rrq_plan* p, int q) {
+  OrderTables T = build_order_tables(q, 2 * q);
+  auto up = [&](const void* src, size_t bytes, void** dst) -> bool {
+    if (hipMalloc(dst, bytes ? bytes : 8) != hipSuccess) return false;
+    p->const_bufs.push_back(*dst);
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  OrderDev& o = p->od[q];
+  o.q = q;
+  o.pt = T.pt;
+  o.np = T.np;
+  o.njk = T.njk;
+  void* b;
+  if (!up(T.gl_t.data(), T.gl_t.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.gl_t = (const double*)b;
+  if (!up(T.gl_w.data(), T.gl_w.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.gl_w = (const double*)b;
+  if (!up(T.glq_w.data(), T.glq_w.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.glq_w = (const double*)b;
+  if (!up(T.U.data(), T.U.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.U = (const double*)b;
+  if (!up(T.lag_m1.data(), T.lag_m1.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.lag_m1 = (const double*)b;
+  if (!up(T.dlp_ptr.data(), T.dlp_ptr.size() * 4, &b)) return RRQ_ERR_OOM;
+  o.dlp_ptr = (const int32_t*)b;
+  if (!up(T.dlp.data(), T.dlp.size() * sizeof(Term), &b)) return RRQ_ERR_OOM;
+  o.dlp = (const Term*)b;
+  if (!up(T.slp_ptr.data(), T.slp_ptr.size() * 4, &b)) return RRQ_ERR_OOM;
+  o.slp_ptr = (const int32_t*)b;
+  if (!up(T.slp.data(), T.slp.size() * sizeof(Term), &b)) return RRQ_ERR_OOM;
+  o.slp = (const Term*)b;
+  return RRQ_OK;
+}
+
+static rrq_status check_surface(const rrq_surface* s) {
+  if (!s || s->npatch <= 0 || !s->order_host || !s->order || !s->node_off || !s->node_xyz ||
+      !s->node_nrm || !s->node_wt || !s->edge_off || !s->edge_xyz || s->nnode <= 0 ||
+      s->nedge <= 0)
+    return RRQ_ERR_ARG;
+  int64_t N = 0, E = 0;
+  for (int P = 0; P < s->npatch; ++P) {
+    const int q = s->order_host[P];
+    if (!supported_order(q)) return RRQ_ERR_UNSUPPORTED;
+    N += (int64_t)q * q;
+    E += 8LL * q;
+  }
+  if (N != s->nnode || E != s->nedge) return RRQ_ERR_ARG;
+  return RRQ_OK;
+}
+
+static rrq_status run_fit(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
+  // plan copies of the smooth-rule data used by the correction
+  if (hipMemcpyAsync(p->node_xyz_d, s->node_xyz, 3 * p->N * 8, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(p->node_nrm_d, s->node_nrm, 3 * p->N * 8, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(p->node_wt_d, s->node_wt, p->N * 8, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess)
+    return RRQ_ERR_DEVICE;
+  PlanDev pd = p->dev();
+  rrq_surface sd = *s;
+  sd.node_off = p->node_off_d;
+  sd.edge_off = p->edge_off_d;
+  for (int qi = 0; qi < kNumOrders; ++qi) {
+    const int q = kOrders[qi];
+    const int cnt = (int)p->patches_h[q].size();
+    if (!cnt) continue;
+    if (launch_geometry(pd, sd, p->od[q], p->patches_d[q], cnt, st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+    if (launch_edge_tables(pd, p->od[q], p->patches_d[q], cnt, st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+    if (launch_fit(pd, p->od[q], p->patches_d[q], cnt, p->fit_ws_d, p->fit_ws_per_block,
+                   p->fit_blocks, st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+  }
+  return RRQ_OK;
+}
+
+extern "C" {
+
+const char* rrq_status_string(rrq_status s) {
+  switch (s) {
+    case RRQ_OK: return "ok";
+    case RRQ_ERR_ARG: return "invalid argument";
+    case RRQ_ERR_DEVICE: return "device error";
+    case RRQ_ERR_OOM: return "out of device memory";
+    case RRQ_ERR_UNSUPPORTED: return "unsupported order or option";
+    case RRQ_ERR_BUFFER: return "buffer too small";
+  }
+  return "unknown status";
+}
+
+rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* stream,
+                           rrq_plan** out) {
+  if (!out) return RRQ_ERR_ARG;
+  *out = nullptr;
+  rrq_status cs = check_surface(s);
+  if (cs != RRQ_OK) return cs;
+  rrq_plan* p = new (std::nothrow) rrq_plan();
+  if (!p) return RRQ_ERR_OOM;
+  if (opts) p->opt = *opts;
+  if (p->opt.newton_tol <= 0) p->opt.newton_tol = 1e-14;
+  if (p->opt.newton_maxit <= 0) p->opt.newton_maxit = 60;
+  p->P = s->npatch;
+  p->N = s->nnode;
+  p->E = s->nedge;
+  p->order_h.assign(s->order_host, s->order_host + s->npatch);
+  p->node_off_h.resize(p->P + 1);
+  p->edge_off_h.resize(p->P + 1);
+  std::vector<int64_t> map_off(p->P + 1), tab_off(p->P + 1);
+  p->node_off_h[0] = p->edge_off_h[0] = map_off[0] = tab_off[0] = 0;
+  int64_t maxws = 0;
+  for (int P = 0; P < p->P; ++P) {
+    const int q = p->order_h[P];
+    p->node_off_h[P + 1] = p->node_off_h[P] + (int64_t)q * q;
+    p->edge_off_h[P + 1] = p->edge_off_h[P] + 8LL * q;
+    map_off[P + 1] = map_off[P] + map_doubles(q);
+    tab_off[P + 1] = tab_off[P] + tab_doubles(q);
+    p->patches_h[q].push_back(P);
+    maxws = std::max(maxws, fit_ws_doubles(q));
+  }
+  hipStream_t st = (hipStream_t)stream;
+  bool ok = true;
+  ok &= dalloc(&p->order_d, p->P) == hipSuccess;
+  ok &= dalloc(&p->node_off_d, p->P + 1) == hipSuccess;
+  ok &= dalloc(&p->edge_off_d, p->P + 1) == hipSuccess;
+  ok &= dalloc(&p->node_xyz_d, 3 * p->N) == hipSuccess;
+  ok &= dalloc(&p->node_nrm_d, 3 * p->N) == hipSuccess;
+  ok &= dalloc(&p->node_wt_d, p->N) == hipSuccess;
+  ok &= dalloc(&p->frame_d, (size_t)p->P * kFrame) == hipSuccess;
+  ok &= dalloc(&p->node_loc_d, 6 * p->N) == hipSuccess;
+  ok &= dalloc(&p->edge_loc_d, 3 * p->E) == hipSuccess;
+  ok &= dalloc(&p->edge_tan_d, 3 * p->E) == hipSuccess;
+  ok &= dalloc(&p->edge_coef_d, 3 * p->E) == hipSuccess;
+  ok &= dalloc(&p->maps_d, map_off[p->P]) == hipSuccess;
+  ok &= dalloc(&p->map_off_d, p->P + 1) == hipSuccess;
+  ok &= dalloc(&p->tabs_d, tab_off[p->P]) == hipSuccess;
+  ok &= dalloc(&p->tab_off_d, p->P + 1) == hipSuccess;
+  p->fit_blocks = std::min(p->P, 512);
+  p->fit_ws_per_block = maxws;
+  ok &= dalloc(&p->fit_ws_d, (size_t)maxws * p->fit_blocks) == hipSuccess;
+  for (int q = 0; q <= kMaxQ && ok; ++q)
+    if (!p->patches_h[q].empty()) {
+      ok &= dalloc(&p->patches_d[q], p->patches_h[q].size()) == hipSuccess;
+      ok &= hipMemcpy(p->patches_d[q], p->patches_h[q].data(), p->patches_h[q].size() * 4,
+                      hipMemcpyHostToDevice) == hipSuccess;
+      if (ok && upload_consts(p, q) != RRQ_OK) ok = false;
+      p->rho_far[q] = p->opt.rho_far > 0 ? p->opt.rho_far : pow(10.0, 8.0 / (2 * q));
+    }
+  if (!ok) {
+    plan_free(p);
+    return RRQ_ERR_OOM;
+  }
+  ok &= hipMemcpy(p->order_d, p->order_h.data(), p->P * 4, hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemcpy(p->node_off_d, p->node_off_h.data(), (p->P + 1) * 8, hipMemcpyHostToDevice) ==
+        hipSuccess;
+  ok &= hipMemcpy(p->edge_off_d, p->edge_off_h.data(), (p->P + 1) * 8, hipMemcpyHostToDevice) ==
+        hipSuccess;
+  ok &= hipMemcpy(p->map_off_d, map_off.data(), (p->P + 1) * 8, hipMemcpyHostToDevice) ==
+        hipSuccess;
+  ok &= hipMemcpy(p->tab_off_d, tab_off.data(), (p->P + 1) * 8, hipMemcpyHostToDevice) ==
+        hipSuccess;
+  if (!ok) {
+    plan_free(p);
+    return RRQ_ERR_DEVICE;
+  }
+  rrq_status r = run_fit(p, s, st);
+  if (r != RRQ_OK) {
+    plan_free(p);
+    return r;
+  }
+  *out = p;
+  return RRQ_OK;
+}
+
+rrq_status rrq_plan_refit(rrq_plan* p, const rrq_surface* s, void* stream) {
+  if (!p) return RRQ_ERR_ARG;
+  rrq_status cs = check_surface(s);
+  if (cs != RRQ_OK) return cs;
+  if (s->npatch != p->P || s->nnode != p->N || s->nedge != p->E) return RRQ_ERR_ARG;
+  for (int P = 0; P < p->P; ++P)
+    if (s->order_host[P] != p->order_h[P]) return RRQ_ERR_ARG;
+  return run_fit(p, s, (hipStream_t)stream);
+}
+
+rrq_status rrq_plan_destroy(rrq_plan* p) {
+  if (!p) return RRQ_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  plan_free(p);
+  return RRQ_OK;
+}
+
+static rrq_status check_targets(const rrq_plan* p, const rrq_targets* tg) {
+  if (!p || !tg || tg->ntarget < 0 || tg->nnz < 0) return RRQ_ERR_ARG;
+  if (tg->ntarget > 0 && (!tg->xyz || !tg->nrm || !tg->self_patch || !tg->self_node ||
+                          !tg->near_ptr))
+    return RRQ_ERR_ARG;
+  if (tg->nnz > 0 && !tg->near_patch) return RRQ_ERR_ARG;
+  return RRQ_OK;
+}
+
+static TargetsDev tdev(const rrq_targets* tg) {
+  TargetsDev t;
+  t.T = tg->ntarget;
+  t.nnz = tg->nnz;
+  t.xyz = tg->xyz;
+  t.nrm = tg->nrm;
+  t.self_patch = tg->self_patch;
+  t.self_node = tg->self_node;
+  t.near_ptr = tg->near_ptr;
+  t.near_patch = tg->near_patch;
+  return t;
+}
+
+static size_t ws_bytes(int64_t nnz) {
+  // owner[nnz] (int64) + counters[8]
+  return (size_t)(nnz > 0 ? nnz : 1) * 8 + 8 * 8 + 256;
+}
+
+rrq_status rrq_workspace_size(const rrq_plan* p, const rrq_targets* tg, size_t* bytes) {
+  if (!bytes) return RRQ_ERR_ARG;
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  *bytes = ws_bytes(tg->nnz);
+  return RRQ_OK;
+}
+
+rrq_status rrq_pair_offsets(const rrq_plan* p, const rrq_targets* tg, int64_t* pair_off,
+                            int64_t* nweights, void* stream) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!pair_off) return RRQ_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_pair_offsets(p->dev(), tdev(tg), pair_off, nullptr, st) != hipSuccess)
+    return RRQ_ERR_DEVICE;
+  if (nweights) {
+    if (hipMemcpyAsync(nweights, pair_off + tg->nnz, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return RRQ_ERR_DEVICE;
+  }
+  return RRQ_OK;
+}
+
+rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                        uint32_t flags, double* out_S, double* out_D, double* out_Sp,
+                        double* out_Dp, const int64_t* pair_off, void* workspace,
+                        size_t workspace_bytes, void* stream, rrq_stats* stats) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
+  if (workspace_bytes < ws_bytes(tg->nnz)) return RRQ_ERR_BUFFER;
+  double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
+  for (int K = 0; K < 4; ++K)
+    if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
+  if (flags & RRQ_F_LEARNED) return RRQ_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  int64_t* owner = (int64_t*)workspace;
+  unsigned long long* counters =
+      (unsigned long long*)((char*)workspace + (size_t)(tg->nnz > 0 ? tg->nnz : 1) * 8);
+  TargetsDev td = tdev(tg);
+  if (launch_owner(td, owner, counters, st) != hipSuccess) return RRQ_ERR_DEVICE;
+  AssembleOut ao;
+  for (int K = 0; K < 4; ++K) ao.w[K] = (kmask & (1u << K)) ? outs[K] : nullptr;
+  ao.kmask = kmask;
+  ao.flags = flags;
+  ao.pair_off = pair_off;
+  ao.owner = owner;
+  ao.counters = counters;
+  PlanDev pd = p->dev();
+  for (int qi = 0; qi < kNumOrders; ++qi) {
+    const int q = kOrders[qi];
+    if (p->patches_h[q].empty()) continue;
+    SolveOpts so{p->rho_far[q], p->opt.newton_tol, p->opt.newton_maxit};
+    if (launch_pair_plain(q, pd, p->od[q], td, ao, so, st) != hipSuccess) return RRQ_ERR_DEVICE;
+  }
+  if (stats) {
+    unsigned long long h[8];
+    if (hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+    stats->pairs = tg->nnz;
+    stats->near_edges = (int64_t)h[0];
+    stats->newton_iters = (int64_t)h[1];
+    stats->newton_fail = (int64_t)h[2];
+    stats->learned_accept = (int64_t)h[3];
+    stats->newton_max = (int64_t)h[4];
+  }
+  return RRQ_OK;
+}
+
+rrq_status rrq_apply(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                     const double* w_S, const double* w_D, const double* w_Sp,
+                     const double* w_Dp, const int64_t* pair_off, const double* density,
+                     double* pot_S, double* pot_D, double* pot_Sp, double* pot_Dp,
+                     void* stream) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!pair_off || !density || (kmask & ~15u)) return RRQ_ERR_ARG;
+  const double* w[4] = {w_S, w_D, w_Sp, w_Dp};
+  double* pot[4] = {pot_S, pot_D, pot_Sp, pot_Dp};
+  for (int K = 0; K < 4; ++K)
+    if ((kmask & (1u << K)) && (!w[K] || !pot[K])) return RRQ_ERR_ARG;
+  if (launch_apply(p->dev(), tdev(tg), w, kmask, pair_off, nullptr, density, pot,
+                   (hipStream_t)stream) != hipSuccess)
+    return RRQ_ERR_DEVICE;
+  return RRQ_OK;
+}
+
+}  // extern "C"

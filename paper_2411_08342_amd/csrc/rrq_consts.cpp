@@ -1,0 +1,138 @@
+// Constant tables (host, long double): Gauss-Legendre rules, the inverse Vandermonde matrix U
+// of the edge interpolation (Sec. 3.5) and the index/coefficient lists of the translation
+// sums of eq. cdlp1dintegral and Theorem thm:cslp1form.
+#include "rrq_consts.h"
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace rrq {
+
+void gauss_legendre_ld(int n, std::vector<double>& t, std::vector<double>& w) {
+  t.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    long double x = cosl(pi * (i + 0.75L) / (n + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = x; p0 = 1; }
+      dp = n * (x * p1 - p0) / (x * x - 1);
+      long double dx = p1 / dp;
+      x -= dx;
+      if (fabsl(dx) < 1e-19L) break;
+    }
+    long double p0 = 1, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1);
+    t[n - 1 - i] = (double)x;                       // increasing order
+    w[n - 1 - i] = (double)(2.0L / ((1 - x * x) * dp * dp));
+  }
+}
+
+static long double binom_ld(int n, int k) {
+  if (k < 0 || k > n || n < 0) return 0;
+  long double r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+static long double fact_ld(int n) {
+  long double r = 1;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+OrderTables build_order_tables(int q, int pt) {
+  OrderTables T;
+  T.q = q;
+  T.pt = pt;
+  T.np = np_of(q);
+  T.njk = njk_of(q);
+  gauss_legendre_ld(pt, T.gl_t, T.gl_w);
+  std::vector<double> tq;
+  gauss_legendre_ld(q, tq, T.glq_w);
+
+  // U = V^{-1}, V[i][k] = t_i^k, by Gauss-Jordan elimination in long double
+  std::vector<long double> A(pt * 2 * pt, 0.0L);
+  for (int i = 0; i < pt; ++i) {
+    long double x = T.gl_t[i], p = 1;
+    for (int k = 0; k < pt; ++k) {
+      A[i * 2 * pt + k] = p;
+      p *= x;
+    }
+    A[i * 2 * pt + pt + i] = 1;
+  }
+  for (int c = 0; c < pt; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < pt; ++r)
+      if (fabsl(A[r * 2 * pt + c]) > fabsl(A[piv * 2 * pt + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < 2 * pt; ++k) std::swap(A[c * 2 * pt + k], A[piv * 2 * pt + k]);
+    long double d = A[c * 2 * pt + c];
+    for (int k = 0; k < 2 * pt; ++k) A[c * 2 * pt + k] /= d;
+    for (int r = 0; r < pt; ++r) {
+      if (r == c) continue;
+      long double f = A[r * 2 * pt + c];
+      if (f == 0) continue;
+      for (int k = 0; k < 2 * pt; ++k) A[r * 2 * pt + k] -= f * A[c * 2 * pt + k];
+    }
+  }
+  // inverse V^{-1}[k][i]: coefficient k of the Lagrange polynomial l_i
+  T.U.assign(pt * pt, 0.0);
+  T.lag_m1.assign(pt, 0.0);
+  for (int k = 0; k < pt; ++k)
+    for (int i = 0; i < pt; ++i) T.U[k * pt + i] = (double)A[k * 2 * pt + pt + i];
+  for (int i = 0; i < pt; ++i) {
+    long double s = 0, p = 1;
+    for (int k = 0; k < pt; ++k) {
+      s += A[k * 2 * pt + pt + i] * p;
+      p *= -1;
+    }
+    T.lag_m1[i] = (double)s;
+  }
+
+  // translation terms, grouped by basis function (l, m), 1 <= m <= l <= q
+  T.dlp_ptr.assign(1, 0);
+  T.slp_ptr.assign(1, 0);
+  for (int l = 1; l <= q; ++l)
+    for (int m = 1; m <= l; ++m) {
+      for (int pass = 0; pass < 2; ++pass) {
+        const int j0 = pass == 0 ? 2 : 1;
+        for (int j = j0; j <= l; ++j) {
+          long double wj = pass == 0
+                               ? fact_ld(j - 2) * fact_ld(l - j) / fact_ld(l - 1)   // C_{j,l}
+                               : fact_ld(j - 1) * fact_ld(l - j) / fact_ld(l);      // D_{j,l}
+          for (int k = -j; k <= j; ++k) {
+            if (std::abs(m - k) > l - j) continue;
+            long double tc = sqrtl(binom_ld(l + m, j + k) * binom_ld(l - m, j - k));
+            Term t;
+            int ak = std::abs(k);
+            t.n = jk_index(j, ak);
+            t.a = (int16_t)(l - j);
+            t.b = (int16_t)(m - k);
+            t.neg = k < 0;
+            long double sg = (k < 0 && (ak & 1)) ? -1.0L : 1.0L;
+            t.coef = (double)(wj * tc * sg);
+            (pass == 0 ? T.dlp : T.slp).push_back(t);
+          }
+        }
+        (pass == 0 ? T.dlp_ptr : T.slp_ptr).push_back(
+            (int32_t)(pass == 0 ? T.dlp.size() : T.slp.size()));
+      }
+    }
+  return T;
+}
+
+}  // namespace rrq

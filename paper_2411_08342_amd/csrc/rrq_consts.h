@@ -1,0 +1,39 @@
+// Host-side constant tables of the quadrature rules and of the translation sums.
+// Computed once per order in extended precision and uploaded with the plan.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+namespace rrq {
+
+constexpr int kMaxQ = 10;
+constexpr int kNumOrders = 5;
+constexpr int kOrders[kNumOrders] = {4, 5, 6, 8, 10};
+
+__host__ __device__ constexpr int np_of(int p) { return p * (p + 1) / 2; }
+__host__ __device__ constexpr int njk_of(int p) { return p * (p + 3) / 2; }   // (j,k), 1<=j<=p, 0<=k<=j
+__host__ __device__ constexpr int jk_index(int j, int k) { return j * (j + 1) / 2 - 1 + k; }
+
+// one term of a translation sum: out[lm] += coef * X^{(j,|k|)} (conj if neg) * S^{(a,b)}(x)
+struct Term {
+  int32_t n;      // index of (j, |k|) in the jk table
+  int16_t a, b;   // S^{(a,b)}: a = l - j, b = m - k (b may be negative)
+  int32_t neg;    // k < 0: use conj(X^{(j,|k|)})
+  double coef;    // (weight C_{j,l} or D_{j,l}) * T_{jk,lm} * (-1)^{|k|} if k < 0
+};
+
+struct OrderTables {
+  int q, pt, np, njk;
+  std::vector<double> gl_t, gl_w;     // ptilde-point GL rule on [-1, 1]
+  std::vector<double> glq_w;          // q-point GL weights (least-squares weights)
+  std::vector<double> U;              // [pt][pt]: U[k*pt + i] = coeff of t^k in l_i(t)
+  std::vector<double> lag_m1;         // l_i(-1)
+  std::vector<int32_t> dlp_ptr, slp_ptr;   // [np+1]
+  std::vector<Term> dlp, slp;
+};
+
+void gauss_legendre_ld(int n, std::vector<double>& t, std::vector<double>& w);
+OrderTables build_order_tables(int q, int ptilde);
+
+}  // namespace rrq

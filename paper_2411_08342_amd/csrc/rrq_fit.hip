@@ -1,0 +1,398 @@
+// Source-only kernels (Steps 1-3 of the algorithm in Sec. 4): patch frame and local
+// coordinates, edge interpolants and edge tables, and the least-squares harmonic fits that
+// give the nodal-to-coefficient maps of every patch.
+#include "rrq_device.h"
+#include "rrq_internal.h"
+
+namespace rrq {
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------------------------------
+// Frame (Sec. 5.1 scaling/rotation): origin = mean of the corners, z along
+// (c2 - c0) x (c3 - c1) (sign of the mean node normal), x along the first side, scale =
+// longest side.  Local coordinates R^T (r - o) / s of nodes and edge samples; monomial
+// coefficients of each edge interpolant (c = U samples, Sec. 3.5) and its tangent.
+// ---------------------------------------------------------------------------------------
+template <int Q>
+__global__ __launch_bounds__(NT) void k_geometry(PlanDev pd, rrq_surface s, OrderDev od,
+                                                 const int32_t* patches, int count) {
+  constexpr int PT = 2 * Q;
+  __shared__ double sm_fr[kFrame];
+  __shared__ double sm_c[4][3];
+  __shared__ double sm_nrm[NT / 64 * 3];
+  __shared__ double sm_loc[4 * PT * 3];
+  __shared__ double sm_coef[4 * PT * 3];
+  for (int it = blockIdx.x; it < count; it += gridDim.x) {
+    const int P = patches[it];
+    const int64_t n0 = s.node_off[P];
+    const int64_t e0 = s.edge_off[P];
+    const int tid = threadIdx.x;
+    // corners c_e = r_e(-1) = sum_i l_i(-1) s_{e,i}
+    if (tid < 12) {
+      const int e = tid / 3, c = tid % 3;
+      double acc = 0.0;
+      for (int i = 0; i < PT; ++i) acc += od.lag_m1[i] * s.edge_xyz[c * s.nedge + e0 + e * PT + i];
+      sm_c[e][c] = acc;
+    }
+    // mean node normal (only its direction's sign is used)
+    double nx = 0, ny = 0, nz = 0;
+    for (int i = tid; i < Q * Q; i += NT) {
+      nx += s.node_nrm[0 * s.nnode + n0 + i];
+      ny += s.node_nrm[1 * s.nnode + n0 + i];
+      nz += s.node_nrm[2 * s.nnode + n0 + i];
+    }
+    nx = wave_sum(nx);
+    ny = wave_sum(ny);
+    nz = wave_sum(nz);
+    if ((tid & 63) == 0) {
+      sm_nrm[(tid >> 6) * 3 + 0] = nx;
+      sm_nrm[(tid >> 6) * 3 + 1] = ny;
+      sm_nrm[(tid >> 6) * 3 + 2] = nz;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double mn[3] = {0, 0, 0};
+      for (int w = 0; w < NT / 64; ++w)
+        for (int c = 0; c < 3; ++c) mn[c] += sm_nrm[w * 3 + c];
+      double o[3], a[3], b[3], ez[3], ex[3], ey[3];
+      for (int c = 0; c < 3; ++c) {
+        o[c] = 0.25 * (sm_c[0][c] + sm_c[1][c] + sm_c[2][c] + sm_c[3][c]);
+        a[c] = sm_c[2][c] - sm_c[0][c];
+        b[c] = sm_c[3][c] - sm_c[1][c];
+      }
+      ez[0] = a[1] * b[2] - a[2] * b[1];
+      ez[1] = a[2] * b[0] - a[0] * b[2];
+      ez[2] = a[0] * b[1] - a[1] * b[0];
+      double nn = sqrt(ez[0] * ez[0] + ez[1] * ez[1] + ez[2] * ez[2]);
+      for (int c = 0; c < 3; ++c) ez[c] /= nn;
+      if (ez[0] * mn[0] + ez[1] * mn[1] + ez[2] * mn[2] < 0)
+        for (int c = 0; c < 3; ++c) ez[c] = -ez[c];
+      double s1[3];
+      for (int c = 0; c < 3; ++c) s1[c] = sm_c[1][c] - sm_c[0][c];
+      double pz = s1[0] * ez[0] + s1[1] * ez[1] + s1[2] * ez[2];
+      for (int c = 0; c < 3; ++c) ex[c] = s1[c] - pz * ez[c];
+      nn = sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
+      for (int c = 0; c < 3; ++c) ex[c] /= nn;
+      ey[0] = ez[1] * ex[2] - ez[2] * ex[1];
+      ey[1] = ez[2] * ex[0] - ez[0] * ex[2];
+      ey[2] = ez[0] * ex[1] - ez[1] * ex[0];
+      double sc = 0.0;
+      for (int e = 0; e < 4; ++e) {
+        double d2 = 0;
+        for (int c = 0; c < 3; ++c) {
+          double d = sm_c[(e + 1) & 3][c] - sm_c[e][c];
+          d2 += d * d;
+        }
+        sc = fmax(sc, sqrt(d2));
+      }
+      for (int c = 0; c < 3; ++c) {
+        sm_fr[c] = o[c];
+        sm_fr[3 + c] = ex[c];
+        sm_fr[6 + c] = ey[c];
+        sm_fr[9 + c] = ez[c];
+      }
+      sm_fr[12] = sc;
+      for (int c = 13; c < kFrame; ++c) sm_fr[c] = 0.0;
+    }
+    __syncthreads();
+    if (tid < kFrame) pd.frame[(int64_t)P * kFrame + tid] = sm_fr[tid];
+    const double inv_s = 1.0 / sm_fr[12];
+    for (int i = tid; i < Q * Q; i += NT) {
+      double d[3], v[3];
+      for (int c = 0; c < 3; ++c) {
+        d[c] = s.node_xyz[c * s.nnode + n0 + i] - sm_fr[c];
+        v[c] = s.node_nrm[c * s.nnode + n0 + i];
+      }
+      for (int a = 0; a < 3; ++a) {
+        const double* ax = sm_fr + 3 + 3 * a;
+        pd.node_loc[a * pd.N + n0 + i] = (d[0] * ax[0] + d[1] * ax[1] + d[2] * ax[2]) * inv_s;
+        pd.node_loc[(3 + a) * pd.N + n0 + i] = v[0] * ax[0] + v[1] * ax[1] + v[2] * ax[2];
+      }
+    }
+    for (int i = tid; i < 4 * PT; i += NT) {
+      double d[3];
+      for (int c = 0; c < 3; ++c) d[c] = s.edge_xyz[c * s.nedge + e0 + i] - sm_fr[c];
+      for (int a = 0; a < 3; ++a) {
+        const double* ax = sm_fr + 3 + 3 * a;
+        double v = (d[0] * ax[0] + d[1] * ax[1] + d[2] * ax[2]) * inv_s;
+        sm_loc[i * 3 + a] = v;
+        pd.edge_loc[a * pd.E + e0 + i] = v;
+      }
+    }
+    __syncthreads();
+    // monomial coefficients a_k = sum_i U[k][i] s_i per edge and coordinate
+    for (int idx = tid; idx < 4 * PT * 3; idx += NT) {
+      const int c = idx % 3, k = (idx / 3) % PT, e = idx / (3 * PT);
+      double acc = 0.0;
+      for (int i = 0; i < PT; ++i) acc += od.U[k * PT + i] * sm_loc[(e * PT + i) * 3 + c];
+      pd.edge_coef[c * pd.E + e0 + e * PT + k] = acc;
+      sm_coef[(e * PT + k) * 3 + c] = acc;
+    }
+    __syncthreads();
+    // tangent r'(t_i) = sum_k k a_k t_i^{k-1}
+    for (int idx = tid; idx < 4 * PT * 3; idx += NT) {
+      const int c = idx % 3, i = (idx / 3) % PT, e = idx / (3 * PT);
+      const double t = od.gl_t[i];
+      double der = 0.0, val = 0.0;
+      for (int k = PT - 1; k >= 0; --k) {
+        der = der * t + val;
+        val = val * t + sm_coef[(e * PT + k) * 3 + c];
+      }
+      pd.edge_tan[c * pd.E + e0 + e * PT + i] = der;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Edge tables (Step 3): at every edge node r_i with tangent r'_i and every (j, k),
+// 1 <= j <= p, 0 <= k <= j:  c = grad S^{jk}(r_i) x r'_i,  h = Hess S^{jk}(r_i) r'_i.
+// ---------------------------------------------------------------------------------------
+template <int Q>
+__global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
+                                                    const int32_t* patches, int count) {
+  constexpr int PT = 2 * Q;
+  constexpr int NJK = njk_of(Q);
+  const int64_t total = (int64_t)count * 4 * PT;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int P = patches[g / (4 * PT)];
+    const int ei = (int)(g % (4 * PT));
+    const int e = ei / PT, i = ei % PT;
+    const int64_t col = pd.edge_off[P] + ei;
+    const double x = pd.edge_loc[0 * pd.E + col];
+    const double y = pd.edge_loc[1 * pd.E + col];
+    const double z = pd.edge_loc[2 * pd.E + col];
+    const double tp[3] = {pd.edge_tan[0 * pd.E + col], pd.edge_tan[1 * pd.E + col],
+                          pd.edge_tan[2 * pd.E + col]};
+    cplx R[tri(Q, Q) + 1];
+    solid_table<Q>(y, z, x, R);
+    double* base = pd.tabs + pd.tab_off[P];
+    for (int j = 1; j <= Q; ++j)
+      for (int k = 0; k <= j; ++k) {
+        cplx g3[3], h3[3];
+        for (int a = 0; a < 3; ++a) {
+          g3[a] = dS(R, j, k, a);
+          cplx acc = mk(0, 0);
+          for (int b = 0; b < 3; ++b) acc = acc + tp[b] * d2S(R, j, k, a, b);
+          h3[a] = acc;
+        }
+        cplx c3[3];
+        c3[0] = tp[2] * g3[1] - tp[1] * g3[2];
+        c3[1] = tp[0] * g3[2] - tp[2] * g3[0];
+        c3[2] = tp[1] * g3[0] - tp[0] * g3[1];
+        double* o = base + (((int64_t)e * NJK + jk_index(j, k)) * PT + i) * 12;
+        for (int a = 0; a < 3; ++a) {
+          o[2 * a] = c3[a].re;
+          o[2 * a + 1] = c3[a].im;
+          o[6 + 2 * a] = h3[a].re;
+          o[6 + 2 * a + 1] = h3[a].im;
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Weighted least squares by Householder QR on a row-major m x ncols matrix in global
+// workspace (first n columns: system, the rest: right-hand sides).  On exit the RHS columns
+// hold the solution in rows 0..n-1.
+// ---------------------------------------------------------------------------------------
+__device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* sv, double* red) {
+  for (int k = 0; k < n; ++k) {
+    double part = 0.0;
+    for (int r = k + threadIdx.x; r < m; r += NT) {
+      const double a = A[(int64_t)r * ld + k];
+      part += a * a;
+    }
+    const double nrm2 = block_sum<NT>(part, red);
+    const double akk = A[(int64_t)k * ld + k];
+    const double nrm = sqrt(nrm2);
+    const double alpha = akk >= 0.0 ? -nrm : nrm;
+    const double vtv = 2.0 * nrm * (nrm + fabs(akk));
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    for (int r = k + threadIdx.x; r < m; r += NT)
+      sv[r - k] = (r == k) ? akk - alpha : A[(int64_t)r * ld + k];
+    __syncthreads();
+    for (int j = k + 1 + threadIdx.x; j < ncols; j += NT) {
+      double sdot = 0.0;
+      for (int r = k; r < m; ++r) sdot += sv[r - k] * A[(int64_t)r * ld + j];
+      sdot *= beta;
+      for (int r = k; r < m; ++r) A[(int64_t)r * ld + j] -= sdot * sv[r - k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A[(int64_t)k * ld + k] = alpha;
+    __syncthreads();
+  }
+  for (int j = n + threadIdx.x; j < ncols; j += NT) {
+    for (int r = n - 1; r >= 0; --r) {
+      double acc = A[(int64_t)r * ld + j];
+      for (int c = r + 1; c < n; ++c) acc -= A[(int64_t)r * ld + c] * A[(int64_t)c * ld + j];
+      A[(int64_t)r * ld + j] = acc / A[(int64_t)r * ld + r];
+    }
+  }
+  __syncthreads();
+}
+
+int64_t fit_ws_doubles(int q) {
+  const int np = np_of(q), q2 = q * q;
+  const int64_t a = (int64_t)(4 * q2) * (4 * np + q2);
+  const int64_t b = (int64_t)q2 * (np + q2);
+  return a + b + (int64_t)q2 * np + (int64_t)q2 * q2 + 64;
+}
+
+// ---------------------------------------------------------------------------------------
+// Fits (Steps 1-2 with Step 2 skipped, remark after the algorithm):
+//   DLP:  (0, grad H) c = (mu, 0) in the least-squares sense with weights w_a w_b
+//         (block system of eq. dlpdensitylinearsystem2)  ->  M_D = A^+[:, block 0]
+//   S':   right-hand side (0, sigma nu) (eq. sprimedensitylinearsystem): since the system
+//         is quaternion-linear, column j of the map is (column j of M_D) * (0, nu_j)
+//   SLP:  scalar system grad H . nu d = sigma (eq. slpdensitylinearsystem) -> B^+, and the
+//         intermediate density rho = H d refitted by M_D (Theorem thm:slpreduction):
+//         M_S = [B^+; M_D Hmat B^+]
+// ---------------------------------------------------------------------------------------
+template <int Q>
+__global__ __launch_bounds__(NT) void k_fit(PlanDev pd, OrderDev od, const int32_t* patches,
+                                            int count, double* ws, int64_t ws_per_block) {
+  constexpr int NP = np_of(Q);
+  constexpr int Q2 = Q * Q;
+  constexpr int M = 4 * Q2;
+  constexpr int LDA = 4 * NP + Q2;
+  constexpr int LDB = NP + Q2;
+  __shared__ double sv[M];
+  __shared__ double red[NT / 64];
+  double* A = ws + (int64_t)blockIdx.x * ws_per_block;
+  double* B = A + (int64_t)M * LDA;
+  double* Hm = B + (int64_t)Q2 * LDB;
+  double* T1 = Hm + (int64_t)Q2 * NP;
+  for (int it = blockIdx.x; it < count; it += gridDim.x) {
+    const int P = patches[it];
+    const int64_t n0 = pd.node_off[P];
+    const int tid = threadIdx.x;
+    // clear workspace
+    for (int64_t i = tid; i < (int64_t)M * LDA; i += NT) A[i] = 0.0;
+    for (int64_t i = tid; i < (int64_t)Q2 * LDB; i += NT) B[i] = 0.0;
+    __syncthreads();
+    // basis at the nodes: one thread per node
+    for (int i = tid; i < Q2; i += NT) {
+      const double x = pd.node_loc[0 * pd.N + n0 + i];
+      const double y = pd.node_loc[1 * pd.N + n0 + i];
+      const double z = pd.node_loc[2 * pd.N + n0 + i];
+      const double nu[3] = {pd.node_loc[3 * pd.N + n0 + i], pd.node_loc[4 * pd.N + n0 + i],
+                            pd.node_loc[5 * pd.N + n0 + i]};
+      const double om = sqrt(od.glq_w[i / Q] * od.glq_w[i % Q]);
+      cplx R[tri(Q, Q) + 1];
+      solid_table<Q>(y, z, x, R);
+      int lm = 0;
+      for (int l = 1; l <= Q; ++l)
+        for (int m = 1; m <= l; ++m, ++lm) {
+          double F[3];
+          for (int a = 0; a < 3; ++a) F[a] = kSqrt2 * dS(R, l, m, a).im;
+          Hm[i * NP + lm] = kSqrt2 * R[tri(l, m)].im;
+          const double F1 = om * F[0], F2 = om * F[1], F3 = om * F[2];
+          double* r0 = A + (int64_t)(0 * Q2 + i) * LDA;
+          double* r1 = A + (int64_t)(1 * Q2 + i) * LDA;
+          double* r2 = A + (int64_t)(2 * Q2 + i) * LDA;
+          double* r3 = A + (int64_t)(3 * Q2 + i) * LDA;
+          // [0 -F1 -F2 -F3; F1 0 -F3 F2; F2 F3 0 -F1; F3 -F2 F1 0]
+          r0[1 * NP + lm] = -F1; r0[2 * NP + lm] = -F2; r0[3 * NP + lm] = -F3;
+          r1[0 * NP + lm] = F1;  r1[2 * NP + lm] = -F3; r1[3 * NP + lm] = F2;
+          r2[0 * NP + lm] = F2;  r2[1 * NP + lm] = F3;  r2[3 * NP + lm] = -F1;
+          r3[0 * NP + lm] = F3;  r3[1 * NP + lm] = -F2; r3[2 * NP + lm] = F1;
+          B[(int64_t)i * LDB + lm] = om * (F[0] * nu[0] + F[1] * nu[1] + F[2] * nu[2]);
+        }
+      A[(int64_t)i * LDA + 4 * NP + i] = om;
+      B[(int64_t)i * LDB + NP + i] = om;
+    }
+    __syncthreads();
+    hh_lsq(A, M, 4 * NP, LDA, LDA, sv, red);
+    hh_lsq(B, Q2, NP, LDB, LDB, sv, red);
+    double* maps = pd.maps + pd.map_off[P];
+    double* MD = maps;
+    double* MSp = maps + 4 * NP * Q2;
+    double* MS = maps + 8 * NP * Q2;
+    for (int idx = tid; idx < 4 * NP * Q2; idx += NT) {
+      const int r = idx / Q2, j = idx % Q2;
+      MD[idx] = A[(int64_t)r * LDA + 4 * NP + j];
+    }
+    for (int idx = tid; idx < NP * Q2; idx += NT) {
+      const int r = idx / Q2, j = idx % Q2;
+      MS[idx] = B[(int64_t)r * LDB + NP + j];
+    }
+    // T1 = Hmat (Q2 x NP) * B^+ (NP x Q2)
+    for (int idx = tid; idx < Q2 * Q2; idx += NT) {
+      const int i = idx / Q2, j = idx % Q2;
+      double acc = 0.0;
+      for (int n = 0; n < NP; ++n) acc += Hm[i * NP + n] * B[(int64_t)n * LDB + NP + j];
+      T1[idx] = acc;
+    }
+    __syncthreads();
+    // M_S lower block = M_D * T1 ; M_Sp column j = (M_D column j) (0, nu_j)
+    for (int idx = tid; idx < 4 * NP * Q2; idx += NT) {
+      const int r = idx / Q2, j = idx % Q2;
+      double acc = 0.0;
+      for (int i = 0; i < Q2; ++i) acc += A[(int64_t)r * LDA + 4 * NP + i] * T1[i * Q2 + j];
+      MS[NP * Q2 + idx] = acc;
+    }
+    for (int idx = tid; idx < NP * Q2; idx += NT) {
+      const int lm = idx / Q2, j = idx % Q2;
+      const double c0 = A[(int64_t)(0 * NP + lm) * LDA + 4 * NP + j];
+      const double c1 = A[(int64_t)(1 * NP + lm) * LDA + 4 * NP + j];
+      const double c2 = A[(int64_t)(2 * NP + lm) * LDA + 4 * NP + j];
+      const double c3 = A[(int64_t)(3 * NP + lm) * LDA + 4 * NP + j];
+      const double v1 = pd.node_loc[3 * pd.N + n0 + j];
+      const double v2 = pd.node_loc[4 * pd.N + n0 + j];
+      const double v3 = pd.node_loc[5 * pd.N + n0 + j];
+      MSp[(0 * NP + lm) * Q2 + j] = -(c1 * v1 + c2 * v2 + c3 * v3);
+      MSp[(1 * NP + lm) * Q2 + j] = c0 * v1 + (c2 * v3 - c3 * v2);
+      MSp[(2 * NP + lm) * Q2 + j] = c0 * v2 + (c3 * v1 - c1 * v3);
+      MSp[(3 * NP + lm) * Q2 + j] = c0 * v3 + (c1 * v2 - c2 * v1);
+    }
+    __syncthreads();
+  }
+}
+
+#define RRQ_FOR_ORDERS(X) X(4) X(5) X(6) X(8) X(10)
+
+hipError_t launch_geometry(const PlanDev& pd, const rrq_surface& s, const OrderDev& od,
+                           const int32_t* patches, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int grid = count < 65535 ? count : 65535;
+  switch (od.q) {
+#define X(q) case q: hipLaunchKernelGGL(k_geometry<q>, dim3(grid), dim3(NT), 0, st, pd, s, od, patches, count); break;
+    RRQ_FOR_ORDERS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_tables(const PlanDev& pd, const OrderDev& od, const int32_t* patches,
+                              int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t total = (int64_t)count * 4 * od.pt;
+  int64_t g = (total + 127) / 128;
+  const int grid = (int)(g < 65535 ? g : 65535);
+  switch (od.q) {
+#define X(q) case q: hipLaunchKernelGGL(k_edge_tables<q>, dim3(grid), dim3(128), 0, st, pd, od, patches, count); break;
+    RRQ_FOR_ORDERS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fit(const PlanDev& pd, const OrderDev& od, const int32_t* patches, int count,
+                      double* ws, int64_t ws_per_block, int blocks, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int grid = count < blocks ? count : blocks;
+  switch (od.q) {
+#define X(q) case q: hipLaunchKernelGGL(k_fit<q>, dim3(grid), dim3(NT), 0, st, pd, od, patches, count, ws, ws_per_block); break;
+    RRQ_FOR_ORDERS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rrq

@@ -1,0 +1,94 @@
+// Internal declarations shared by the host runtime and the kernels of the RRQ library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/rrq.h"
+#include "rrq_consts.h"
+
+namespace rrq {
+
+// constant tables of one order, on the device
+struct OrderDev {
+  int q, pt, np, njk;
+  const double* gl_t;
+  const double* gl_w;
+  const double* glq_w;
+  const double* U;
+  const double* lag_m1;
+  const int32_t* dlp_ptr;
+  const Term* dlp;
+  const int32_t* slp_ptr;
+  const Term* slp;
+};
+
+// per-patch data layout constants
+__host__ __device__ constexpr int64_t map_doubles(int q) { return 13LL * np_of(q) * q * q; }
+__host__ __device__ constexpr int64_t tab_doubles(int q) { return 4LL * njk_of(q) * (2 * q) * 12; }
+constexpr int kFrame = 16;   // o[3], ex[3], ey[3], ez[3], s, pad
+
+struct PlanDev {
+  int32_t npatch;
+  int64_t N, E;
+  const int32_t* order;
+  const int64_t* node_off;
+  const int64_t* edge_off;
+  const double* node_xyz;   // [3][N] plan copy (global coordinates)
+  const double* node_nrm;
+  const double* node_wt;
+  double* frame;            // [P][kFrame]
+  double* node_loc;         // [6][N] local coordinates and normals
+  double* edge_loc;         // [3][E]
+  double* edge_tan;         // [3][E]
+  double* edge_coef;        // [3][E] monomial coefficients per edge
+  double* maps;             // per patch: M_D [4np][q^2], M_Sp [4np][q^2], M_S [5np][q^2]
+  const int64_t* map_off;
+  double* tabs;             // per patch: [4][njk][pt][12]: c (3 cplx), h (3 cplx)
+  const int64_t* tab_off;
+};
+
+struct TargetsDev {
+  int64_t T, nnz;
+  const double* xyz;
+  const double* nrm;
+  const int32_t* self_patch;
+  const int32_t* self_node;
+  const int64_t* near_ptr;
+  const int32_t* near_patch;
+};
+
+struct AssembleOut {
+  double* w[4];      // S, D, Sp, Dp
+  uint32_t kmask, flags;
+  const int64_t* pair_off;
+  const int64_t* owner;     // [nnz] target of each pair
+  unsigned long long* counters;   // [8] stats
+};
+
+struct SolveOpts {
+  double rho_far, newton_tol;
+  int newton_maxit;
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_geometry(const PlanDev& pd, const rrq_surface& s, const OrderDev& od,
+                           const int32_t* patches, int count, hipStream_t st);
+hipError_t launch_edge_tables(const PlanDev& pd, const OrderDev& od, const int32_t* patches,
+                              int count, hipStream_t st);
+hipError_t launch_fit(const PlanDev& pd, const OrderDev& od, const int32_t* patches, int count,
+                      double* ws, int64_t ws_per_block, int blocks, hipStream_t st);
+hipError_t launch_owner(const TargetsDev& tg, int64_t* owner, unsigned long long* counters,
+                        hipStream_t st);
+hipError_t launch_pair_offsets(const PlanDev& pd, const TargetsDev& tg, int64_t* pair_off,
+                               int64_t* scratch, hipStream_t st);
+hipError_t launch_pair_plain(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
+                             const AssembleOut& out, const SolveOpts& so, hipStream_t st);
+hipError_t launch_apply(const PlanDev& pd, const TargetsDev& tg, const double* const* w,
+                        uint32_t kmask, const int64_t* pair_off, const int64_t* owner,
+                        const double* density, double* const* pot, hipStream_t st);
+
+int64_t fit_ws_doubles(int q);
+
+}  // namespace rrq

@@ -1,0 +1,216 @@
+"""Thin Python binding of the C ABI in include/rrq.h (ctypes; argument marshalling only).
+
+Device memory and streams come from PyTorch: every array argument is a CUDA (HIP) tensor
+whose data pointer is handed to the library, and calls run on torch's current stream.  Every
+step of the computation runs in the HIP library; there is no host fallback: a missing library
+raises at import of the first call.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librrq.so")
+
+RRQ_K_S, RRQ_K_D, RRQ_K_SP, RRQ_K_DP, RRQ_K_ALL = 1, 2, 4, 8, 15
+RRQ_F_CORRECTION, RRQ_F_ONSURF_PV, RRQ_F_PLAIN, RRQ_F_LEARNED = 1, 2, 8, 16
+KERNELS = ("S", "D", "Sp", "Dp")
+
+EXPORTED = ("rrq_plan_create", "rrq_plan_refit", "rrq_plan_destroy", "rrq_workspace_size",
+            "rrq_pair_offsets", "rrq_assemble", "rrq_apply", "rrq_status_string")
+
+
+class RRQError(RuntimeError):
+    pass
+
+
+class Surface(ctypes.Structure):
+    _fields_ = [("npatch", ctypes.c_int32), ("order_host", ctypes.c_void_p),
+                ("order", ctypes.c_void_p), ("node_off", ctypes.c_void_p),
+                ("node_xyz", ctypes.c_void_p), ("node_nrm", ctypes.c_void_p),
+                ("node_wt", ctypes.c_void_p), ("edge_off", ctypes.c_void_p),
+                ("edge_xyz", ctypes.c_void_p), ("nnode", ctypes.c_int64),
+                ("nedge", ctypes.c_int64)]
+
+
+class Targets(ctypes.Structure):
+    _fields_ = [("ntarget", ctypes.c_int64), ("nnz", ctypes.c_int64), ("xyz", ctypes.c_void_p),
+                ("nrm", ctypes.c_void_p), ("self_patch", ctypes.c_void_p),
+                ("self_node", ctypes.c_void_p), ("near_ptr", ctypes.c_void_p),
+                ("near_patch", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("rho_far", ctypes.c_double), ("newton_tol", ctypes.c_double),
+                ("newton_maxit", ctypes.c_int32), ("tile_targets", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("near_edges", ctypes.c_int64),
+                ("newton_iters", ctypes.c_int64), ("newton_fail", ctypes.c_int64),
+                ("learned_accept", ctypes.c_int64), ("newton_max", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load librrq.so (built in-tree by paper_2411_08342_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RRQError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64
+        L.rrq_plan_create.argtypes = [ctypes.POINTER(Surface), ctypes.POINTER(Options), vp,
+                                      ctypes.POINTER(vp)]
+        L.rrq_plan_refit.argtypes = [vp, ctypes.POINTER(Surface), vp]
+        L.rrq_plan_destroy.argtypes = [vp]
+        L.rrq_workspace_size.argtypes = [vp, ctypes.POINTER(Targets), ctypes.POINTER(ctypes.c_size_t)]
+        L.rrq_pair_offsets.argtypes = [vp, ctypes.POINTER(Targets), vp, ctypes.POINTER(i64), vp]
+        L.rrq_assemble.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp, vp,
+                                   ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
+        L.rrq_apply.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                vp, vp, vp]
+        L.rrq_status_string.argtypes = [i32]
+        L.rrq_status_string.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name != "rrq_status_string":
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RRQError(f"rrq call failed: {rc} ({lib().rrq_status_string(rc).decode()})")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+class DeviceSurface:
+    """Surface arrays resident on the device (torch tensors) plus the host order list."""
+
+    def __init__(self, surf):
+        import torch
+        self.order_host = np.ascontiguousarray(surf["order"], dtype=np.int32)
+        self.order = _dev(self.order_host, torch.int32)
+        self.node_off = _dev(surf["node_off"], torch.int64)
+        self.node_xyz = _dev(surf["node_xyz"], torch.float64)
+        self.node_nrm = _dev(surf["node_nrm"], torch.float64)
+        self.node_wt = _dev(surf["node_wt"], torch.float64)
+        self.edge_off = _dev(surf["edge_off"], torch.int64)
+        self.edge_xyz = _dev(surf["edge_xyz"], torch.float64)
+        self.npatch = int(len(self.order_host))
+
+    def cstruct(self):
+        return Surface(self.npatch, self.order_host.ctypes.data, self.order.data_ptr(),
+                       self.node_off.data_ptr(), self.node_xyz.data_ptr(),
+                       self.node_nrm.data_ptr(), self.node_wt.data_ptr(),
+                       self.edge_off.data_ptr(), self.edge_xyz.data_ptr(),
+                       int(self.node_xyz.shape[1]), int(self.edge_xyz.shape[1]))
+
+
+class DeviceTargets:
+    def __init__(self, tg):
+        import torch
+        self.xyz = _dev(tg["xyz"], torch.float64)
+        self.nrm = _dev(tg["nrm"], torch.float64)
+        self.self_patch = _dev(tg["self_patch"], torch.int32)
+        self.self_node = _dev(tg["self_node"], torch.int32)
+        self.near_ptr = _dev(tg["near_ptr"], torch.int64)
+        self.near_patch = _dev(tg["near_patch"], torch.int32)
+        self.ntarget = int(self.xyz.shape[1])
+        self.nnz = int(self.near_patch.shape[0])
+
+    def cstruct(self):
+        return Targets(self.ntarget, self.nnz, self.xyz.data_ptr(), self.nrm.data_ptr(),
+                       self.self_patch.data_ptr(), self.self_node.data_ptr(),
+                       self.near_ptr.data_ptr(), self.near_patch.data_ptr() if self.nnz else 0)
+
+
+class Plan:
+    """rrq_plan: per-patch frames, coefficient maps and edge tables on the device."""
+
+    def __init__(self, dsurf, rho_far=0.0, newton_tol=0.0, newton_maxit=0, tile_targets=0):
+        self.dsurf = dsurf
+        self._s = dsurf.cstruct()
+        self._o = Options(rho_far, newton_tol, newton_maxit, tile_targets)
+        h = ctypes.c_void_p()
+        _check(lib().rrq_plan_create(ctypes.byref(self._s), ctypes.byref(self._o), _stream(),
+                                     ctypes.byref(h)))
+        self.handle = h
+
+    def refit(self, dsurf=None):
+        if dsurf is not None:
+            self.dsurf = dsurf
+            self._s = dsurf.cstruct()
+        _check(lib().rrq_plan_refit(self.handle, ctypes.byref(self._s), _stream()))
+
+    def close(self):
+        if self.handle:
+            _check(lib().rrq_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Assembler:
+    """Pair offsets, workspace and output buffers for one near list."""
+
+    def __init__(self, plan, dtg, kmask=RRQ_K_ALL):
+        import torch
+        self.plan, self.dtg, self.kmask = plan, dtg, kmask
+        self._t = dtg.cstruct()
+        self.pair_off = torch.empty(dtg.nnz + 1, dtype=torch.int64, device="cuda")
+        nw = ctypes.c_int64()
+        _check(lib().rrq_pair_offsets(plan.handle, ctypes.byref(self._t), self.pair_off.data_ptr(),
+                                      ctypes.byref(nw), _stream()))
+        self.nweights = int(nw.value)
+        sz = ctypes.c_size_t()
+        _check(lib().rrq_workspace_size(plan.handle, ctypes.byref(self._t), ctypes.byref(sz)))
+        self.workspace = torch.empty(int(sz.value), dtype=torch.uint8, device="cuda")
+        self.out = {k: (torch.empty(self.nweights, dtype=torch.float64, device="cuda")
+                        if kmask & (1 << i) else None) for i, k in enumerate(KERNELS)}
+
+    def pair_offsets(self):
+        _check(lib().rrq_pair_offsets(self.plan.handle, ctypes.byref(self._t),
+                                      self.pair_off.data_ptr(), None, _stream()))
+
+    def assemble(self, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV, stats=False):
+        st = Stats() if stats else None
+        ptr = [self.out[k].data_ptr() if self.out[k] is not None else None for k in KERNELS]
+        _check(lib().rrq_assemble(self.plan.handle, ctypes.byref(self._t), self.kmask, flags,
+                                  ptr[0], ptr[1], ptr[2], ptr[3], self.pair_off.data_ptr(),
+                                  self.workspace.data_ptr(), self.workspace.numel(), _stream(),
+                                  ctypes.byref(st) if st is not None else None))
+        return st.as_dict() if st is not None else None
+
+    def apply(self, density):
+        import torch
+        dens = torch.as_tensor(density, dtype=torch.float64, device="cuda")
+        pots = {k: (torch.empty(self.dtg.ntarget, dtype=torch.float64, device="cuda")
+                    if self.out[k] is not None else None) for k in KERNELS}
+        ptr = lambda d, k: d[k].data_ptr() if d[k] is not None else None
+        _check(lib().rrq_apply(self.plan.handle, ctypes.byref(self._t), self.kmask,
+                               ptr(self.out, "S"), ptr(self.out, "D"), ptr(self.out, "Sp"),
+                               ptr(self.out, "Dp"), self.pair_off.data_ptr(), dens.data_ptr(),
+                               ptr(pots, "S"), ptr(pots, "D"), ptr(pots, "Sp"), ptr(pots, "Dp"),
+                               _stream()))
+        return pots
