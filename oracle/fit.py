@@ -33,21 +33,34 @@ def monomial_interp_matrix(t):
 
 
 def edge_coefficients(samples):
-    """Monomial coefficients (ptilde, 3) of the edge interpolant through GL samples (Sec. 3.5)."""
+    """Legendre coefficients (ptilde, 3) of the degree ptilde-1 interpolant through the GL
+    samples of an edge: c_k = (2k+1)/2 sum_i w_i P_k(t_i) s_i (exact, since the GL rule
+    integrates P_k times the interpolant exactly).  The paper leaves the representation of
+    the boundary curve open; the Legendre basis keeps its evaluation well conditioned."""
     n = samples.shape[0]
-    t, _ = gauss_legendre(n)
-    return np.linalg.solve(np.vander(t, n, increasing=True), samples)
+    t, w = gauss_legendre(n)
+    P = np.polynomial.legendre.legvander(t, n - 1)          # P[i, k] = P_k(t_i)
+    return ((2 * np.arange(n) + 1) / 2.0)[:, None] * (P.T @ (w[:, None] * samples))
 
 
 def poly_eval(coef, t):
-    """Evaluate sum_k coef[k] t^k (coef (n, 3)) and its t-derivative at t (real or complex)."""
+    """Value and t-derivative of the Legendre series sum_k coef[k] P_k(t) (coef (n, 3)) at t
+    (real or complex), by the three-term recurrence P_{k+1} = ((2k+1) t P_k - k P_{k-1})/(k+1)
+    and P'_{k+1} = P'_{k-1} + (2k+1) P_k."""
     t = np.asarray(t)
     n = coef.shape[0]
-    val = np.zeros(t.shape + (3,), dtype=np.result_type(t, coef))
+    dt = np.result_type(t, coef)
+    p_prev, p = np.zeros(t.shape, dtype=dt), np.ones(t.shape, dtype=dt)
+    d_prev, d = np.zeros(t.shape, dtype=dt), np.zeros(t.shape, dtype=dt)
+    val = p[..., None] * coef[0]
     der = np.zeros_like(val)
-    for k in range(n - 1, -1, -1):
-        der = der * t[..., None] + val
-        val = val * t[..., None] + coef[k]
+    for k in range(0, n - 1):
+        p_next = ((2 * k + 1) * t * p - k * p_prev) / (k + 1)
+        d_next = d_prev + (2 * k + 1) * p
+        p_prev, p = p, p_next
+        d_prev, d = d, d_next
+        val = val + p[..., None] * coef[k + 1]
+        der = der + d[..., None] * coef[k + 1]
     return val, der
 
 
@@ -80,9 +93,13 @@ class Frame:
         return np.asarray(v) @ self.R
 
 
-def _weighted_pinv(M, w):
-    """(Omega M)^+ Omega with Omega = diag(sqrt(w)), via Householder QR."""
+def _weighted_pinv(M, w, solver="qr"):
+    """(Omega M)^+ Omega with Omega = diag(sqrt(w)), via Householder QR (default) or, as an
+    independent backward-stable alternative used to measure conditioning, the SVD."""
     sw = np.sqrt(w)
+    if solver == "svd":
+        X, *_ = np.linalg.lstsq(sw[:, None] * M, np.diag(sw), rcond=None)
+        return X
     Q, Rr = np.linalg.qr(sw[:, None] * M)
     return np.linalg.solve(Rr, Q.T * sw[None, :])
 
@@ -109,7 +126,7 @@ class PatchFit:
     M_S  (5 n_p, N): nodal sigma         -> [d; g] of Theorem thm:slpreduction
     """
 
-    def __init__(self, q, node_xyz, node_nrm, edge_samples):
+    def __init__(self, q, node_xyz, node_nrm, edge_samples, lsq_solver="qr"):
         self.q = q
         self.p = q
         self.frame = Frame(edge_samples, node_nrm)
@@ -123,12 +140,12 @@ class PatchFit:
         N = node_xyz.shape[0]
         A = dlp_system_matrix(gH)
         self.A = A
-        Ap = _weighted_pinv(A, np.tile(self.lsw, 4))
+        Ap = _weighted_pinv(A, np.tile(self.lsw, 4), lsq_solver)
         self.M_D = Ap[:, :N]
         self.M_Sp = sum(Ap[:, k * N:(k + 1) * N] * self.nl[None, :, k - 1] for k in (1, 2, 3))
         B = np.einsum('ikn,ik->in', gH, self.nl)
         self.B = B
-        Bp = _weighted_pinv(B, self.lsw)
+        Bp = _weighted_pinv(B, self.lsw, lsq_solver)
         self.M_S = np.vstack([Bp, self.M_D @ H @ Bp])
         edges_local = [self.frame.point(edge_samples[e]) for e in range(4)]
         self.edges_local = np.array(edges_local)

@@ -15,12 +15,18 @@ ptilde Gauss-Legendre samples) and a target x:
 * lambda^{(m)} = U^T I^{(m)} (eq. ssq1dintegrals2), so that
   int f(t) / |r(t) - x|^m dt ~= sum_i w_i^{(m)} f(t_i) with
   w_i^{(m)} = lambda_i^{(m)} |t_i - t0|^m / |r_i - x|^m.
+  The recurrence and the product U^T I are evaluated in 40-digit arithmetic
+  (mpmath) from the double-precision t0 and nodes, then rounded: in double
+  precision this route loses up to 8 digits for ptilde >= 12 (growth of the
+  forward recurrence for |t0| > 1 and cancellation in U^T I), so the oracle
+  evaluates the paper's formula exactly instead.
 * An edge whose root lies outside the Bernstein ellipse of radius rho_far is
   integrated with the plain GL rule (reading: the near/far split of point (3)
   in the introduction; rho_far = 10^{8/ptilde}).
 """
 import math
 
+import mpmath
 import numpy as np
 
 from .fit import gauss_legendre, poly_eval
@@ -95,6 +101,50 @@ def moments(t0, n):
     return I1, I3
 
 
+_MP_DPS = 40
+_U_EXACT = {}
+
+
+def _exact_U(t):
+    """U = V^{-1} of the (double) GL nodes, in 40-digit arithmetic."""
+    key = tuple(t)
+    if key not in _U_EXACT:
+        with mpmath.workdps(_MP_DPS):
+            n = len(t)
+            V = mpmath.matrix(n, n)
+            for i in range(n):
+                for k in range(n):
+                    V[i, k] = mpmath.mpf(float(t[i])) ** k
+            _U_EXACT[key] = V ** -1
+    return _U_EXACT[key]
+
+
+def lagrange_moments_exact(t0, t):
+    """lambda^{(1)}, lambda^{(3)} = U^T I^{(1)}, U^T I^{(3)} with the moment recurrences of
+    `moments` carried out in 40-digit arithmetic (inputs: double t0 and nodes t)."""
+    n = len(t)
+    U = _exact_U(t)
+    with mpmath.workdps(_MP_DPS):
+        a = mpmath.mpf(float(t0.real))
+        b = abs(mpmath.mpf(float(t0.imag)))
+        b2 = b * b
+        abs2 = a * a + b2
+        Rp = mpmath.sqrt((1 - a) ** 2 + b2)
+        Rm = mpmath.sqrt((1 + a) ** 2 + b2)
+        I1 = [mpmath.asinh((1 - a) / b) + mpmath.asinh((1 + a) / b)]
+        I1.append((Rp - Rm) + a * I1[0])
+        for k in range(2, n):
+            I1.append(((Rp - (-1) ** (k - 1) * Rm) + (2 * k - 1) * a * I1[k - 1]
+                       - (k - 1) * abs2 * I1[k - 2]) / k)
+        I3 = [(1 - a) / (b2 * Rp) - (-1 - a) / (b2 * Rm)]
+        I3.append(-(1 / Rp - 1 / Rm) + a * I3[0])
+        for k in range(2, n):
+            I3.append(I1[k - 2] + 2 * a * I3[k - 1] - abs2 * I3[k - 2])
+        lam1 = [float(mpmath.fsum(U[k, i] * I1[k] for k in range(n))) for i in range(n)]
+        lam3 = [float(mpmath.fsum(U[k, i] * I3[k] for k in range(n))) for i in range(n)]
+    return np.array(lam1), np.array(lam3)
+
+
 class EdgeQuadrature:
     """Effective weights of one (target, edge) pair for 1/|r-x| and 1/|r-x|^3."""
 
@@ -119,11 +169,7 @@ class EdgeQuadrature:
             if ok and bernstein_radius(t0) <= rf:
                 self.near = True
         if self.near:
-            # lambda = U^T I with U = V^{-1}: solve V^T lambda = I (LU, backward stable)
-            Vt = np.vander(t, ptilde, increasing=True).T
-            I1, I3 = moments(self.t0, ptilde)
-            lam1 = np.linalg.solve(Vt, I1)
-            lam3 = np.linalg.solve(Vt, I3)
+            lam1, lam3 = lagrange_moments_exact(self.t0, t)
             tt = np.sqrt((t - self.t0.real) ** 2 + self.t0.imag ** 2)
             self.w1 = lam1 * tt / dist
             self.w3 = lam3 * tt ** 3 / dist ** 3

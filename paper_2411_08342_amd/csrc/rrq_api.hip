@@ -116,10 +116,14 @@ static rrq_status upload_consts(rrq_plan* p, int q) {
   o.gl_w = (const double*)b;
   if (!up(T.glq_w.data(), T.glq_w.size() * 8, &b)) return RRQ_ERR_OOM;
   o.glq_w = (const double*)b;
-  if (!up(T.U.data(), T.U.size() * 8, &b)) return RRQ_ERR_OOM;
-  o.U = (const double*)b;
+  if (!up(T.LT.data(), T.LT.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.LT = (const double*)b;
+  if (!up(T.DP.data(), T.DP.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.DP = (const double*)b;
   if (!up(T.lag_m1.data(), T.lag_m1.size() * 8, &b)) return RRQ_ERR_OOM;
   o.lag_m1 = (const double*)b;
+  if (!up(T.bary.data(), T.bary.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.bary = (const double*)b;
   if (!up(T.dlp_ptr.data(), T.dlp_ptr.size() * 4, &b)) return RRQ_ERR_OOM;
   o.dlp_ptr = (const int32_t*)b;
   if (!up(T.dlp.data(), T.dlp.size() * sizeof(Term), &b)) return RRQ_ERR_OOM;

@@ -103,6 +103,25 @@ OrderTables build_order_tables(int q, int pt) {
     T.lag_m1[i] = (double)s;
   }
 
+  // discrete Legendre transform of the GL samples and Legendre derivatives at the nodes
+  T.LT.assign(pt * pt, 0.0);
+  T.DP.assign(pt * pt, 0.0);
+  for (int i = 0; i < pt; ++i) {
+    long double x = T.gl_t[i], p0 = 0, p1 = 1, d0 = 0, d1 = 0;
+    for (int k = 0; k < pt; ++k) {
+      T.LT[k * pt + i] = (double)((2 * k + 1) / 2.0L * (long double)T.gl_w[i] * p1);
+      T.DP[i * pt + k] = (double)d1;
+      long double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+      long double d2 = d0 + (2 * k + 1) * p1;
+      p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+  }
+  T.bary.assign(pt, 0.0);
+  for (int i = 0; i < pt; ++i) {
+    long double ti = T.gl_t[i];
+    T.bary[i] = (double)((i & 1 ? -1.0L : 1.0L) * sqrtl((1 - ti * ti) * (long double)T.gl_w[i]));
+  }
+
   // translation terms, grouped by basis function (l, m), 1 <= m <= l <= q
   T.dlp_ptr.assign(1, 0);
   T.slp_ptr.assign(1, 0);

@@ -28,7 +28,10 @@ struct OrderTables {
   std::vector<double> gl_t, gl_w;     // ptilde-point GL rule on [-1, 1]
   std::vector<double> glq_w;          // q-point GL weights (least-squares weights)
   std::vector<double> U;              // [pt][pt]: U[k*pt + i] = coeff of t^k in l_i(t)
+  std::vector<double> LT;             // [pt][pt]: LT[k*pt + i] = (2k+1)/2 w_i P_k(t_i)
+  std::vector<double> DP;             // [pt][pt]: DP[i*pt + k] = P_k'(t_i)
   std::vector<double> lag_m1;         // l_i(-1)
+  std::vector<double> bary;           // barycentric weights (-1)^i sqrt((1 - t_i^2) w_i)
   std::vector<int32_t> dlp_ptr, slp_ptr;   // [np+1]
   std::vector<Term> dlp, slp;
 };

@@ -11,8 +11,9 @@ constexpr int NT = 256;
 // ---------------------------------------------------------------------------------------
 // Frame (Sec. 5.1 scaling/rotation): origin = mean of the corners, z along
 // (c2 - c0) x (c3 - c1) (sign of the mean node normal), x along the first side, scale =
-// longest side.  Local coordinates R^T (r - o) / s of nodes and edge samples; monomial
-// coefficients of each edge interpolant (c = U samples, Sec. 3.5) and its tangent.
+// longest side.  Local coordinates R^T (r - o) / s of nodes and edge samples; Legendre
+// coefficients of each edge interpolant (discrete Legendre transform of the GL samples,
+// a well-conditioned representation of the boundary curve) and its tangent.
 // ---------------------------------------------------------------------------------------
 template <int Q>
 __global__ __launch_bounds__(NT) void k_geometry(PlanDev pd, rrq_surface s, OrderDev od,
@@ -121,24 +122,20 @@ __global__ __launch_bounds__(NT) void k_geometry(PlanDev pd, rrq_surface s, Orde
       }
     }
     __syncthreads();
-    // monomial coefficients a_k = sum_i U[k][i] s_i per edge and coordinate
+    // Legendre coefficients c_k = (2k+1)/2 sum_i w_i P_k(t_i) s_i per edge and coordinate
     for (int idx = tid; idx < 4 * PT * 3; idx += NT) {
       const int c = idx % 3, k = (idx / 3) % PT, e = idx / (3 * PT);
       double acc = 0.0;
-      for (int i = 0; i < PT; ++i) acc += od.U[k * PT + i] * sm_loc[(e * PT + i) * 3 + c];
+      for (int i = 0; i < PT; ++i) acc += od.LT[k * PT + i] * sm_loc[(e * PT + i) * 3 + c];
       pd.edge_coef[c * pd.E + e0 + e * PT + k] = acc;
       sm_coef[(e * PT + k) * 3 + c] = acc;
     }
     __syncthreads();
-    // tangent r'(t_i) = sum_k k a_k t_i^{k-1}
+    // tangent r'(t_i) = sum_k c_k P_k'(t_i)
     for (int idx = tid; idx < 4 * PT * 3; idx += NT) {
       const int c = idx % 3, i = (idx / 3) % PT, e = idx / (3 * PT);
-      const double t = od.gl_t[i];
-      double der = 0.0, val = 0.0;
-      for (int k = PT - 1; k >= 0; --k) {
-        der = der * t + val;
-        val = val * t + sm_coef[(e * PT + k) * 3 + c];
-      }
+      double der = 0.0;
+      for (int k = 0; k < PT; ++k) der += od.DP[i * PT + k] * sm_coef[(e * PT + k) * 3 + c];
       pd.edge_tan[c * pd.E + e0 + e * PT + i] = der;
     }
     __syncthreads();

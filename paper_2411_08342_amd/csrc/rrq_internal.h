@@ -16,8 +16,10 @@ struct OrderDev {
   const double* gl_t;
   const double* gl_w;
   const double* glq_w;
-  const double* U;
+  const double* LT;         // Legendre transform of GL samples
+  const double* DP;         // Legendre derivatives at the GL nodes
   const double* lag_m1;
+  const double* bary;       // barycentric weights of the ptilde GL nodes
   const int32_t* dlp_ptr;
   const Term* dlp;
   const int32_t* slp_ptr;

@@ -82,7 +82,9 @@ struct PairSmem {
   double t0[4][2];
   int near[4];
   int npan[4];
-  double mom1[4][PT], mom3[4][PT];
+  double lam1[4][PT], lam3[4][PT];
+  double pt_tau[PNT], pt_w1[PNT], pt_w3[PNT];
+  int pt_hit[PNT];
   double w1[4 * PT], w3[4 * PT], d[4 * PT * 3], av[4 * PT * 3];
   double pan[4][kMaxPanels][2];
   cplx V[NJK];
@@ -97,16 +99,24 @@ struct PairSmem {
   int cand_i[PNT / 64];
 };
 
-__device__ __forceinline__ void horner3(const double* coef, int stride, int n, cplx t, cplx* r,
-                                        cplx* dr) {
+// value and derivative of the Legendre series sum_k coef[k*stride + c] P_k(t), c = 0..2,
+// at complex t: P_{k+1} = ((2k+1) t P_k - k P_{k-1})/(k+1), P'_{k+1} = P'_{k-1} + (2k+1) P_k
+__device__ __forceinline__ void leg3(const double* coef, int stride, int n, cplx t, cplx* r,
+                                     cplx* dr) {
+  cplx p0 = mk(0, 0), p1 = mk(1, 0), d0 = mk(0, 0), d1 = mk(0, 0);
   for (int c = 0; c < 3; ++c) {
-    cplx v = mk(0, 0), d = mk(0, 0);
-    for (int k = n - 1; k >= 0; --k) {
-      d = d * t + v;
-      v = v * t + mk(coef[k * stride + c], 0.0);
+    r[c] = mk(coef[c], 0.0);
+    dr[c] = mk(0, 0);
+  }
+  for (int k = 0; k < n - 1; ++k) {
+    const cplx p2 = (1.0 / (k + 1)) * ((2.0 * k + 1.0) * (t * p1) - (double)k * p0);
+    const cplx d2 = d0 + (2.0 * k + 1.0) * p1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    for (int c = 0; c < 3; ++c) {
+      const double ck = coef[(k + 1) * stride + c];
+      r[c] = r[c] + ck * p1;
+      dr[c] = dr[c] + ck * d1;
     }
-    r[c] = v;
-    dr[c] = d;
   }
 }
 
@@ -200,11 +210,12 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
     if (tid < 4) {
       const int e = tid;
       const double* cf = S.ecoef + e * PT * 3;
+      // end points r(-1) = sum_k (-1)^k c_k, r(1) = sum_k c_k (P_k(+-1) = (+-1)^k)
       double A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-      for (int kk = PT - 1; kk >= 0; --kk)
+      for (int kk = 0; kk < PT; ++kk)
         for (int c = 0; c < 3; ++c) {
-          A[c] = -A[c] + cf[kk * 3 + c];
-          B[c] = B[c] + cf[kk * 3 + c];
+          A[c] += (kk & 1) ? -cf[kk * 3 + c] : cf[kk * 3 + c];
+          B[c] += cf[kk * 3 + c];
         }
       double m[3], dv[3], v[3];
       for (int c = 0; c < 3; ++c) {
@@ -224,7 +235,7 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
         conv = 0;
         for (its = 1; its <= so.newton_maxit; ++its) {
           cplx r[3], dr[3];
-          horner3(cf, 3, PT, t0, r, dr);
+          leg3(cf, 3, PT, t0, r, dr);
           cplx f = mk(0, 0), fp = mk(0, 0);
           for (int c = 0; c < 3; ++c) {
             cplx ec = r[c] - mk(S.x[c], 0.0);
@@ -248,22 +259,8 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
       S.t0[e][1] = t0.im;
       if (near) {
         atomicAdd(&out.counters[0], 1ull);
-        const double a = t0.re, b = fabs(t0.im), b2 = b * b, abs2 = a * a + b2;
-        const double Rp = sqrt((1 - a) * (1 - a) + b2), Rm = sqrt((1 + a) * (1 + a) + b2);
-        double* I1 = S.mom1[e];
-        double* I3 = S.mom3[e];
-        I1[0] = asinh((1 - a) / b) + asinh((1 + a) / b);
-        I1[1] = (Rp - Rm) + a * I1[0];
-        double sgn = -1.0;   // (-1)^(k-1) for k = 2
-        for (int kk = 2; kk < PT; ++kk) {
-          const double bnd = Rp - sgn * Rm;
-          I1[kk] = (bnd + (2 * kk - 1) * a * I1[kk - 1] - (kk - 1) * abs2 * I1[kk - 2]) / kk;
-          sgn = -sgn;
-        }
-        I3[0] = (1 - a) / (b2 * Rp) - (-1 - a) / (b2 * Rm);
-        I3[1] = -(1.0 / Rp - 1.0 / Rm) + a * I3[0];
-        for (int kk = 2; kk < PT; ++kk) I3[kk] = I1[kk - 2] + 2 * a * I3[kk - 1] - abs2 * I3[kk - 2];
-        // graded panels for Omega_0 (bisection toward Re t0)
+        // graded panels: dyadic bisection toward Re t0 until every panel sees t0 at
+        // Bernstein radius >= rho_far in its own scaled coordinate
         double stk[64][3];
         int sp = 0, np_ = 0;
         stk[sp][0] = -1.0; stk[sp][1] = 1.0; stk[sp][2] = 0; ++sp;
@@ -292,6 +289,69 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
       }
     }
     __syncthreads();
+    // Lagrange-basis moments of near edges, lambda_i^{(m)} = int l_i(t) |t - t0|^{-m} dt
+    // (the vector U^T I^{(m)} of the singularity swap), by GL quadrature on the graded panels
+    // with barycentric l_i; Omega_0 of near edges on the same points.
+    double om_near = 0.0;
+    for (int e = 0; e < 4; ++e) {
+      if (!S.near[e]) continue;
+      const int npts = S.npan[e] * PT;
+      const double a = S.t0[e][0], b = S.t0[e][1];
+      double l1 = 0.0, l3 = 0.0;
+      for (int base = 0; base < npts; base += PNT) {
+        const int idx = base + tid;
+        if (idx < npts) {
+          const int pn = idx / PT, g = idx % PT;
+          const double lo = S.pan[e][pn][0], hi = S.pan[e][pn][1];
+          const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+          const double tau = c + h * od.gl_t[g];
+          const double K2 = (tau - a) * (tau - a) + b * b;
+          const double K1 = 1.0 / sqrt(K2);
+          const double hw = h * od.gl_w[g];
+          double den = 0.0;
+          int hit = -1;
+          for (int j = 0; j < PT; ++j) {
+            const double dt = tau - od.gl_t[j];
+            if (dt == 0.0) hit = j;
+            else den += od.bary[j] / dt;
+          }
+          const double sc1 = hit >= 0 ? hw * K1 : hw * K1 / den;
+          S.pt_tau[tid] = tau;
+          S.pt_w1[tid] = sc1;
+          S.pt_w3[tid] = sc1 / K2;
+          S.pt_hit[tid] = hit;
+          cplx r[3], dr[3];
+          leg3(S.ecoef + e * PT * 3, 3, PT, mk(tau, 0.0), r, dr);
+          const double rr[3] = {r[0].re, r[1].re, r[2].re};
+          const double dd[3] = {dr[0].re, dr[1].re, dr[2].re};
+          om_near += hw * omega0_at(S.x, S.u, rr, dd);
+        } else {
+          S.pt_tau[tid] = 3.0;
+          S.pt_w1[tid] = 0.0;
+          S.pt_w3[tid] = 0.0;
+          S.pt_hit[tid] = -2;
+        }
+        __syncthreads();
+        if (tid < PT) {
+          const int cnt = npts - base < PNT ? npts - base : PNT;
+          const double ti = od.gl_t[tid], bi = od.bary[tid];
+          for (int pidx = 0; pidx < cnt; ++pidx) {
+            const int hit = S.pt_hit[pidx];
+            double li;
+            if (hit >= 0) li = hit == tid ? 1.0 : 0.0;
+            else li = bi / (S.pt_tau[pidx] - ti);
+            l1 += S.pt_w1[pidx] * li;
+            l3 += S.pt_w3[pidx] * li;
+          }
+        }
+        __syncthreads();
+      }
+      if (tid < PT) {
+        S.lam1[e][tid] = l1;
+        S.lam3[e][tid] = l3;
+      }
+    }
+    __syncthreads();
     // effective weights per (edge, node)
     double om_far = 0, ov0 = 0, ov1 = 0, ov2 = 0, dv0 = 0, dv1 = 0, dv2 = 0, dom0 = 0;
     for (int idx = tid; idx < 4 * PT; idx += PNT) {
@@ -302,12 +362,7 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
       const double R = sqrt(R2);
       double w1, w3;
       if (S.near[e]) {
-        double l1 = 0, l3 = 0;
-        for (int kk = 0; kk < PT; ++kk) {
-          const double uu = od.U[kk * PT + i];
-          l1 += uu * S.mom1[e][kk];
-          l3 += uu * S.mom3[e][kk];
-        }
+        const double l1 = S.lam1[e][i], l3 = S.lam3[e][i];
         const double ta = od.gl_t[i] - S.t0[e][0], tb = S.t0[e][1];
         const double tt = sqrt(ta * ta + tb * tb);
         const double q1 = tt / R;
@@ -338,23 +393,7 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
       const double cz = rp[0] * d[1] - rp[1] * d[0];
       dom0 -= w3 * (cx * S.nu[0] + cy * S.nu[1] + cz * S.nu[2]);
     }
-    // Omega_0 on graded panels of near edges
-    {
-      int tot = 0;
-      for (int e = 0; e < 4; ++e) tot += S.npan[e] * PT;
-      for (int idx = tid; idx < tot; idx += PNT) {
-        int rem = idx, e = 0;
-        while (rem >= S.npan[e] * PT) { rem -= S.npan[e] * PT; ++e; }
-        const int pn = rem / PT, i = rem % PT;
-        const double lo = S.pan[e][pn][0], hi = S.pan[e][pn][1];
-        const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
-        cplx r[3], dr[3];
-        horner3(S.ecoef + e * PT * 3, 3, PT, mk(c + h * od.gl_t[i], 0.0), r, dr);
-        const double rr[3] = {r[0].re, r[1].re, r[2].re};
-        const double dd[3] = {dr[0].re, dr[1].re, dr[2].re};
-        om_far += h * od.gl_w[i] * omega0_at(S.x, S.u, rr, dd);
-      }
-    }
+    om_far += om_near;
     {
       double v;
       v = block_sum<PNT>(om_far, S.red); if (tid == 0) S.Om[0] = v;

@@ -12,7 +12,7 @@ from scipy.special import lpmv
 from scipy import integrate
 
 from oracle import harmonics as hm
-from oracle.fit import PatchFit, gauss_legendre, poly_eval
+from oracle.fit import PatchFit, gauss_legendre, poly_eval, edge_coefficients
 from oracle.ssq import moments, chord_start, newton_root, EdgeQuadrature
 from oracle.rrq import pair_weights, line_integrals, choose_u
 from oracle.quaternion import qmul, pure
@@ -191,19 +191,32 @@ def test_moments_against_adaptive_quadrature(t0):
         assert abs(I3[k] - float(r3)) <= 1e-13 * max(1.0, abs(float(r3))) * 10 ** (k // 8)
 
 
+def test_edge_interpolant_reproduces_polynomial_curve():
+    """The Legendre-series interpolant through ptilde GL samples reproduces a polynomial curve
+    of degree < ptilde and its derivative at any (complex) parameter."""
+    t, _ = gauss_legendre(10)
+    f = lambda s: np.stack([s ** 3 - 0.5 * s, 0.2 * s ** 9 + s ** 2, np.ones_like(s) * 0.3 + 0 * s], -1)
+    fd = lambda s: np.stack([3 * s ** 2 - 0.5, 1.8 * s ** 8 + 2 * s, 0 * s], -1)
+    coef = edge_coefficients(f(t))
+    z = np.array([0.3 + 0.2j, -1.0 + 0j, 1.0 + 0j, 1.5 - 0.7j])
+    v, d = poly_eval(coef, z)
+    assert np.allclose(v, f(z), rtol=1e-13, atol=1e-11)
+    assert np.allclose(d, fd(z), rtol=1e-12, atol=1e-10)
+
+
 def test_root_straight_edge_is_chord_start_and_residual():
     """For a straight edge the root of eq. complexparameter is the chord start itself."""
     t, _ = gauss_legendre(12)
     a, b = np.array([0.1, -0.2, 0.3]), np.array([0.7, 0.4, -0.1])
     samples = 0.5 * (a + b) + 0.5 * (b - a) * t[:, None]
-    coef = np.linalg.solve(np.vander(t, 12, increasing=True), samples)
+    coef = edge_coefficients(samples)
     x = np.array([0.3, 0.2, 0.25])
     ts = chord_start(coef, x)
     t0, its, ok = newton_root(coef, x, ts)
     assert ok and abs(t0 - ts) < 1e-13
     # curved edge: residual of eq. complexparameter at the converged root
     samples2 = samples + 0.2 * (t ** 2)[:, None] * np.array([0.0, 0.3, 0.5])
-    coef2 = np.linalg.solve(np.vander(t, 12, increasing=True), samples2)
+    coef2 = edge_coefficients(samples2)
     t0, its, ok = newton_root(coef2, x, chord_start(coef2, x))
     r, _ = poly_eval(coef2, np.array(t0))
     assert ok and abs(np.sum((r - x) ** 2)) < 1e-14
@@ -217,7 +230,7 @@ def test_effective_weights_integrate_smooth_times_kernel():
     t, _ = gauss_legendre(n)
     curve = lambda s: np.array([s, 0.2 * s * s, 0.05 * s ** 3])
     samples = np.array([curve(s) for s in t])
-    coef = np.linalg.solve(np.vander(t, n, increasing=True), samples)
+    coef = edge_coefficients(samples)
     x = curve(0.37) + np.array([0.0, -0.01, 0.02])
     eq = EdgeQuadrature(coef, samples, x, n)
     assert eq.near
