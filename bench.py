@@ -1,0 +1,180 @@
+"""Benchmark: near-correction weights/sec (FP64, S/D/S'/D') for the star-shaped surface workload
+(1536 quadrilateral patches of order 8, 98,304 on-surface targets, near radius 1.5 patch
+diameters).  One step = the whole hot path on device-resident inputs: source-only plan
+(frames, edge tables, least-squares fits), pair offsets, and assembly of the four kernels'
+correction weights.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "near-correction weights/sec (FP64, S/D/S'/D') at ≤1e-11 err; batched vs plain"
+FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
+
+
+def flops_per_pair(q):
+    """Algorithmic FP64 flops of one (target, patch) pair at order q (ptilde = 2q), counting
+    only data-independent work (Newton iterations and panel points excluded):
+      edge contractions  4 ptilde (16 J1 + 76 J2)      V: 16, Q and dQ: 38 each per (j,k,node)
+      edge weights/Omega 4 ptilde * 60
+      translations       100 tD + 10 tS                  terms of the DLP/SLP sums
+      target harmonics   60 (q+1)^2
+      weight contraction 2 q^2 17 n_p                    rows x maps
+    """
+    p, pt = q, 2 * q
+    n_p = p * (p + 1) // 2
+    J1 = p * (p + 3) // 2
+    J2 = J1 - 2
+    tD = tS = 0
+    for l in range(1, p + 1):
+        for m in range(1, l + 1):
+            for j in range(1, l + 1):
+                for k in range(-j, j + 1):
+                    if abs(m - k) <= l - j:
+                        tS += 1
+                        if j >= 2:
+                            tD += 1
+    return (4 * pt * (16 * J1 + 76 * J2) + 4 * pt * 60 + 100 * tD + 10 * tS
+            + 60 * (p + 1) ** 2 + 2 * q * q * 17 * n_p)
+
+
+def build_workload(name):
+    from paper_2411_08342_amd import workloads as wl
+    if name == "star":
+        surf, tg, dens = wl.config2()
+        desc = ("star r=1+0.2ReY43+0.1ReY21, 1536 quads q=8, 98304 node targets, "
+                "near 1.5 patch diameters")
+    elif name == "star-small":
+        surf, tg, dens = wl.config2(n=4)
+        desc = "star, 96 quads q=8, node targets, near 1.5 patch diameters"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return surf, tg, desc
+
+
+def cpu_baseline(surf, tg, seconds=20.0, seed=0):
+    """The oracle, as it stands, on all near pairs of seeded targets (fits of the touched
+    patches included), one thread, until about `seconds` of work."""
+    from threadpoolctl import threadpool_limits
+    from oracle.assemble import pair_block
+    rng = np.random.default_rng(seed)
+    T = len(tg["near_ptr"]) - 1
+    order = rng.permutation(T)
+    fits = {}
+    nw = 0
+    npairs = 0
+    ntg = 0
+    results = {}
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for t in order:
+            for i in range(tg["near_ptr"][t], tg["near_ptr"][t + 1]):
+                P = int(tg["near_patch"][i])
+                W, _ = pair_block(surf, tg, fits, int(t), P)
+                results[int(i)] = W
+                nw += 4 * len(W["S"])
+                npairs += 1
+            ntg += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        dt = time.perf_counter() - t0
+    return dict(value=nw / dt, unit="weights/s", cores=1, kind="oracle",
+                sample=f"all {npairs} near pairs of {ntg} seeded targets "
+                       f"({len(fits)} patch fits included), {dt:.1f} s"), results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="star")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2411_08342_amd import rrq
+
+    surf, tg, desc = build_workload(args.workload)
+    print(f"[bench] workload ready: {surf['npatch']} patches, {tg['ntarget']} targets, "
+          f"{len(tg['near_patch'])} pairs", flush=True)
+    ds = rrq.DeviceSurface(surf)
+    dt = rrq.DeviceTargets(tg)
+    plan = rrq.Plan(ds)
+    asm = rrq.Assembler(plan, dt)
+    flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    if args.form == "plain":
+        flags |= rrq.RRQ_F_PLAIN
+    nweights = 4 * asm.nweights
+
+    def step(ev=None):
+        plan.refit()
+        asm.pair_offsets()
+        if ev is not None:
+            ev[0].record()
+        asm.assemble(flags=flags)
+        if ev is not None:
+            ev[1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = asm.assemble(flags=flags, stats=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+        print(f"[bench] step {k + 1}/{args.steps} queued", flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    asm_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    value = nweights / (ms_per_step / 1e3)
+
+    q = int(surf["order"][0])
+    alg_tflop = len(tg["near_patch"]) * flops_per_pair(q) / 1e12
+    achieved = alg_tflop / (asm_ms / 1e3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "weights/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "form": args.form, "pairs": int(len(tg["near_patch"])),
+                   "weights_per_step": int(nweights), "assemble_ms": asm_ms,
+                   "newton_iters_per_near_edge": stats["newton_iters"] / max(1, stats["near_edges"]),
+                   "near_edges": stats["near_edges"], "newton_fail": stats["newton_fail"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
+                     "kernel": f"k_pair_{args.form}<{q}>",
+                     "flops_per_pair": flops_per_pair(q)},
+    }
+    if not args.no_cpu_baseline:
+        cb, res = cpu_baseline(surf, tg, args.cpu_seconds)
+        off = asm.pair_off.cpu().numpy()
+        worst = 0.0
+        for i, W in res.items():
+            for k in rrq.KERNELS:
+                g = asm.out[k][off[i]:off[i + 1]].cpu().numpy()
+                worst = max(worst, np.max(np.abs(g - W[k])) / np.max(np.abs(W[k])))
+        cb["gpu_vs_oracle_max_rel_err_on_sample"] = worst
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
