@@ -97,7 +97,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--form", default="batched", choices=["plain", "batched"])
+    ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -113,7 +114,7 @@ def main():
           f"{len(tg['near_patch'])} pairs", flush=True)
     ds = rrq.DeviceSurface(surf)
     dt = rrq.DeviceTargets(tg)
-    plan = rrq.Plan(ds)
+    plan = rrq.Plan(ds, tile_targets=args.tile)
     asm = rrq.Assembler(plan, dt)
     flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
     if args.form == "plain":
@@ -160,7 +161,7 @@ def main():
                    "near_edges": stats["near_edges"], "newton_fail": stats["newton_fail"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
-                     "kernel": f"k_pair_{args.form}<{q}>",
+                     "kernel": (f"k_pair_plain<{q}>" if args.form == "plain" else f"k_pair_tile<{q},T>"),
                      "flops_per_pair": flops_per_pair(q)},
     }
     if not args.no_cpu_baseline:

@@ -58,6 +58,8 @@ struct rrq_plan {
   OrderDev od[kMaxQ + 1] = {};
   std::vector<void*> const_bufs;
   double rho_far[kMaxQ + 1] = {};
+  int tile = 8;                 // targets per tile of the batched form
+  int grid[kMaxQ + 1] = {};     // workgroups of the batched kernel per order
 
   PlanDev dev() const {
     PlanDev d;
@@ -204,6 +206,12 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
   if (opts) p->opt = *opts;
   if (p->opt.newton_tol <= 0) p->opt.newton_tol = 1e-14;
   if (p->opt.newton_maxit <= 0) p->opt.newton_maxit = 60;
+  if (p->opt.tile_targets != 0 && p->opt.tile_targets != 4 && p->opt.tile_targets != 8) {
+    delete p;
+    return RRQ_ERR_UNSUPPORTED;
+  }
+  p->tile = p->opt.tile_targets > 0 ? p->opt.tile_targets : 8;
+  for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = 2048;
   p->P = s->npatch;
   p->N = s->nnode;
   p->E = s->nedge;
@@ -315,16 +323,35 @@ static TargetsDev tdev(const rrq_targets* tg) {
   return t;
 }
 
-static size_t ws_bytes(int64_t nnz) {
-  // owner[nnz] (int64) + counters[8]
-  return (size_t)(nnz > 0 ? nnz : 1) * 8 + 8 * 8 + 256;
+// workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
+// start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4
+struct WsLayout {
+  size_t owner, counters, cnt, fill, start, tstart, ntiles, sorted, tiles, total;
+};
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+static WsLayout ws_layout(int64_t nnz, int P) {
+  const size_t n = (size_t)(nnz > 0 ? nnz : 1);
+  WsLayout w;
+  size_t o = 0;
+  w.owner = o; o = al(o + n * 8);
+  w.counters = o; o = al(o + 64);
+  w.cnt = o; o = al(o + (size_t)P * 4);
+  w.fill = o; o = al(o + (size_t)P * 4);
+  w.start = o; o = al(o + (size_t)(P + 1) * 8);
+  w.tstart = o; o = al(o + (size_t)(P + 1) * 8);
+  w.ntiles = o; o = al(o + 8);
+  w.sorted = o; o = al(o + n * 8);
+  w.tiles = o; o = al(o + (n / 4 + (size_t)P + 1) * 16);
+  w.total = o;
+  return w;
 }
+static size_t ws_bytes(int64_t nnz, int P) { return ws_layout(nnz, P).total; }
 
 rrq_status rrq_workspace_size(const rrq_plan* p, const rrq_targets* tg, size_t* bytes) {
   if (!bytes) return RRQ_ERR_ARG;
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
-  *bytes = ws_bytes(tg->nnz);
+  *bytes = ws_bytes(tg->nnz, p->P);
   return RRQ_OK;
 }
 
@@ -351,15 +378,16 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
   if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
-  if (workspace_bytes < ws_bytes(tg->nnz)) return RRQ_ERR_BUFFER;
+  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
   double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
   for (int K = 0; K < 4; ++K)
     if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
   if (flags & RRQ_F_LEARNED) return RRQ_ERR_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
-  int64_t* owner = (int64_t*)workspace;
-  unsigned long long* counters =
-      (unsigned long long*)((char*)workspace + (size_t)(tg->nnz > 0 ? tg->nnz : 1) * 8);
+  const WsLayout wl = ws_layout(tg->nnz, p->P);
+  char* wb = (char*)workspace;
+  int64_t* owner = (int64_t*)(wb + wl.owner);
+  unsigned long long* counters = (unsigned long long*)(wb + wl.counters);
   TargetsDev td = tdev(tg);
   if (launch_owner(td, owner, counters, st) != hipSuccess) return RRQ_ERR_DEVICE;
   AssembleOut ao;
@@ -370,11 +398,36 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   ao.owner = owner;
   ao.counters = counters;
   PlanDev pd = p->dev();
-  for (int qi = 0; qi < kNumOrders; ++qi) {
-    const int q = kOrders[qi];
-    if (p->patches_h[q].empty()) continue;
-    SolveOpts so{p->rho_far[q], p->opt.newton_tol, p->opt.newton_maxit};
-    if (launch_pair_plain(q, pd, p->od[q], td, ao, so, st) != hipSuccess) return RRQ_ERR_DEVICE;
+  if (flags & RRQ_F_PLAIN) {
+    for (int qi = 0; qi < kNumOrders; ++qi) {
+      const int q = kOrders[qi];
+      if (p->patches_h[q].empty()) continue;
+      SolveOpts so{p->rho_far[q], p->opt.newton_tol, p->opt.newton_maxit};
+      if (launch_pair_plain(q, pd, p->od[q], td, ao, so, st) != hipSuccess) return RRQ_ERR_DEVICE;
+    }
+  } else {
+    const int tile = p->tile;
+    int32_t* cnt = (int32_t*)(wb + wl.cnt);
+    int32_t* fill = (int32_t*)(wb + wl.fill);
+    int64_t* start = (int64_t*)(wb + wl.start);
+    int64_t* tstart = (int64_t*)(wb + wl.tstart);
+    int64_t* ntiles = (int64_t*)(wb + wl.ntiles);
+    int64_t* sorted = (int64_t*)(wb + wl.sorted);
+    int4* tiles = (int4*)(wb + wl.tiles);
+    if (launch_binning(td, p->P, tile, cnt, fill, start, tstart, ntiles, sorted, tiles, st) !=
+        hipSuccess)
+      return RRQ_ERR_DEVICE;
+    for (int qi = 0; qi < kNumOrders; ++qi) {
+      const int q = kOrders[qi];
+      if (p->patches_h[q].empty()) continue;
+      SolveOpts so{p->rho_far[q], p->opt.newton_tol, p->opt.newton_maxit};
+      int T = tile;
+      while (T > 4 && !tile_supported(q, T)) T /= 2;
+      if (!tile_supported(q, T)) return RRQ_ERR_UNSUPPORTED;
+      if (launch_pair_tile(q, T, p->grid[q], pd, p->od[q], td, ao, so, tiles, ntiles, sorted,
+                           st) != hipSuccess)
+        return RRQ_ERR_DEVICE;
+    }
   }
   if (stats) {
     unsigned long long h[8];

@@ -176,4 +176,37 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// value and derivative of the Legendre series sum_k coef[k*stride + c] P_k(t), c = 0..2,
+// at complex t: P_{k+1} = ((2k+1) t P_k - k P_{k-1})/(k+1), P'_{k+1} = P'_{k-1} + (2k+1) P_k
+__device__ __forceinline__ void leg3(const double* coef, int stride, int n, cplx t, cplx* r,
+                                     cplx* dr) {
+  cplx p0 = mk(0, 0), p1 = mk(1, 0), d0 = mk(0, 0), d1 = mk(0, 0);
+  for (int c = 0; c < 3; ++c) {
+    r[c] = mk(coef[c], 0.0);
+    dr[c] = mk(0, 0);
+  }
+  for (int k = 0; k < n - 1; ++k) {
+    const cplx p2 = (1.0 / (k + 1)) * ((2.0 * k + 1.0) * (t * p1) - (double)k * p0);
+    const cplx d2 = d0 + (2.0 * k + 1.0) * p1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    for (int c = 0; c < 3; ++c) {
+      const double ck = coef[(k + 1) * stride + c];
+      r[c] = r[c] + ck * p1;
+      dr[c] = dr[c] + ck * d1;
+    }
+  }
+}
+
+// omega_0 integrand (eq. omega0def) per unit dt at a real parameter
+__device__ __forceinline__ double omega0_at(const double* x, const double* u, const double* r,
+                                            const double* dr) {
+  const double d0 = x[0] - r[0], d1 = x[1] - r[1], d2 = x[2] - r[2];
+  const double R = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double c0 = d1 * u[2] - d2 * u[1];
+  const double c1 = d2 * u[0] - d0 * u[2];
+  const double c2 = d0 * u[1] - d1 * u[0];
+  const double num = c0 * dr[0] + c1 * dr[1] + c2 * dr[2];
+  return num / (R * (R + d0 * u[0] + d1 * u[1] + d2 * u[2]));
+}
+
 }  // namespace rrq

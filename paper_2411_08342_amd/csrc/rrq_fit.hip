@@ -179,7 +179,7 @@ __global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
         c3[0] = tp[2] * g3[1] - tp[1] * g3[2];
         c3[1] = tp[0] * g3[2] - tp[2] * g3[0];
         c3[2] = tp[1] * g3[0] - tp[0] * g3[1];
-        double* o = base + (((int64_t)e * NJK + jk_index(j, k)) * PT + i) * 12;
+        double* o = base + (((int64_t)e * PT + i) * NJK + jk_index(j, k)) * 12;
         for (int a = 0; a < 3; ++a) {
           o[2 * a] = c3[a].re;
           o[2 * a + 1] = c3[a].im;

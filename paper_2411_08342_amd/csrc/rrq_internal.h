@@ -47,7 +47,7 @@ struct PlanDev {
   double* edge_coef;        // [3][E] monomial coefficients per edge
   double* maps;             // per patch: M_D [4np][q^2], M_Sp [4np][q^2], M_S [5np][q^2]
   const int64_t* map_off;
-  double* tabs;             // per patch: [4][njk][pt][12]: c (3 cplx), h (3 cplx)
+  double* tabs;             // per patch: [4][pt][njk][12]: c (3 cplx), h (3 cplx)
   const int64_t* tab_off;
 };
 
@@ -90,6 +90,16 @@ hipError_t launch_pair_plain(int q, const PlanDev& pd, const OrderDev& od, const
 hipError_t launch_apply(const PlanDev& pd, const TargetsDev& tg, const double* const* w,
                         uint32_t kmask, const int64_t* pair_off, const int64_t* owner,
                         const double* density, double* const* pot, hipStream_t st);
+
+hipError_t launch_binning(const TargetsDev& tg, int P, int tile, int32_t* cnt, int32_t* fill,
+                          int64_t* start, int64_t* tstart, int64_t* ntiles, int64_t* sorted,
+                          int4* tiles, hipStream_t st);
+hipError_t launch_pair_tile(int q, int T, int grid, const PlanDev& pd, const OrderDev& od,
+                            const TargetsDev& tg, const AssembleOut& out, const SolveOpts& so,
+                            const int4* tiles, const int64_t* ntiles, const int64_t* sorted,
+                            hipStream_t st);
+size_t tile_lds_bytes(int q, int T);
+int tile_supported(int q, int T);
 
 int64_t fit_ws_doubles(int q);
 

@@ -150,6 +150,7 @@ def test_config1_raw_and_exterior_limit():
 
 
 def _small_star(n=3, q=8):
+    """Star surface with 6 n^2 patches of order q, node targets and 300 close targets."""
     surf = wl.discretize(wl.cubed_sphere_patches(n, radial=wl.star_radius), np.full(6 * n * n, q))
     x, nn, sp, sn = wl.node_targets(surf)
     rng = np.random.default_rng(5)
@@ -200,6 +201,48 @@ def test_empty_rows_and_kernel_mask():
     gpu, off, stats, _ = _run_gpu(surf, tg2, kmask=rrq.RRQ_K_D | rrq.RRQ_K_SP)
     assert gpu["S"] is None and gpu["Dp"] is None
     _compare(surf, tg2, gpu, off, list(range(len(tg2["near_patch"]))))
+
+
+def test_plain_form_parity():
+    """The reference one-pair-per-workgroup form (RRQ_F_PLAIN) on config-1 pairs."""
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    gpu, off, stats, _ = _run_gpu(surf, tg, flags=rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+                                  | rrq.RRQ_F_PLAIN)
+    rng = np.random.default_rng(4)
+    self_pairs = [k for t in range(0, 216, 31)
+                  for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])
+                  if tg["near_patch"][k] == tg["self_patch"][t]]
+    _compare(surf, tg, gpu, off, _sample(tg, 60, rng, must=self_pairs))
+
+
+@pytest.mark.parametrize("tile", [4, 8])
+def test_batched_tiles_vs_oracle_and_plain(tile):
+    """Batched form with tiles of 4 and 8 targets per patch against the oracle (sampled pairs,
+    conditioning-aware gates) and against the plain form on every pair (max-norm relative
+    difference reported; bounded by 1e-9 since both forms sum in different orders)."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg = _small_star(n=2)
+    ds, dt = rrq.DeviceSurface(surf), rrq.DeviceTargets(tg)
+    plan = rrq.Plan(ds, tile_targets=tile)
+    asm = rrq.Assembler(plan, dt)
+    base = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    asm.assemble(flags=base | rrq.RRQ_F_PLAIN)
+    torch.cuda.synchronize()
+    plain = {k: asm.out[k].cpu().numpy() for k in KERNELS}
+    st = asm.assemble(flags=base, stats=True)
+    torch.cuda.synchronize()
+    gpu = {k: asm.out[k].cpu().numpy() for k in KERNELS}
+    assert st["pairs"] == len(tg["near_patch"])
+    for k in KERNELS:
+        rel = np.max(np.abs(plain[k] - gpu[k])) / np.max(np.abs(plain[k]))
+        print("plain vs batched", k, f"{rel:.2e}")
+        assert rel <= 1e-9, (k, rel)
+    rng = np.random.default_rng(tile)
+    T0 = surf["node_xyz"].shape[1]
+    close = [k for t in range(T0, T0 + 300, 11) for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])]
+    _compare(surf, tg, gpu, asm.pair_off.cpu().numpy(), _sample(tg, 80, rng, must=close))
 
 
 def test_apply_matches_weights(cfg1):
