@@ -436,6 +436,7 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
         double Qr[4] = {0, 0, 0, 0}, Qi[4] = {0, 0, 0, 0};
         double Dr[4] = {0, 0, 0, 0}, Di[4] = {0, 0, 0, 0};
         for (int e = 0; e < 4; ++e)
+#pragma unroll 4
           for (int i = 0; i < PT; ++i) {
             const double* o = tb + (((int64_t)e * PT + i) * NJK + n) * 12;
             const double* tdp = td + ((t * 4 + e) * PT + i) * 8;
@@ -593,7 +594,18 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
         else if (K == 1) { M = maps; rr = rows; KR = 4 * NP; rstride = 4 * NP; }
         else if (K == 2) { M = maps + 4 * NP * Q2; rr = rows + T * 4 * NP; KR = 4 * NP; rstride = 4 * NP; }
         else { M = maps; rr = rows + T * 13 * NP; KR = 4 * NP; rstride = 4 * NP; }
-        for (int r = 0; r < KR; ++r) {
+        // rows x maps: 8 map loads in flight per thread
+        int r = 0;
+        for (; r + 8 <= KR; r += 8) {
+          double mv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) mv[u] = M[(r + u) * Q2 + j];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[t] += rr[t * rstride + r + u] * mv[u];
+        }
+        for (; r < KR; ++r) {
           const double mv = M[r * Q2 + j];
 #pragma unroll
           for (int t = 0; t < T; ++t) acc[t] += rr[t * rstride + r] * mv;

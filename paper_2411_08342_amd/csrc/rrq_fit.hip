@@ -212,10 +212,21 @@ __device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* sv, d
       sv[r - k] = (r == k) ? akk - alpha : A[(int64_t)r * ld + k];
     __syncthreads();
     for (int j = k + 1 + threadIdx.x; j < ncols; j += NT) {
-      double sdot = 0.0;
-      for (int r = k; r < m; ++r) sdot += sv[r - k] * A[(int64_t)r * ld + j];
-      sdot *= beta;
-      for (int r = k; r < m; ++r) A[(int64_t)r * ld + j] -= sdot * sv[r - k];
+      // 8 independent partial sums keep 8 loads in flight
+      double ps[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int r = k;
+      for (; r + 8 <= m; r += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ps[u] += sv[r + u - k] * A[(int64_t)(r + u) * ld + j];
+      }
+      for (; r < m; ++r) ps[0] += sv[r - k] * A[(int64_t)r * ld + j];
+      const double sdot = beta * (((ps[0] + ps[1]) + (ps[2] + ps[3])) + ((ps[4] + ps[5]) + (ps[6] + ps[7])));
+      r = k;
+      for (; r + 8 <= m; r += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) A[(int64_t)(r + u) * ld + j] -= sdot * sv[r + u - k];
+      }
+      for (; r < m; ++r) A[(int64_t)r * ld + j] -= sdot * sv[r - k];
     }
     __syncthreads();
     if (threadIdx.x == 0) A[(int64_t)k * ld + k] = alpha;
