@@ -143,6 +143,36 @@ rrq_status rrq_apply(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask
                      double* pot_S, double* pot_D, double* pot_Sp, double* pot_Dp,
                      void* stream);
 
+/* Autotuner of the batched form: times rrq_assemble on this near list for every supported
+ * tile size (targets per workgroup: 4, 8) and grid size (1024, 2048, 4096 workgroups) with
+ * HIP events on `stream`, keeps the fastest in the plan and returns it.  If `cache_path`
+ * (HOST, may be NULL) names a readable file written by an earlier call with the same patch
+ * orders, its choice is loaded instead of timing; otherwise the choice is written there.
+ * Synchronous.  Overwrites the output buffers. */
+typedef struct {
+  int32_t tile_targets;
+  int32_t grid;
+  double best_ms;
+  int32_t from_cache;
+} rrq_tune_result;
+rrq_status rrq_autotune(rrq_plan* plan, const rrq_targets* tg, uint32_t kmask, uint32_t flags,
+                        double* out_S, double* out_D, double* out_Sp, double* out_Dp,
+                        const int64_t* pair_off, void* workspace, size_t workspace_bytes,
+                        const char* cache_path, void* stream, rrq_tune_result* result);
+
+/* One whole assembly step (rrq_plan_refit, rrq_pair_offsets, rrq_assemble with the given
+ * arguments) captured into a HIP graph; rrq_graph_launch replays it on `stream`.  The graph
+ * holds the pointers it was created with: the buffers must stay allocated and the sizes
+ * unchanged until rrq_graph_destroy.  Nothing in the captured step allocates memory or
+ * issues memset/memcpy nodes. */
+typedef struct rrq_graph rrq_graph;
+rrq_status rrq_graph_create(rrq_plan* plan, const rrq_surface* surf, const rrq_targets* tg,
+                            uint32_t kmask, uint32_t flags, double* out_S, double* out_D,
+                            double* out_Sp, double* out_Dp, int64_t* pair_off,
+                            void* workspace, size_t workspace_bytes, rrq_graph** out);
+rrq_status rrq_graph_launch(rrq_graph* g, void* stream);
+rrq_status rrq_graph_destroy(rrq_graph* g);
+
 const char* rrq_status_string(rrq_status s);
 
 #ifdef __cplusplus

@@ -153,15 +153,26 @@ static rrq_status check_surface(const rrq_surface* s) {
   return RRQ_OK;
 }
 
+__global__ void k_copy3(const double* a, const double* b, const double* c, double* A, double* B,
+                        double* C, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    A[i] = a[i];
+    B[i] = b[i];
+    if (i < n) C[i] = c[i];
+  }
+}
+
 static rrq_status run_fit(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
-  // plan copies of the smooth-rule data used by the correction
-  if (hipMemcpyAsync(p->node_xyz_d, s->node_xyz, 3 * p->N * 8, hipMemcpyDeviceToDevice, st) !=
-          hipSuccess ||
-      hipMemcpyAsync(p->node_nrm_d, s->node_nrm, 3 * p->N * 8, hipMemcpyDeviceToDevice, st) !=
-          hipSuccess ||
-      hipMemcpyAsync(p->node_wt_d, s->node_wt, p->N * 8, hipMemcpyDeviceToDevice, st) !=
-          hipSuccess)
-    return RRQ_ERR_DEVICE;
+  // plan copies of the smooth-rule data used by the correction (a kernel, not a memcpy, so
+  // that the step can be captured into a graph)
+  {
+    int64_t g = (3 * p->N + 255) / 256;
+    hipLaunchKernelGGL(k_copy3, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st,
+                       s->node_xyz, s->node_nrm, s->node_wt, p->node_xyz_d, p->node_nrm_d,
+                       p->node_wt_d, p->N);
+    if (hipGetLastError() != hipSuccess) return RRQ_ERR_DEVICE;
+  }
   PlanDev pd = p->dev();
   rrq_surface sd = *s;
   sd.node_off = p->node_off_d;
@@ -463,3 +474,147 @@ rrq_status rrq_apply(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// autotuner and graph capture
+// ---------------------------------------------------------------------------------------
+#include <stdio.h>
+#include <string>
+
+static std::string order_key(const rrq_plan* p) {
+  std::string k;
+  for (int q = 0; q <= kMaxQ; ++q)
+    if (!p->patches_h[q].empty()) k += std::to_string(q) + "x" + std::to_string(p->patches_h[q].size()) + ";";
+  return k;
+}
+
+extern "C" rrq_status rrq_autotune(rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                                   uint32_t flags, double* out_S, double* out_D, double* out_Sp,
+                                   double* out_Dp, const int64_t* pair_off, void* workspace,
+                                   size_t workspace_bytes, const char* cache_path, void* stream,
+                                   rrq_tune_result* result) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!result) return RRQ_ERR_ARG;
+  const std::string key = order_key(p);
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char buf[512];
+      int T = 0, G = 0;
+      double ms = 0;
+      if (fgets(buf, sizeof buf, f) && fscanf(f, "%d %d %lf", &T, &G, &ms) == 3 &&
+          std::string(buf) == key + "\n" && (T == 4 || T == 8) && G > 0) {
+        fclose(f);
+        p->tile = T;
+        for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = G;
+        *result = rrq_tune_result{T, G, ms, 1};
+        return RRQ_OK;
+      }
+      fclose(f);
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RRQ_ERR_DEVICE;
+  const int tiles[2] = {4, 8};
+  const int grids[3] = {1024, 2048, 4096};
+  double best = 1e300;
+  int bT = p->tile, bG = p->grid[kOrders[0]];
+  flags &= ~(uint32_t)RRQ_F_PLAIN;
+  for (int T : tiles)
+    for (int G : grids) {
+      p->tile = T;
+      for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = G;
+      rrq_status r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off,
+                                  workspace, workspace_bytes, stream, nullptr);  // warm
+      if (r != RRQ_OK) continue;
+      (void)hipEventRecord(e0, st);
+      r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
+                       workspace_bytes, stream, nullptr);
+      (void)hipEventRecord(e1, st);
+      if (r != RRQ_OK || hipEventSynchronize(e1) != hipSuccess) continue;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; bT = T; bG = G; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->tile = bT;
+  for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = bG;
+  *result = rrq_tune_result{bT, bG, best, 0};
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "w");
+    if (f) {
+      fprintf(f, "%s\n%d %d %.6f\n", key.c_str(), bT, bG, best);
+      fclose(f);
+    }
+  }
+  return best < 1e300 ? RRQ_OK : RRQ_ERR_DEVICE;
+}
+
+struct rrq_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const rrq_targets* tg,
+                                       uint32_t kmask, uint32_t flags, double* out_S,
+                                       double* out_D, double* out_Sp, double* out_Dp,
+                                       int64_t* pair_off, void* workspace,
+                                       size_t workspace_bytes, rrq_graph** out) {
+  if (!out || !p) return RRQ_ERR_ARG;
+  *out = nullptr;
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  c = check_surface(s);
+  if (c != RRQ_OK) return c;
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RRQ_ERR_DEVICE;
+  // one eager pass on the capture stream first: kernel attributes are set outside capture
+  rrq_status r = rrq_plan_refit(p, s, cs);
+  if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, nullptr, cs);
+  if (r == RRQ_OK)
+    r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
+                     workspace_bytes, cs, nullptr);
+  if (r != RRQ_OK || hipStreamSynchronize(cs) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return r != RRQ_OK ? r : RRQ_ERR_DEVICE;
+  }
+  rrq_graph* g = new (std::nothrow) rrq_graph();
+  if (!g) { (void)hipStreamDestroy(cs); return RRQ_ERR_OOM; }
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete g;
+    (void)hipStreamDestroy(cs);
+    return RRQ_ERR_DEVICE;
+  }
+  r = rrq_plan_refit(p, s, cs);
+  if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, nullptr, cs);
+  if (r == RRQ_OK)
+    r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
+                     workspace_bytes, cs, nullptr);
+  hipError_t ec = hipStreamEndCapture(cs, &g->graph);
+  if (r == RRQ_OK && ec == hipSuccess &&
+      hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    *out = g;
+    return RRQ_OK;
+  }
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  (void)hipStreamDestroy(cs);
+  return r != RRQ_OK ? r : RRQ_ERR_DEVICE;
+}
+
+extern "C" rrq_status rrq_graph_launch(rrq_graph* g, void* stream) {
+  if (!g || !g->exec) return RRQ_ERR_ARG;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? RRQ_OK : RRQ_ERR_DEVICE;
+}
+
+extern "C" rrq_status rrq_graph_destroy(rrq_graph* g) {
+  if (!g) return RRQ_ERR_ARG;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return RRQ_OK;
+}

@@ -8,6 +8,7 @@
 namespace rrq {
 
 constexpr int BNT = 256;
+typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kWavePanels = 64;
 
 // ---------------------------------------------------------------------------------------
@@ -579,61 +580,76 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
         }
       }
       __syncthreads();
-      // ---- weights = rows x maps for all targets of the tile, correction, store
-      const double* maps = pd.maps + pd.map_off[P];
-      const double sc = fr[12];
-      for (int idx = tid; idx < 4 * Q2; idx += BNT) {
-        const int K = idx / Q2, j = idx % Q2;
-        if (!(out.kmask & (1u << K)) || out.w[K] == nullptr) continue;
-        double acc[T];
-        for (int t = 0; t < T; ++t) acc[t] = 0.0;
-        const double* M;
-        const double* rr;
-        int KR, rstride;
-        if (K == 0) { M = maps + 8 * NP * Q2; rr = rows + T * 8 * NP; KR = 5 * NP; rstride = 5 * NP; }
-        else if (K == 1) { M = maps; rr = rows; KR = 4 * NP; rstride = 4 * NP; }
-        else if (K == 2) { M = maps + 4 * NP * Q2; rr = rows + T * 4 * NP; KR = 4 * NP; rstride = 4 * NP; }
-        else { M = maps; rr = rows + T * 13 * NP; KR = 4 * NP; rstride = 4 * NP; }
-        // rows x maps: 8 map loads in flight per thread
-        int r = 0;
-        for (; r + 8 <= KR; r += 8) {
-          double mv[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) mv[u] = M[(r + u) * Q2 + j];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int t = 0; t < T; ++t) acc[t] += rr[t * rstride + r + u] * mv[u];
-        }
-        for (; r < KR; ++r) {
-          const double mv = M[r * Q2 + j];
-#pragma unroll
-          for (int t = 0; t < T; ++t) acc[t] += rr[t * rstride + r] * mv;
-        }
-        const int64_t nj = n0 + j;
-        const double rx = pd.node_xyz[nj], ry = pd.node_xyz[pd.N + nj], rz = pd.node_xyz[2 * pd.N + nj];
-        const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
-        const double wj = pd.node_wt[nj] * kInv4Pi;
-        for (int t = 0; t < nt; ++t) {
-          const int64_t k = sorted[tile.y + sub + t];
-          const int64_t g = out.owner[k];
-          double val = acc[t];
-          if (K == 0) val *= sc;
-          else if (K == 3) val /= sc;
-          if ((out.flags & RRQ_F_CORRECTION) && j != sself[t]) {
-            const double d0 = tg.xyz[g] - rx, d1 = tg.xyz[tg.T + g] - ry, d2 = tg.xyz[2 * tg.T + g] - rz;
-            const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
-            const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
-            const double dn = d0 * v0 + d1 * v1 + d2 * v2;
-            const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
-            double kv;
-            if (K == 0) kv = 1.0 / R;
-            else if (K == 1) kv = dn / R3;
-            else if (K == 2) kv = -dnt / R3;
-            else kv = (v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2);
-            val -= kv * wj;
+      // ---- Step 8 (matrix rows): weights = rows x maps on FP64 MFMA 16x16x4.
+      // Jobs (group, 16-column tile): group 0 = [rD; rDp] x M_D, 1 = rSp x M_Sp, 2 = rS x M_S.
+      // MFMA operand layout: lane l holds A[l%16][l/16], B[l/16][l%16]; result element v of
+      // lane l is D[l/16 + 4v][l%16].
+      {
+        constexpr int NCT = (Q2 + 15) / 16;
+        const double* maps = pd.maps + pd.map_off[P];
+        const double sc = fr[12];
+        const int arow = lane & 15, akk = lane >> 4;
+        for (int job = wv; job < 3 * NCT; job += BNT / 64) {
+          const int grp = job / NCT, ct = job % NCT;
+          const double* M = grp == 0 ? maps : (grp == 1 ? maps + 4 * NP * Q2 : maps + 8 * NP * Q2);
+          const int KR = grp == 2 ? 5 * NP : 4 * NP;
+          const double* rowp = nullptr;
+          if (grp == 0) {
+            if (arow < T) rowp = rows + arow * 4 * NP;
+            else if (arow < 2 * T) rowp = rows + T * 13 * NP + (arow - T) * 4 * NP;
+          } else if (arow < T) {
+            rowp = grp == 1 ? rows + T * 4 * NP + arow * 4 * NP : rows + T * 8 * NP + arow * 5 * NP;
           }
-          out.w[K][out.pair_off[k] + j] = val;
+          const int bcol = ct * 16 + (lane & 15);
+          const bool bval = bcol < Q2;
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+          // 8 k-steps per batch: operands loaded first (8 map loads in flight), then 8 MFMAs
+          for (int kb = 0; kb < KR; kb += 32) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int k = kb + 4 * u + akk;
+              const bool ok = k < KR;
+              av[u] = (rowp != nullptr && ok) ? rowp[k] : 0.0;
+              bv[u] = (bval && ok) ? M[k * Q2 + bcol] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+          }
+          if (!bval) continue;
+          const int j = bcol;
+          const int64_t nj = n0 + j;
+          const double rx = pd.node_xyz[nj], ry = pd.node_xyz[pd.N + nj], rz = pd.node_xyz[2 * pd.N + nj];
+          const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
+          const double wj = pd.node_wt[nj] * kInv4Pi;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = (lane >> 4) + 4 * v;
+            int K, t;
+            if (grp == 0) { K = i < T ? 1 : 3; t = i < T ? i : i - T; if (i >= 2 * T) t = T; }
+            else { K = grp == 1 ? 2 : 0; t = i < T ? i : T; }
+            if (t >= nt || !(out.kmask & (1u << K)) || out.w[K] == nullptr) continue;
+            const int64_t k = sorted[tile.y + sub + t];
+            const int64_t g = out.owner[k];
+            double val = acc[v];
+            if (K == 0) val *= sc;
+            else if (K == 3) val /= sc;
+            if ((out.flags & RRQ_F_CORRECTION) && j != sself[t]) {
+              const double d0 = tg.xyz[g] - rx, d1 = tg.xyz[tg.T + g] - ry, d2 = tg.xyz[2 * tg.T + g] - rz;
+              const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
+              const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
+              const double dn = d0 * v0 + d1 * v1 + d2 * v2;
+              const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
+              double kv;
+              if (K == 0) kv = 1.0 / R;
+              else if (K == 1) kv = dn / R3;
+              else if (K == 2) kv = -dnt / R3;
+              else kv = (v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2);
+              val -= kv * wj;
+            }
+            out.w[K][out.pair_off[k] + j] = val;
+          }
         }
       }
     }

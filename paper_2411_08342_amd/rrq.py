@@ -18,7 +18,8 @@ RRQ_F_CORRECTION, RRQ_F_ONSURF_PV, RRQ_F_PLAIN, RRQ_F_LEARNED = 1, 2, 8, 16
 KERNELS = ("S", "D", "Sp", "Dp")
 
 EXPORTED = ("rrq_plan_create", "rrq_plan_refit", "rrq_plan_destroy", "rrq_workspace_size",
-            "rrq_pair_offsets", "rrq_assemble", "rrq_apply", "rrq_status_string")
+            "rrq_pair_offsets", "rrq_assemble", "rrq_apply", "rrq_autotune", "rrq_graph_create",
+            "rrq_graph_launch", "rrq_graph_destroy", "rrq_status_string")
 
 
 class RRQError(RuntimeError):
@@ -55,6 +56,11 @@ class Stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile_targets", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -76,6 +82,14 @@ def lib():
                                    ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
         L.rrq_apply.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp]
+        L.rrq_autotune.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp, vp,
+                                   ctypes.c_size_t, ctypes.c_char_p, vp,
+                                   ctypes.POINTER(TuneResult)]
+        L.rrq_graph_create.argtypes = [vp, ctypes.POINTER(Surface), ctypes.POINTER(Targets), u32,
+                                       u32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                       ctypes.POINTER(vp)]
+        L.rrq_graph_launch.argtypes = [vp, vp]
+        L.rrq_graph_destroy.argtypes = [vp]
         L.rrq_status_string.argtypes = [i32]
         L.rrq_status_string.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -214,3 +228,48 @@ class Assembler:
                                ptr(pots, "S"), ptr(pots, "D"), ptr(pots, "Sp"), ptr(pots, "Dp"),
                                _stream()))
         return pots
+
+
+def _out_ptrs(asm):
+    return [asm.out[k].data_ptr() if asm.out[k] is not None else None for k in KERNELS]
+
+
+def autotune(asm, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV, cache_path=None):
+    """rrq_autotune: pick the tile size and grid of the batched form for this near list."""
+    r = TuneResult()
+    p = _out_ptrs(asm)
+    _check(lib().rrq_autotune(asm.plan.handle, ctypes.byref(asm._t), asm.kmask, flags, p[0], p[1],
+                              p[2], p[3], asm.pair_off.data_ptr(), asm.workspace.data_ptr(),
+                              asm.workspace.numel(),
+                              cache_path.encode() if cache_path else None, _stream(),
+                              ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in r._fields_}
+
+
+class Graph:
+    """rrq_graph: one whole step (refit, pair offsets, assembly) captured into a HIP graph."""
+
+    def __init__(self, asm, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV):
+        self.asm = asm
+        self._s = asm.plan.dsurf.cstruct()
+        p = _out_ptrs(asm)
+        h = ctypes.c_void_p()
+        _check(lib().rrq_graph_create(asm.plan.handle, ctypes.byref(self._s), ctypes.byref(asm._t),
+                                      asm.kmask, flags, p[0], p[1], p[2], p[3],
+                                      asm.pair_off.data_ptr(), asm.workspace.data_ptr(),
+                                      asm.workspace.numel(), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        _check(lib().rrq_graph_launch(self.handle, _stream()))
+
+    def close(self):
+        if self.handle:
+            _check(lib().rrq_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

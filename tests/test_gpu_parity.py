@@ -272,3 +272,47 @@ def test_refit_reproduces_plan(cfg1):
     torch.cuda.synchronize()
     for k in KERNELS:
         assert np.array_equal(asm.out[k].cpu().numpy(), gpu[k])
+
+
+def test_graph_replays_match_eager():
+    """The captured step replayed three times, with eager work and synchronisation between the
+    replays, reproduces the eager assembly bit for bit each time."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg = _small_star(n=2)
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
+    asm.assemble()
+    torch.cuda.synchronize()
+    eager = {k: asm.out[k].cpu().numpy().copy() for k in KERNELS}
+    g = rrq.Graph(asm)
+    for rep in range(3):
+        for k in KERNELS:
+            asm.out[k].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for k in KERNELS:
+            assert np.array_equal(asm.out[k].cpu().numpy(), eager[k]), (rep, k)
+        asm.assemble(flags=rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV | rrq.RRQ_F_PLAIN)
+        torch.cuda.synchronize()
+    g.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    """The autotuner returns a supported (tile, grid) choice, re-reads it from its cache, and the
+    tuned assembly still matches the oracle on sampled pairs."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg = _small_star(n=2)
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
+    cache = str(tmp_path / "tune.txt")
+    r1 = rrq.autotune(asm, cache_path=cache)
+    assert r1["tile_targets"] in (4, 8) and r1["grid"] in (1024, 2048, 4096) and r1["from_cache"] == 0
+    r2 = rrq.autotune(asm, cache_path=cache)
+    assert r2["from_cache"] == 1 and r2["tile_targets"] == r1["tile_targets"]
+    asm.assemble()
+    torch.cuda.synchronize()
+    gpu = {k: asm.out[k].cpu().numpy() for k in KERNELS}
+    _compare(surf, tg, gpu, asm.pair_off.cpu().numpy(), _sample(tg, 40, np.random.default_rng(8)))
