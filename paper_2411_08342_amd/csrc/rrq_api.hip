@@ -55,6 +55,8 @@ struct rrq_plan {
   // per order
   std::vector<int32_t> patches_h[kMaxQ + 1];
   int32_t* patches_d[kMaxQ + 1] = {};
+  int32_t* perm_d = nullptr;    // patches grouped by order (kOrders order)
+  BinOrders bin_orders{};
   OrderDev od[kMaxQ + 1] = {};
   std::vector<void*> const_bufs;
   double rho_far[kMaxQ + 1] = {};
@@ -90,7 +92,7 @@ static void plan_free(rrq_plan* p) {
   void* ptrs[] = {p->order_d, p->node_off_d, p->edge_off_d, p->node_xyz_d, p->node_nrm_d,
                   p->node_wt_d, p->frame_d, p->node_loc_d, p->edge_loc_d, p->edge_tan_d,
                   p->edge_coef_d, p->maps_d, p->map_off_d, p->tabs_d, p->tab_off_d,
-                  p->fit_ws_d};
+                  p->fit_ws_d, p->perm_d};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int q = 0; q <= kMaxQ; ++q)
@@ -134,6 +136,14 @@ static rrq_status upload_consts(rrq_plan* p, int q) {
   o.slp_ptr = (const int32_t*)b;
   if (!up(T.slp.data(), T.slp.size() * sizeof(Term), &b)) return RRQ_ERR_OOM;
   o.slp = (const Term*)b;
+  if (!up(T.lag_c.data(), T.lag_c.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.lag_c = (const double*)b;
+  for (int32_t v : T.mrg_ptr)
+    if (v < 0) return RRQ_ERR_DEVICE;   // term tables inconsistent (cannot happen)
+  if (!up(T.mrg_ptr.data(), T.mrg_ptr.size() * 4, &b)) return RRQ_ERR_OOM;
+  o.mrg_ptr = (const int32_t*)b;
+  if (!up(T.mrg.data(), T.mrg.size() * sizeof(Term2), &b)) return RRQ_ERR_OOM;
+  o.mrg = (const Term2*)b;
   return RRQ_OK;
 }
 
@@ -222,7 +232,11 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
     return RRQ_ERR_UNSUPPORTED;
   }
   p->tile = p->opt.tile_targets > 0 ? p->opt.tile_targets : 8;
-  for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = 2048;
+  if (p->opt.grid < 0 || p->opt.grid > (1 << 20)) {
+    delete p;
+    return RRQ_ERR_ARG;
+  }
+  for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = p->opt.grid > 0 ? p->opt.grid : 2048;
   p->P = s->npatch;
   p->N = s->nnode;
   p->E = s->nedge;
@@ -258,6 +272,17 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
   ok &= dalloc(&p->map_off_d, p->P + 1) == hipSuccess;
   ok &= dalloc(&p->tabs_d, tab_off[p->P]) == hipSuccess;
   ok &= dalloc(&p->tab_off_d, p->P + 1) == hipSuccess;
+  {
+    std::vector<int32_t> perm;
+    for (int qi = 0; qi < kNumOrders; ++qi) {
+      p->bin_orders.off[qi] = (int32_t)perm.size();
+      perm.insert(perm.end(), p->patches_h[kOrders[qi]].begin(), p->patches_h[kOrders[qi]].end());
+    }
+    p->bin_orders.off[kNumOrders] = (int32_t)perm.size();
+    ok &= dalloc(&p->perm_d, p->P) == hipSuccess;
+    if (ok) ok &= hipMemcpy(p->perm_d, perm.data(), perm.size() * 4, hipMemcpyHostToDevice) ==
+                  hipSuccess;
+  }
   p->fit_blocks = std::min(p->P, 512);
   p->fit_ws_per_block = maxws;
   ok &= dalloc(&p->fit_ws_d, (size_t)maxws * p->fit_blocks) == hipSuccess;
@@ -335,9 +360,10 @@ static TargetsDev tdev(const rrq_targets* tg) {
 }
 
 // workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
-// start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4
+// start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders] u64 |
+// sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4
 struct WsLayout {
-  size_t owner, counters, cnt, fill, start, tstart, ntiles, sorted, tiles, total;
+  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P) {
@@ -351,6 +377,7 @@ static WsLayout ws_layout(int64_t nnz, int P) {
   w.start = o; o = al(o + (size_t)(P + 1) * 8);
   w.tstart = o; o = al(o + (size_t)(P + 1) * 8);
   w.ntiles = o; o = al(o + 8);
+  w.queue = o; o = al(o + 8 * (2 * kNumOrders + 1));
   w.sorted = o; o = al(o + n * 8);
   w.tiles = o; o = al(o + (n / 4 + (size_t)P + 1) * 16);
   w.total = o;
@@ -425,8 +452,10 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
     int64_t* ntiles = (int64_t*)(wb + wl.ntiles);
     int64_t* sorted = (int64_t*)(wb + wl.sorted);
     int4* tiles = (int4*)(wb + wl.tiles);
-    if (launch_binning(td, p->P, tile, cnt, fill, start, tstart, ntiles, sorted, tiles, st) !=
-        hipSuccess)
+    int64_t* qtile = (int64_t*)(wb + wl.queue);
+    unsigned long long* qctr = (unsigned long long*)(wb + wl.queue + 8 * (kNumOrders + 1));
+    if (launch_binning(td, p->P, tile, p->perm_d, p->bin_orders, cnt, fill, start, tstart,
+                       ntiles, sorted, tiles, qtile, qctr, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
     for (int qi = 0; qi < kNumOrders; ++qi) {
       const int q = kOrders[qi];
@@ -435,8 +464,8 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
       int T = tile;
       while (T > 4 && !tile_supported(q, T)) T /= 2;
       if (!tile_supported(q, T)) return RRQ_ERR_UNSUPPORTED;
-      if (launch_pair_tile(q, T, p->grid[q], pd, p->od[q], td, ao, so, tiles, ntiles, sorted,
-                           st) != hipSuccess)
+      if (launch_pair_tile(q, T, p->grid[q], pd, p->od[q], td, ao, so, tiles, qtile + qi,
+                           qctr + qi, sorted, st) != hipSuccess)
         return RRQ_ERR_DEVICE;
     }
   }

@@ -9,16 +9,22 @@ namespace rrq {
 
 constexpr int BNT = 256;
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int kWavePanels = 64;
+// panel capacity per wave: enough for every level down to kMaxLevel at the order's rho_far
+__host__ __device__ constexpr int wave_panel_cap(int q) {
+  return q <= 4 ? 320 : (q <= 5 ? 224 : (q <= 6 ? 144 : 112));
+}
 
 // ---------------------------------------------------------------------------------------
-// binning: count pairs per patch, scan, scatter pair indices by patch, emit tiles
+// binning: count pairs per patch, scan in order-grouped patch order, scatter pair indices by
+// patch, emit tiles.  Tiles of one order are contiguous, [qtile[qi], qtile[qi+1]), and each
+// order's kernel takes them from its own queue counter qctr[qi] (zeroed here).
 // ---------------------------------------------------------------------------------------
-__global__ void k_bin_clear(int32_t* cnt, int32_t* fill, int P) {
+__global__ void k_bin_clear(int32_t* cnt, int32_t* fill, int P, unsigned long long* qctr) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
     cnt[i] = 0;
     fill[i] = 0;
   }
+  if (blockIdx.x == 0 && threadIdx.x < kNumOrders) qctr[threadIdx.x] = 0;
 }
 
 __global__ void k_bin_count(TargetsDev tg, int32_t* cnt) {
@@ -27,18 +33,21 @@ __global__ void k_bin_count(TargetsDev tg, int32_t* cnt) {
     atomicAdd(&cnt[tg.near_patch[k]], 1);
 }
 
-// exclusive scans of cnt and of ceil(cnt / tile) over patches (one workgroup)
-__global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, int P, int tile,
+// exclusive scans of cnt and of ceil(cnt / tile) over patches taken in the order perm
+// (patches grouped by order), one workgroup
+__global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, const int32_t* perm,
+                                                   BinOrders bo, int P, int tile,
                                                    int64_t* start, int64_t* tstart,
-                                                   int64_t* ntiles) {
+                                                   int64_t* ntiles, int64_t* qtile) {
   __shared__ int64_t s1[1024], s2[1024];
   __shared__ int64_t c1, c2;
   if (threadIdx.x == 0) { c1 = 0; c2 = 0; }
   __syncthreads();
   for (int base = 0; base < P; base += 1024) {
     const int i = base + threadIdx.x;
-    const int64_t a = i < P ? cnt[i] : 0;
-    const int64_t b = i < P ? (cnt[i] + tile - 1) / tile : 0;
+    const int pp = i < P ? perm[i] : 0;
+    const int64_t a = i < P ? cnt[pp] : 0;
+    const int64_t b = i < P ? (cnt[pp] + tile - 1) / tile : 0;
     s1[threadIdx.x] = a;
     s2[threadIdx.x] = b;
     __syncthreads();
@@ -51,17 +60,19 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, int P, in
       __syncthreads();
     }
     if (i < P) {
-      start[i] = c1 + s1[threadIdx.x] - a;
-      tstart[i] = c2 + s2[threadIdx.x] - b;
+      start[pp] = c1 + s1[threadIdx.x] - a;
+      tstart[pp] = c2 + s2[threadIdx.x] - b;
+      for (int qi = 0; qi < kNumOrders; ++qi)
+        if (bo.off[qi] == i) qtile[qi] = c2 + s2[threadIdx.x] - b;
     }
     __syncthreads();
     if (threadIdx.x == 1023) { c1 += s1[1023]; c2 += s2[1023]; }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    start[P] = c1;
-    tstart[P] = c2;
     *ntiles = c2;
+    for (int qi = 0; qi <= kNumOrders; ++qi)
+      if (bo.off[qi] >= P) qtile[qi] = c2;
   }
 }
 
@@ -91,19 +102,130 @@ __global__ void k_bin_tiles(const int32_t* cnt, int P, int tile, const int64_t* 
   }
 }
 
-hipError_t launch_binning(const TargetsDev& tg, int P, int tile, int32_t* cnt, int32_t* fill,
-                          int64_t* start, int64_t* tstart, int64_t* ntiles, int64_t* sorted,
-                          int4* tiles, hipStream_t st) {
+hipError_t launch_binning(const TargetsDev& tg, int P, int tile, const int32_t* perm,
+                          const BinOrders& bo, int32_t* cnt, int32_t* fill, int64_t* start,
+                          int64_t* tstart, int64_t* ntiles, int64_t* sorted, int4* tiles,
+                          int64_t* qtile, unsigned long long* qctr, hipStream_t st) {
   const int gp = (P + 255) / 256;
   int64_t gk = (tg.nnz + 255) / 256;
   if (gk < 1) gk = 1;
   const unsigned gkk = (unsigned)(gk < 65535 ? gk : 65535);
-  hipLaunchKernelGGL(k_bin_clear, dim3(gp), dim3(256), 0, st, cnt, fill, P);
+  hipLaunchKernelGGL(k_bin_clear, dim3(gp), dim3(256), 0, st, cnt, fill, P, qctr);
   hipLaunchKernelGGL(k_bin_count, dim3(gkk), dim3(256), 0, st, tg, cnt);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, cnt, P, tile, start, tstart, ntiles);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, cnt, perm, bo, P, tile, start,
+                     tstart, ntiles, qtile);
   hipLaunchKernelGGL(k_bin_scatter, dim3(gkk), dim3(256), 0, st, tg, start, fill, sorted);
   hipLaunchKernelGGL(k_bin_tiles, dim3(gp), dim3(256), 0, st, cnt, P, tile, start, tstart, tiles);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// wave-collective helpers
+// ---------------------------------------------------------------------------------------
+
+// Real-parameter Legendre series sum_k coef[3k + c] P_k(t) and its derivative, c = 0..2.
+__device__ __forceinline__ void leg3r(const double* coef, int n, double t, double* r, double* dr) {
+  double p0 = 0.0, p1 = 1.0, d0 = 0.0, d1 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    r[c] = coef[c];
+    dr[c] = 0.0;
+  }
+  for (int k = 0; k < n - 1; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * t * p1 - (double)k * p0) / (k + 1);
+    const double d2 = d0 + (2.0 * k + 1.0) * p1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    for (int c = 0; c < 3; ++c) {
+      const double ck = coef[(k + 1) * 3 + c];
+      r[c] += ck * p1;
+      dr[c] += ck * d1;
+    }
+  }
+}
+
+// Sum over the 64 lanes of x[v], v = 0..15, returned in lane l for v = (l >> 2) & 15
+// (a reduce-scatter: 17 exchanges instead of 16 full reductions).  x is overwritten.
+__device__ __forceinline__ double reduce_scatter16(double* x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int w = 8, o = 32; w >= 1; w >>= 1, o >>= 1) {
+    const bool hi = lane & o;
+#pragma unroll
+    for (int j = 0; j < w; ++j) {
+      const double send = hi ? x[j] : x[w + j];
+      const double keep = hi ? x[w + j] : x[j];
+      x[j] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  double v = x[0];
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
+constexpr int kMaxLevel = 52;   // deepest dyadic level that still splits (panel width 2^-51)
+
+// Dyadic panels of [-1, 1] graded toward t0 = a + i b: a panel of half-width h and centre c
+// is split while (t0 - c) / h lies inside the Bernstein ellipse of radius rho (that is,
+// while its Bernstein radius is below rho).  A child's ellipse lies inside its parent's, so
+// the split panels of level L form one index range [s_L, e_L], computed by lane L in closed
+// form; the leaves of level L are the children of level L-1's range outside [s_L, e_L].
+// Writes the leaves (lo, hi) to wpan (capacity cap) and returns their count; *over is set
+// when panels were dropped.  Wave-collective.
+__device__ int wave_graded_panels(double a, double b, double rho, double* wpan, int cap,
+                                  bool* over) {
+  const int lane = threadIdx.x & 63;
+  const double A = 0.5 * (rho + 1.0 / rho), B = 0.5 * (rho - 1.0 / rho);
+  const int L = lane;
+  int64_t s = 0, e = -1;
+  double h = ldexp(1.0, -L);
+  if (L < kMaxLevel) {
+    const double y = b / h;
+    if (y < B) {
+      const double X = A * sqrt(fmax(0.0, 1.0 - (y / B) * (y / B)));
+      const double lo = (a + 1.0 - h * X) / (2.0 * h) - 0.5;
+      const double hi = (a + 1.0 + h * X) / (2.0 * h) - 0.5;
+      const double js = fmax(floor(lo) + 1.0, 0.0);
+      const double je = fmin(ceil(hi) - 1.0, ldexp(1.0, L) - 1.0);
+      if (js <= je) { s = (int64_t)js; e = (int64_t)je; }
+    }
+  }
+  // levels are alive up to the first one with no split
+  const unsigned long long split = __ballot(s <= e);
+  const int lz = __builtin_ctzll(~split);        // first level with no split (< kMaxLevel)
+  const int64_t ps = __shfl(s, lane > 0 ? lane - 1 : 0, 64);
+  const int64_t pe = __shfl(e, lane > 0 ? lane - 1 : 0, 64);
+  int64_t l0 = 0, l1 = -1, r0 = 0, r1 = -1;      // leaf index ranges of this level
+  if (L == 0) {
+    if (lz == 0) { l0 = 0; l1 = 0; }
+  } else if (L <= lz) {
+    const int64_t c0 = 2 * ps, c1 = 2 * pe + 1;   // children of level L-1's split range
+    if (L == lz) { l0 = c0; l1 = c1; }
+    else {
+      const int64_t ss = s > c0 ? s : c0, ee = e < c1 ? e : c1;
+      if (ss <= ee) {
+        l0 = c0; l1 = ss - 1;
+        r0 = ee + 1; r1 = c1;
+      } else {
+        l0 = c0; l1 = c1;
+      }
+    }
+  }
+  const int cnt = (int)((l1 - l0 + 1) + (r1 - r0 + 1));
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  const int total = __shfl(incl, 63, 64);
+  int pos = incl - cnt;
+  const double w = 2.0 * h;
+  for (int64_t j = l0; j <= l1; ++j, ++pos)
+    if (pos < cap) { wpan[2 * pos] = -1.0 + w * (double)j; wpan[2 * pos + 1] = -1.0 + w * (double)(j + 1); }
+  for (int64_t j = r0; j <= r1; ++j, ++pos)
+    if (pos < cap) { wpan[2 * pos] = -1.0 + w * (double)j; wpan[2 * pos + 1] = -1.0 + w * (double)(j + 1); }
+  *over = total > cap;
+  return total < cap ? total : cap;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -122,8 +244,9 @@ struct TileLds {
   static constexpr int o_t0 = o_u + 3 * T;                 // [T][4][2]
   static constexpr int o_om = o_t0 + 8 * T;                // [T][4]: Omega_0, Omega_vec
   static constexpr int o_dom = o_om + 4 * T;               // [T][4]
-  static constexpr int o_om0e = o_dom + 4 * T;             // [T][4]: Omega_0 of near edges
-  static constexpr int o_td = o_om0e + 4 * T;              // [T][4][PT][8] (aliased by rows)
+  static constexpr int o_om0e = o_dom + 4 * T;             // [T][4]: Omega_0 per edge
+  static constexpr int o_part = o_om0e + 4 * T;            // [T][4][8]: edge partial sums
+  static constexpr int o_td = o_part + 32 * T;             // [T][4][PT][8] (aliased by rows)
   static constexpr int n_td = T * 4 * PT * 8;
   static constexpr int o_lam = o_td + n_td;                // [T][4][PT][2]
   static constexpr int n_lam = T * 4 * PT * 2;
@@ -133,25 +256,35 @@ struct TileLds {
   static constexpr int o_vq = o_td + n_scrA;               // [T][NJK][18]
   static constexpr int o_rt = o_vq + T * NJK * 18;         // [T][NR] cplx
   static constexpr int o_gs = o_rt + 2 * T * NR;           // [T][NR] cplx
-  static constexpr int o_pan = o_gs + 2 * T * NR;          // [4 waves][kWavePanels][2]
-  static constexpr int o_red = o_pan + 4 * kWavePanels * 2;
-  static constexpr int n_dbl = o_red + 8;
+  static constexpr int NPAN = wave_panel_cap(Q);
+  static constexpr int o_pan = o_gs + 2 * T * NR;          // [4 waves][NPAN][2]
+  static constexpr int o_red = o_pan + 4 * NPAN * 2;
+  static constexpr int o_cst = o_red + 8;                  // gl_t, gl_w, lag_c [PT] each
+  static constexpr int n_dbl = o_cst + 3 * PT;
   // ints
   static constexpr int i_near = 0;                         // [T][4]
   static constexpr int i_self = i_near + 4 * T;
-  static constexpr int i_npan = i_self + T;                // [4 waves]
-  static constexpr int n_int = i_npan + 4;
+  static constexpr int n_int = i_self + T;
   static constexpr size_t bytes = (size_t)n_dbl * 8 + (size_t)n_int * 4 + 64;
 };
 
+// Persistent workgroups take tiles of this order from a queue, so that the workgroups in
+// flight work on a narrow window of consecutive tiles (tiles of one patch are consecutive)
+// and the patch's maps and edge tables are served from L2.
 template <int Q, int T>
-__global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
+__global__ __launch_bounds__(BNT)
+__attribute__((amdgpu_waves_per_eu(TileLds<Q, T>::bytes <= 80 * 1024 ? 2 : 1)))
+void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
                                                    AssembleOut out, SolveOpts so,
-                                                   const int4* tiles, const int64_t* ntiles_p,
+                                                   const int4* tiles, const int64_t* qtile,
+                                                   unsigned long long* qctr,
                                                    const int64_t* sorted) {
   using L = TileLds<Q, T>;
   constexpr int PT = L::PT, NP = L::NP, NJK = L::NJK, NR = L::NR, Q2 = Q * Q;
+  constexpr int PTP = PT <= 8 ? 8 : (PT <= 16 ? 16 : 32);   // lanes per (target, edge)
+  constexpr int NB8 = (PT + 7) / 8;                          // blocks of 8 edge nodes
   extern __shared__ double smem[];
+  __shared__ long long s_ti;
   double* fr = smem + L::o_fr;
   double* eloc = smem + L::o_eloc;
   double* etan = smem + L::o_etan;
@@ -163,6 +296,7 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
   double* som = smem + L::o_om;
   double* sdom = smem + L::o_dom;
   double* som0e = smem + L::o_om0e;
+  double* part = smem + L::o_part;
   double* td = smem + L::o_td;
   double* lam = smem + L::o_lam;
   double* rows = smem + L::o_rows;
@@ -170,14 +304,27 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
   cplx* Rt = (cplx*)(smem + L::o_rt);
   cplx* gS = (cplx*)(smem + L::o_gs);
   double* pan = smem + L::o_pan;
+  double* cgl_t = smem + L::o_cst;
+  double* cgl_w = cgl_t + PT;
+  double* clag = cgl_w + PT;
   int* ints = (int*)(smem + L::n_dbl);
   int* snear = ints + L::i_near;
   int* sself = ints + L::i_self;
-  int* snpan = ints + L::i_npan;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t ntiles = *ntiles_p;
-  for (int64_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+  const int64_t tlo = qtile[0], thi = qtile[1];
+  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_max = 0;
+  if (tid < PT) {
+    cgl_t[tid] = od.gl_t[tid];
+    cgl_w[tid] = od.gl_w[tid];
+    clag[tid] = od.lag_c[tid];
+  }
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_ti = tlo + (long long)atomicAdd(qctr, 1ull);
+    __syncthreads();
+    const int64_t ti = s_ti;
+    if (ti >= thi) break;
     const int4 tile = tiles[ti];
     const int P = tile.x;
     if (pd.order[P] != Q) continue;
@@ -194,13 +341,12 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
         ecoef[i] = pd.edge_coef[c * pd.E + e0 + ei];
       }
       __syncthreads();
-      // ---- targets: local coordinates, u (nearest node, lowest index on ties)
-      if (tid < nt) {
-        const int t = tid;
+      // ---- targets (one wave each): local coordinates; u from the nearest node, lowest
+      // index on ties (wave argmin)
+      for (int t = wv; t < nt; t += BNT / 64) {
         const int64_t k = sorted[tile.y + sub + t];
         const int64_t g = out.owner[k];
         const int self = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
-        sself[t] = self;
         const double inv_s = 1.0 / fr[12];
         double dx[3], nv[3], xl[3], nl[3];
         for (int c = 0; c < 3; ++c) {
@@ -211,15 +357,11 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
           const double* ax = fr + 3 + 3 * a;
           xl[a] = (dx[0] * ax[0] + dx[1] * ax[1] + dx[2] * ax[2]) * inv_s;
           nl[a] = nv[0] * ax[0] + nv[1] * ax[1] + nv[2] * ax[2];
-          sx[t * 3 + a] = xl[a];
-          snu[t * 3 + a] = nl[a];
         }
-        if (self >= 0) {
-          for (int c = 0; c < 3; ++c) su[t * 3 + c] = nl[c];
-        } else {
-          double bd = 1e300;
-          int bi = 0;
-          for (int i = 0; i < Q2; ++i) {
+        double bd = 1e300;
+        int bi = 0x7fffffff;
+        if (self < 0) {
+          for (int i = lane; i < Q2; i += 64) {
             double d2 = 0;
             for (int c = 0; c < 3; ++c) {
               const double dd = xl[c] - pd.node_loc[c * pd.N + n0 + i];
@@ -227,17 +369,35 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
             }
             if (d2 < bd) { bd = d2; bi = i; }
           }
-          double dd = 0, nn[3];
-          for (int c = 0; c < 3; ++c) {
-            nn[c] = pd.node_loc[(3 + c) * pd.N + n0 + bi];
-            dd += (xl[c] - pd.node_loc[c * pd.N + n0 + bi]) * nn[c];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(bd, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob < bd || (ob == bd && oi < bi)) { bd = ob; bi = oi; }
           }
-          const double sg = dd >= 0.0 ? 1.0 : -1.0;
-          for (int c = 0; c < 3; ++c) su[t * 3 + c] = sg * nn[c];
+        }
+        if (lane == 0) {
+          sself[t] = self;
+          for (int a = 0; a < 3; ++a) {
+            sx[t * 3 + a] = xl[a];
+            snu[t * 3 + a] = nl[a];
+          }
+          if (self >= 0) {
+            for (int c = 0; c < 3; ++c) su[t * 3 + c] = nl[c];
+          } else {
+            double dd = 0, nn[3];
+            for (int c = 0; c < 3; ++c) {
+              nn[c] = pd.node_loc[(3 + c) * pd.N + n0 + bi];
+              dd += (xl[c] - pd.node_loc[c * pd.N + n0 + bi]) * nn[c];
+            }
+            const double sg = dd >= 0.0 ? 1.0 : -1.0;
+            for (int c = 0; c < 3; ++c) su[t * 3 + c] = sg * nn[c];
+          }
         }
       }
       __syncthreads();
-      // ---- Step 5: per (target, edge) classification and Newton root
+      // ---- Step 5: per (target, edge) classification and Newton root (wave 0); Step 4:
+      // target harmonics (wave 1) at the same time
       if (tid < 4 * nt) {
         const int t = tid >> 2, e = tid & 3;
         const double* cf = ecoef + e * PT * 3;
@@ -280,15 +440,18 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
           if (its > so.newton_maxit) its = so.newton_maxit;
           if (t0.im < 0) t0.im = -t0.im;
           if (conv && bernstein_rho(t0) <= so.rho_far) near = 1;
-          atomicAdd(&out.counters[1], (unsigned long long)its);
-          if (!conv) atomicAdd(&out.counters[2], 1ull);
-          atomicMax(&out.counters[4], (unsigned long long)its);
-          if (near) atomicAdd(&out.counters[0], 1ull);
+          c_iters += (unsigned long long)its;
+          if (!conv) ++c_fail;
+          if ((unsigned long long)its > c_max) c_max = its;
+          if (near) ++c_near;
         }
         snear[t * 4 + e] = near;
         st0[(t * 4 + e) * 2] = t0.re;
         st0[(t * 4 + e) * 2 + 1] = t0.im;
         som0e[t * 4 + e] = 0.0;
+      } else if (tid >= 64 && tid < 64 + nt) {
+        const int t = tid - 64;
+        solid_table<Q>(sx[t * 3 + 1], sx[t * 3 + 2], sx[t * 3 + 0], Rt + t * NR);
       }
       __syncthreads();
       // ---- Lagrange-basis moments of near edges on graded panels: one wave per near item
@@ -296,87 +459,89 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
         if (!snear[item]) continue;          // wave-uniform
         const int t = item >> 2, e = item & 3;
         const double a = st0[item * 2], b = st0[item * 2 + 1];
-        double* wpan = pan + wv * kWavePanels * 2;
-        if (lane == 0) {
-          double stk[64][3];
-          int sp = 0, np_ = 0;
-          stk[0][0] = -1.0; stk[0][1] = 1.0; stk[0][2] = 0; sp = 1;
-          while (sp > 0) {
-            --sp;
-            const double lo = stk[sp][0], hi = stk[sp][1];
-            const int lev = (int)stk[sp][2];
-            const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
-            const double rho = bernstein_rho(mk((a - c) / h, b / h));
-            if (lev >= 60 || rho >= so.rho_far || sp >= 62) {
-              if (np_ < kWavePanels) { wpan[np_ * 2] = lo; wpan[np_ * 2 + 1] = hi; ++np_; }
-              else atomicAdd(&out.counters[2], 1ull);
-            } else {
-              stk[sp][0] = c; stk[sp][1] = hi; stk[sp][2] = lev + 1; ++sp;
-              stk[sp][0] = lo; stk[sp][1] = c; stk[sp][2] = lev + 1; ++sp;
-            }
-          }
-          snpan[wv] = np_;
-        }
+        double* wpan = pan + wv * L::NPAN * 2;
+        bool over;
+        const int npan = wave_graded_panels(a, b, so.rho_far, wpan, L::NPAN, &over);
+        if (over && lane == 0) ++c_fail;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int npts = snpan[wv] * PT;
-        double l1acc = 0.0, l3acc = 0.0, om = 0.0;   // lane i < PT keeps lambda_i
+        const int npts = npan * PT;
+        double lacc[NB8];
+#pragma unroll
+        for (int bI = 0; bI < NB8; ++bI) lacc[bI] = 0.0;
+        double om = 0.0;
         for (int base = 0; base < npts; base += 64) {
           const int idx = base + lane;
           double w1p = 0.0, w3p = 0.0, tau = 3.0;
-          int hit = -2;
+          asm volatile("" ::: "memory");   // keep the node tables out of registers
           if (idx < npts) {
             const int pn = idx / PT, g = idx % PT;
             const double lo = wpan[pn * 2], hi = wpan[pn * 2 + 1];
             const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
-            tau = c + h * od.gl_t[g];
+            tau = c + h * cgl_t[g];
             const double K2 = (tau - a) * (tau - a) + b * b;
             const double K1 = 1.0 / sqrt(K2);
-            const double hw = h * od.gl_w[g];
-            double den = 0.0;
-            hit = -1;
-            for (int j = 0; j < PT; ++j) {
-              const double dtj = tau - od.gl_t[j];
-              if (dtj == 0.0) hit = j;
-              else den += od.bary[j] / dtj;
-            }
-            w1p = hit >= 0 ? hw * K1 : hw * K1 / den;
+            const double hw = h * cgl_w[g];
+            w1p = hw * K1;
             w3p = w1p / K2;
-            cplx r[3], dr[3];
-            leg3(ecoef + e * PT * 3, 3, PT, mk(tau, 0.0), r, dr);
-            const double rr[3] = {r[0].re, r[1].re, r[2].re};
-            const double ddd[3] = {dr[0].re, dr[1].re, dr[2].re};
-            om += hw * omega0_at(sx + t * 3, su + t * 3, rr, ddd);
+            double r[3], dr[3];
+            leg3r(ecoef + e * PT * 3, PT, tau, r, dr);
+            om += hw * omega0_at(sx + t * 3, su + t * 3, r, dr);
           }
-          for (int i = 0; i < PT; ++i) {
-            double li;
-            if (hit >= 0) li = hit == i ? 1.0 : 0.0;
-            else if (hit == -1) li = od.bary[i] / (tau - od.gl_t[i]);
-            else li = 0.0;
-            const double s1 = wave_sum(w1p * li);
-            const double s3 = wave_sum(w3p * li);
-            if (lane == i) { l1acc += s1; l3acc += s3; }
+          // Lagrange basis at tau in product form, l_i = c_i prod_{j != i} (tau - t_j), by
+          // prefix and suffix products, 8 nodes at a time
+          double pre = 1.0;                  // prod_{j < 8 bI} (tau - t_j)
+#pragma unroll
+          for (int bI = 0; bI < NB8; ++bI) {
+            const int i0 = bI * 8;
+            double suf = 1.0;                // prod_{j >= i0 + 8} (tau - t_j)
+            for (int j = i0 + 8; j < PT; ++j) suf *= tau - cgl_t[j];
+            double x[16];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              x[v] = pre;
+              if (i0 + v < PT) pre *= tau - cgl_t[i0 + v];
+            }
+#pragma unroll
+            for (int v = 7; v >= 0; --v) {
+              if (i0 + v < PT) {
+                const double l = x[v] * suf * clag[i0 + v];
+                suf *= tau - cgl_t[i0 + v];
+                x[v] = w1p * l;
+                x[8 + v] = w3p * l;
+              } else {
+                x[v] = 0.0;
+                x[8 + v] = 0.0;
+              }
+            }
+            lacc[bI] += reduce_scatter16(x);
           }
         }
         om = wave_sum(om);
-        if (lane < PT) {
-          lam[((t * 4 + e) * PT + lane) * 2] = l1acc;
-          lam[((t * 4 + e) * PT + lane) * 2 + 1] = l3acc;
+        if ((lane & 3) == 0) {
+          const int v = lane >> 2;
+#pragma unroll
+          for (int bI = 0; bI < NB8; ++bI) {
+            const int i = bI * 8 + (v & 7);
+            if (i < PT) lam[((t * 4 + e) * PT + i) * 2 + (v >> 3)] = lacc[bI];
+          }
         }
         if (lane == 0) som0e[item] = om;
         __builtin_amdgcn_wave_barrier();
       }
       __syncthreads();
-      // ---- effective weights per (target, edge, node) and the Omega sums per (target, edge)
-      if (tid < 4 * nt) {
-        const int t = tid >> 2, e = tid & 3;
-        const double* xl = sx + t * 3;
-        const double* nl = snu + t * 3;
-        const int near = snear[tid];
-        const double a = st0[tid * 2], b = st0[tid * 2 + 1];
-        double om0 = near ? som0e[tid] : 0.0;
-        double ov[3] = {0, 0, 0}, dv[3] = {0, 0, 0}, dom0 = 0.0;
-        for (int i = 0; i < PT; ++i) {
+      // ---- effective weights per (target, edge, node), PTP lanes per (target, edge), and
+      // the Omega sums of each (target, edge) by a segmented lane reduction
+      for (int idx = tid; idx < T * 4 * PTP; idx += BNT) {
+        const int te = idx / PTP, i = idx % PTP;
+        const int t = te >> 2, e = te & 3;
+        double om0 = 0.0, ov[3] = {0, 0, 0}, dv[3] = {0, 0, 0}, dom0 = 0.0;
+        const bool act = t < nt && i < PT;
+        const int near = t < nt ? snear[te] : 0;
+        if (act) {
+          const double* xl = sx + t * 3;
+          const double* nl = snu + t * 3;
+          const double a = st0[te * 2], b = st0[te * 2 + 1];
           const int ei = e * PT + i;
           double d[3];
           for (int c = 0; c < 3; ++c) d[c] = xl[c] - eloc[ei * 3 + c];
@@ -384,17 +549,17 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
           const double R = sqrt(R2);
           double w1, w3;
           if (near) {
-            const double ta = od.gl_t[i] - a;
+            const double ta = cgl_t[i] - a;
             const double q1 = sqrt(ta * ta + b * b) / R;
-            w1 = lam[(tid * PT + i) * 2] * q1;
-            w3 = lam[(tid * PT + i) * 2 + 1] * q1 * q1 * q1;
+            w1 = lam[(te * PT + i) * 2] * q1;
+            w3 = lam[(te * PT + i) * 2 + 1] * q1 * q1 * q1;
           } else {
-            w1 = od.gl_w[i] / R;
-            w3 = od.gl_w[i] / (R2 * R);
-            om0 += od.gl_w[i] * omega0_at(xl, su + t * 3, eloc + ei * 3, etan + ei * 3);
+            w1 = cgl_w[i] / R;
+            w3 = cgl_w[i] / (R2 * R);
+            om0 = cgl_w[i] * omega0_at(xl, su + t * 3, eloc + ei * 3, etan + ei * 3);
           }
           const double dn = d[0] * nl[0] + d[1] * nl[1] + d[2] * nl[2];
-          double* o = td + (tid * PT + i) * 8;
+          double* o = td + (te * PT + i) * 8;
           o[0] = w1;
           for (int c = 0; c < 3; ++c) {
             o[1 + c] = d[c];
@@ -402,35 +567,58 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
           }
           const double* rp = etan + ei * 3;
           for (int c = 0; c < 3; ++c) {
-            ov[c] -= w1 * rp[c];
-            dv[c] += w3 * dn * rp[c];
+            ov[c] = -w1 * rp[c];
+            dv[c] = w3 * dn * rp[c];
           }
           const double cx = rp[1] * d[2] - rp[2] * d[1];
           const double cy = rp[2] * d[0] - rp[0] * d[2];
           const double cz = rp[0] * d[1] - rp[1] * d[0];
-          dom0 -= w3 * (cx * nl[0] + cy * nl[1] + cz * nl[2]);
+          dom0 = -w3 * (cx * nl[0] + cy * nl[1] + cz * nl[2]);
         }
-        // per-(t,e) partials into lambda slots (dead now): reuse som0e for Omega_0
-        som0e[tid] = om0;
-        double* pp = lam + tid * PT * 2;   // PT*2 >= 7
-        pp[0] = ov[0]; pp[1] = ov[1]; pp[2] = ov[2];
-        pp[3] = dv[0]; pp[4] = dv[1]; pp[5] = dv[2]; pp[6] = dom0;
+#pragma unroll
+        for (int o = PTP / 2; o > 0; o >>= 1) {
+          om0 += __shfl_xor(om0, o, 64);
+          dom0 += __shfl_xor(dom0, o, 64);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            ov[c] += __shfl_xor(ov[c], o, 64);
+            dv[c] += __shfl_xor(dv[c], o, 64);
+          }
+        }
+        if (i == 0 && t < nt) {
+          double* pp = part + te * 8;
+          pp[0] = near ? som0e[te] : om0;
+          pp[1] = ov[0]; pp[2] = ov[1]; pp[3] = ov[2];
+          pp[4] = dv[0]; pp[5] = dv[1]; pp[6] = dv[2]; pp[7] = dom0;
+        }
       }
       __syncthreads();
       if (tid < nt) {
         const int t = tid;
         double o[4] = {0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
         for (int e = 0; e < 4; ++e) {
-          const double* pp = lam + (t * 4 + e) * PT * 2;
-          o[0] += som0e[t * 4 + e];
-          o[1] += pp[0]; o[2] += pp[1]; o[3] += pp[2];
-          d[1] += pp[3]; d[2] += pp[4]; d[3] += pp[5]; d[0] += pp[6];
+          const double* pp = part + (t * 4 + e) * 8;
+          o[0] += pp[0];
+          o[1] += pp[1]; o[2] += pp[2]; o[3] += pp[3];
+          d[1] += pp[4]; d[2] += pp[5]; d[3] += pp[6]; d[0] += pp[7];
         }
         for (int c = 0; c < 4; ++c) { som[t * 4 + c] = o[c]; sdom[t * 4 + c] = d[c]; }
       }
-      // ---- Step 6: contraction with the edge tables, items (j,k) x target
+      // ---- Step 6: contraction with the edge tables, items (j,k) x target; then the normal
+      // derivatives nu'.grad S^{ab} at the targets, items (target, a, b)
       const double* tb = pd.tabs + pd.tab_off[P];
-      for (int idx = tid; idx < NJK * T; idx += BNT) {
+      for (int idx = tid; idx < NJK * T + nt * NR; idx += BNT) {
+        if (idx >= NJK * T) {
+          const int it = idx - NJK * T;
+          const int t = it / NR, r = it % NR;
+          int a = 0;
+          while (tri(a + 1, 0) <= r) ++a;
+          const int b = r - tri(a, 0);
+          cplx acc = mk(0, 0);
+          for (int c = 0; c < 3; ++c) acc = acc + snu[t * 3 + c] * dS(Rt + t * NR, a, b, c);
+          gS[it] = acc;
+          continue;
+        }
         const int n = idx / T, t = idx % T;
         if (t >= nt) continue;
         double V0 = 0, V1 = 0;
@@ -473,21 +661,6 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
           o[10 + 2 * c] = Dr[c]; o[11 + 2 * c] = Di[c];
         }
       }
-      // ---- Step 4: target harmonics
-      if (tid >= BNT - nt) {
-        const int t = BNT - 1 - tid;
-        solid_table<Q>(sx[t * 3 + 1], sx[t * 3 + 2], sx[t * 3 + 0], Rt + t * NR);
-      }
-      __syncthreads();
-      for (int idx = tid; idx < nt * NR; idx += BNT) {
-        const int t = idx / NR, r = idx % NR;
-        int a = 0;
-        while (tri(a + 1, 0) <= r) ++a;
-        const int b = r - tri(a, 0);
-        cplx acc = mk(0, 0);
-        for (int c = 0; c < 3; ++c) acc = acc + snu[t * 3 + c] * dS(Rt + t * NR, a, b, c);
-        gS[idx] = acc;
-      }
       __syncthreads();
       // ---- Steps 7-8: translation and rows, items (target, l, m)
       for (int idx = tid; idx < nt * NP; idx += BNT) {
@@ -500,38 +673,33 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
         const double* VQ = vq + t * NJK * 18;
         cplx Ia[4] = {mk(0, 0), mk(0, 0), mk(0, 0), mk(0, 0)};
         cplx dIa[4] = {mk(0, 0), mk(0, 0), mk(0, 0), mk(0, 0)};
-        for (int it = od.dlp_ptr[lm]; it < od.dlp_ptr[lm + 1]; ++it) {
-          const Term tm = od.dlp[it];
+        cplx sl = mk(0, 0);
+        // one pass over the (j, k) terms of this (l, m): single-layer sum (weights D_{j,l})
+        // and double-layer sums (weights C_{j,l}, zero for j = 1)
+        const int m_end = od.mrg_ptr[lm + 1];
+        for (int it = od.mrg_ptr[lm]; it < m_end; ++it) {
+          const Term2 tm = od.mrg[it];
           const cplx s_ = rget(R, tm.a, tm.b);
-          cplx gs;
-          if (tm.b >= 0) gs = G[tri(tm.a, tm.b)];
-          else {
-            const cplx g = G[tri(tm.a, -tm.b)];
-            gs = ((-tm.b) & 1) ? mk(-g.re, g.im) : mk(g.re, -g.im);
-          }
+          const cplx cs = tm.cD * s_;
+          const cplx cg = tm.cD * rget(G, tm.a, tm.b);
           const double* q = VQ + tm.n * 18;
+          cplx V = mk(q[0], q[1]);
+          if (tm.neg) V = conjg(V);
+          sl = sl + tm.cS * (V * s_);
           for (int c = 0; c < 4; ++c) {
             cplx X = mk(q[2 + 2 * c], q[3 + 2 * c]), dX = mk(q[10 + 2 * c], q[11 + 2 * c]);
             if (tm.neg) { X = conjg(X); dX = conjg(dX); }
-            Ia[c] = Ia[c] + tm.coef * (X * s_);
-            dIa[c] = dIa[c] + tm.coef * (dX * s_ + X * gs);
+            Ia[c] = Ia[c] + X * cs;
+            dIa[c] = dIa[c] + (dX * cs + X * cg);
           }
         }
-        cplx sl = mk(0, 0);
-        for (int it = od.slp_ptr[lm]; it < od.slp_ptr[lm + 1]; ++it) {
-          const Term tm = od.slp[it];
-          const double* q = VQ + tm.n * 18;
-          cplx X = mk(q[0], q[1]);
-          if (tm.neg) X = conjg(X);
-          sl = sl + tm.coef * (X * rget(R, tm.a, tm.b));
-        }
         const double* nu = snu + t * 3;
+        // gradient of S^{lm} and its normal derivative: nu'.grad (d_a S^{lm}) is the same
+        // ladder combination applied to the table nu'.grad S^{ab}
         cplx g[3], hn[3];
         for (int a = 0; a < 3; ++a) {
           g[a] = dS(R, l, m, a);
-          cplx acc = mk(0, 0);
-          for (int b = 0; b < 3; ++b) acc = acc + nu[b] * d2S(R, l, m, a, b);
-          hn[a] = acc;
+          hn[a] = dS(G, l, m, a);
         }
         const double o0 = -som[t * 4], o1 = som[t * 4 + 1], o2 = som[t * 4 + 2], o3 = som[t * 4 + 3];
         const double p0 = -sdom[t * 4], p1 = sdom[t * 4 + 1], p2 = sdom[t * 4 + 2], p3 = sdom[t * 4 + 3];
@@ -654,6 +822,10 @@ __global__ __launch_bounds__(BNT) void k_pair_tile(PlanDev pd, OrderDev od, Targ
       }
     }
   }
+  if (c_iters) atomicAdd(&out.counters[1], c_iters);
+  if (c_fail) atomicAdd(&out.counters[2], c_fail);
+  if (c_max) atomicMax(&out.counters[4], c_max);
+  if (c_near) atomicAdd(&out.counters[0], c_near);
 }
 
 #define RRQ_TILE_CASES(X) X(4, 4) X(4, 8) X(5, 4) X(5, 8) X(6, 4) X(6, 8) X(8, 4) X(8, 8) X(10, 4)
@@ -671,8 +843,8 @@ int tile_supported(int q, int T) { return tile_lds_bytes(q, T) > 0 && tile_lds_b
 
 hipError_t launch_pair_tile(int q, int T, int grid, const PlanDev& pd, const OrderDev& od,
                             const TargetsDev& tg, const AssembleOut& out, const SolveOpts& so,
-                            const int4* tiles, const int64_t* ntiles, const int64_t* sorted,
-                            hipStream_t st) {
+                            const int4* tiles, const int64_t* qtile, unsigned long long* qctr,
+                            const int64_t* sorted, hipStream_t st) {
   if (tg.nnz <= 0) return hipSuccess;
   switch (q * 100 + T) {
 #define X(Q, TT)                                                                               \
@@ -686,7 +858,7 @@ hipError_t launch_pair_tile(int q, int T, int grid, const PlanDev& pd, const Ord
       attr = true;                                                                            \
     }                                                                                         \
     hipLaunchKernelGGL((k_pair_tile<Q, TT>), dim3(grid), dim3(BNT), lds, st, pd, od, tg, out, \
-                       so, tiles, ntiles, sorted);                                            \
+                       so, tiles, qtile, qctr, sorted);                                            \
     break;                                                                                    \
   }
     RRQ_TILE_CASES(X)

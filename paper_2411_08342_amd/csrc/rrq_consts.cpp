@@ -122,6 +122,14 @@ OrderTables build_order_tables(int q, int pt) {
     T.bary[i] = (double)((i & 1 ? -1.0L : 1.0L) * sqrtl((1 - ti * ti) * (long double)T.gl_w[i]));
   }
 
+  T.lag_c.assign(pt, 0.0);
+  for (int i = 0; i < pt; ++i) {
+    long double pr = 1;
+    for (int j = 0; j < pt; ++j)
+      if (j != i) pr *= (long double)T.gl_t[i] - (long double)T.gl_t[j];
+    T.lag_c[i] = (double)(1.0L / pr);
+  }
+
   // translation terms, grouped by basis function (l, m), 1 <= m <= l <= q
   T.dlp_ptr.assign(1, 0);
   T.slp_ptr.assign(1, 0);
@@ -151,6 +159,31 @@ OrderTables build_order_tables(int q, int pt) {
             (int32_t)(pass == 0 ? T.dlp.size() : T.slp.size()));
       }
     }
+  // merged lists: the double-layer terms are the single-layer terms with j >= 2, in the same
+  // (j, k) order
+  T.mrg_ptr.assign(1, 0);
+  for (int lm = 0; lm < T.np; ++lm) {
+    int d = T.dlp_ptr[lm];
+    for (int s = T.slp_ptr[lm]; s < T.slp_ptr[lm + 1]; ++s) {
+      const Term& ts = T.slp[s];
+      Term2 t2;
+      t2.n = ts.n;
+      t2.a = ts.a;
+      t2.b = ts.b;
+      t2.neg = ts.neg;
+      t2.pad = 0;
+      t2.cS = ts.coef;
+      t2.cD = 0.0;
+      if (d < T.dlp_ptr[lm + 1] && T.dlp[d].n == ts.n && T.dlp[d].a == ts.a &&
+          T.dlp[d].b == ts.b && T.dlp[d].neg == ts.neg) {
+        t2.cD = T.dlp[d].coef;
+        ++d;
+      }
+      T.mrg.push_back(t2);
+    }
+    T.mrg_ptr.push_back((int32_t)T.mrg.size());
+    if (d != T.dlp_ptr[lm + 1]) T.mrg_ptr.back() = -1;   // not a subset: flagged for the caller
+  }
   return T;
 }
 

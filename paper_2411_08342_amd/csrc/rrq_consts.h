@@ -23,6 +23,17 @@ struct Term {
   double coef;    // (weight C_{j,l} or D_{j,l}) * T_{jk,lm} * (-1)^{|k|} if k < 0
 };
 
+// one term of the merged translation sum over the (j, k) index set of the single-layer sum;
+// the double-layer weight cD is zero for j = 1
+struct Term2 {
+  int32_t n;
+  int16_t a, b;
+  int32_t neg;
+  int32_t pad;
+  double cD;      // C_{j,l} T_{jk,lm} (sign for k < 0 included)
+  double cS;      // D_{j,l} T_{jk,lm} (sign for k < 0 included)
+};
+
 struct OrderTables {
   int q, pt, np, njk;
   std::vector<double> gl_t, gl_w;     // ptilde-point GL rule on [-1, 1]
@@ -32,8 +43,11 @@ struct OrderTables {
   std::vector<double> DP;             // [pt][pt]: DP[i*pt + k] = P_k'(t_i)
   std::vector<double> lag_m1;         // l_i(-1)
   std::vector<double> bary;           // barycentric weights (-1)^i sqrt((1 - t_i^2) w_i)
+  std::vector<double> lag_c;          // 1 / prod_{j != i} (t_i - t_j) (product-form Lagrange)
   std::vector<int32_t> dlp_ptr, slp_ptr;   // [np+1]
   std::vector<Term> dlp, slp;
+  std::vector<int32_t> mrg_ptr;        // [np+1]
+  std::vector<Term2> mrg;
 };
 
 void gauss_legendre_ld(int n, std::vector<double>& t, std::vector<double>& w);

@@ -20,10 +20,13 @@ struct OrderDev {
   const double* DP;         // Legendre derivatives at the GL nodes
   const double* lag_m1;
   const double* bary;       // barycentric weights of the ptilde GL nodes
+  const double* lag_c;      // product-form Lagrange normalisation 1 / prod_{j != i}(t_i - t_j)
   const int32_t* dlp_ptr;
   const Term* dlp;
   const int32_t* slp_ptr;
   const Term* slp;
+  const int32_t* mrg_ptr;
+  const Term2* mrg;
 };
 
 // per-patch data layout constants
@@ -91,13 +94,19 @@ hipError_t launch_apply(const PlanDev& pd, const TargetsDev& tg, const double* c
                         uint32_t kmask, const int64_t* pair_off, const int64_t* owner,
                         const double* density, double* const* pot, hipStream_t st);
 
-hipError_t launch_binning(const TargetsDev& tg, int P, int tile, int32_t* cnt, int32_t* fill,
-                          int64_t* start, int64_t* tstart, int64_t* ntiles, int64_t* sorted,
-                          int4* tiles, hipStream_t st);
+// first position of each order's patches in the order-grouped patch permutation; off[n] = P
+struct BinOrders {
+  int32_t off[kNumOrders + 1];
+};
+
+hipError_t launch_binning(const TargetsDev& tg, int P, int tile, const int32_t* perm,
+                          const BinOrders& bo, int32_t* cnt, int32_t* fill, int64_t* start,
+                          int64_t* tstart, int64_t* ntiles, int64_t* sorted, int4* tiles,
+                          int64_t* qtile, unsigned long long* qctr, hipStream_t st);
 hipError_t launch_pair_tile(int q, int T, int grid, const PlanDev& pd, const OrderDev& od,
                             const TargetsDev& tg, const AssembleOut& out, const SolveOpts& so,
-                            const int4* tiles, const int64_t* ntiles, const int64_t* sorted,
-                            hipStream_t st);
+                            const int4* tiles, const int64_t* qtile, unsigned long long* qctr,
+                            const int64_t* sorted, hipStream_t st);
 size_t tile_lds_bytes(int q, int T);
 int tile_supported(int q, int T);
 

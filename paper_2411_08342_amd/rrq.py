@@ -44,7 +44,8 @@ class Targets(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("rho_far", ctypes.c_double), ("newton_tol", ctypes.c_double),
-                ("newton_maxit", ctypes.c_int32), ("tile_targets", ctypes.c_int32)]
+                ("newton_maxit", ctypes.c_int32), ("tile_targets", ctypes.c_int32),
+                ("grid", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -158,10 +159,11 @@ class DeviceTargets:
 class Plan:
     """rrq_plan: per-patch frames, coefficient maps and edge tables on the device."""
 
-    def __init__(self, dsurf, rho_far=0.0, newton_tol=0.0, newton_maxit=0, tile_targets=0):
+    def __init__(self, dsurf, rho_far=0.0, newton_tol=0.0, newton_maxit=0, tile_targets=0,
+                 grid=0):
         self.dsurf = dsurf
         self._s = dsurf.cstruct()
-        self._o = Options(rho_far, newton_tol, newton_maxit, tile_targets)
+        self._o = Options(rho_far, newton_tol, newton_maxit, tile_targets, grid)
         h = ctypes.c_void_p()
         _check(lib().rrq_plan_create(ctypes.byref(self._s), ctypes.byref(self._o), _stream(),
                                      ctypes.byref(h)))
