@@ -124,10 +124,13 @@ rrq_status rrq_plan_destroy(rrq_plan* plan);
 /* Bytes of caller-provided device workspace that rrq_assemble needs for this near list. */
 rrq_status rrq_workspace_size(const rrq_plan* plan, const rrq_targets* tg, size_t* bytes);
 
-/* pair_off[nnz+1] (device) = prefix sum of q_P^2 over the near list.  Synchronous: also
- * returns the total number of weights per kernel in *nweights (HOST). */
+/* pair_off[nnz+1] (device) = prefix sum of q_P^2 over the near list (the output offset of
+ * every pair's weight block).  `workspace` is the rrq_assemble workspace (its scan partials
+ * are used).  Asynchronous; if `nweights` (HOST) is non-NULL the call synchronises the stream
+ * and returns there the total number of weights per kernel. */
 rrq_status rrq_pair_offsets(const rrq_plan* plan, const rrq_targets* tg, int64_t* pair_off,
-                            int64_t* nweights, void* stream);
+                            void* workspace, size_t workspace_bytes, int64_t* nweights,
+                            void* stream);
 
 /* Assemble the weight blocks of every near pair.  out_* are [nweights] device arrays (NULL
  * for a kernel not in kmask).  pair_off from rrq_pair_offsets.  `workspace` of at least
@@ -175,6 +178,59 @@ rrq_status rrq_graph_create(rrq_plan* plan, const rrq_surface* surf, const rrq_t
                             void* workspace, size_t workspace_bytes, rrq_graph** out);
 rrq_status rrq_graph_launch(rrq_graph* g, void* stream);
 rrq_status rrq_graph_destroy(rrq_graph* g);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned initial guess of the singularity-swap Newton solve.  The paper finds the complex
+ * root t0 of sum_c (r_c(t) - x_c)^2 (eq. complexparameter) by Newton from the chord start
+ * (Sec. 3.5, Step 5); it has no learned part.  Here a network 8 -> 64 -> 64 -> 2 (tanh
+ * hidden units, float32) predicts dt = t0 - t_s from features of the edge and the target:
+ * t_s (2), and the quadratic and cubic Legendre coefficients of the edge over the chord
+ * half-length, in the chord frame (6).  With RRQ_F_LEARNED the batched form starts Newton
+ * at t_s + dt and accepts the root if Newton converges within 8 iterations to a root inside
+ * the Bernstein ellipse of radius rho_far; otherwise plain Newton from t_s decides.
+ * Parameter vector (float32, RRQ_MLP_PARAMS): W1 [64][8], b1 [64], W2 [64][64], b2 [64],
+ * W3 [2][64], b3 [2], row-major, in this order.
+ * --------------------------------------------------------------------------------------- */
+#define RRQ_MLP_PARAMS 4866
+
+typedef struct {
+  int32_t steps;   /* Adam steps                                                        */
+  int32_t batch;   /* samples per step (drawn with replacement), 1 .. 65536              */
+  float lr;        /* peak learning rate (cosine decay to 5 % of it)                     */
+  uint32_t seed;   /* seeds the initial weights and the sample draws                     */
+} rrq_mlp_cfg;
+
+/* Training samples produced by the method itself: for every near pair and edge whose chord
+ * start lies inside the Bernstein ellipse of radius rho_far and whose plain Newton solve
+ * converges to a root inside it, in pair order: feat [8][cap] (float32, SoA), dt [2][cap]
+ * (float32, t0 - t_s) and t0 [2][cap] (float64, may be NULL).  *count (HOST) = samples
+ * written (at most cap).  Synchronous; allocates and frees temporary device memory. */
+rrq_status rrq_collect_roots(const rrq_plan* plan, const rrq_targets* tg, int64_t cap,
+                             float* feat, float* dt, double* t0, int64_t* count, void* stream);
+
+/* Train the network on m samples (feat [8][m], dt [2][m], device) with the library's own
+ * forward, backward and Adam kernels (inputs and targets are standardised during training;
+ * the standardisation is folded into the returned parameters).  params [RRQ_MLP_PARAMS]
+ * (device) receives the result, loss_curve [steps] (device, may be NULL) the mean squared
+ * error of every step in standardised units.  Deterministic for a given seed.
+ * Synchronous; allocates and frees temporary device memory. */
+rrq_status rrq_mlp_train(const float* feat, const float* dt, int64_t m, const rrq_mlp_cfg* cfg,
+                         float* params, float* loss_curve, void* stream);
+
+/* Mean squared error L = (1/n) sum_b sum_o (y_bo - dt_ob)^2 of the network `params` on n
+ * samples (1 <= n <= 65536) and its gradient with respect to the parameters, with the same
+ * kernels as the training (gradient check).  loss [1], grad [RRQ_MLP_PARAMS] device.
+ * Synchronous; allocates and frees temporary device memory. */
+rrq_status rrq_mlp_loss_grad(const float* params, const float* feat, const float* dt, int64_t n,
+                             float* loss, float* grad, void* stream);
+
+/* Network outputs out [2][n] for features feat [8][n] (device).  Asynchronous. */
+rrq_status rrq_mlp_predict(const float* params, const float* feat, int64_t n, float* out,
+                           void* stream);
+
+/* Give the plan a trained parameter vector (device, copied on `stream`; NULL removes it).
+ * RRQ_F_LEARNED needs one (else RRQ_ERR_ARG); it is not supported with RRQ_F_PLAIN. */
+rrq_status rrq_plan_set_mlp(rrq_plan* plan, const float* params, void* stream);
 
 const char* rrq_status_string(rrq_status s);
 

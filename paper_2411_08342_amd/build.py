@@ -5,7 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librrq.so")
-SOURCES = ["rrq_consts.cpp", "rrq_fit.hip", "rrq_pair.hip", "rrq_batch.hip", "rrq_api.hip"]
+SOURCES = ["rrq_consts.cpp", "rrq_fit.hip", "rrq_pair.hip", "rrq_batch.hip", "rrq_mlp.hip",
+           "rrq_api.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -56,6 +56,8 @@ struct rrq_plan {
   std::vector<int32_t> patches_h[kMaxQ + 1];
   int32_t* patches_d[kMaxQ + 1] = {};
   int32_t* perm_d = nullptr;    // patches grouped by order (kOrders order)
+  float* mlp_d = nullptr;       // learned-guess network, inference layout
+  bool has_mlp = false;
   BinOrders bin_orders{};
   OrderDev od[kMaxQ + 1] = {};
   std::vector<void*> const_bufs;
@@ -83,6 +85,7 @@ struct rrq_plan {
     d.map_off = map_off_d;
     d.tabs = tabs_d;
     d.tab_off = tab_off_d;
+    d.mlp = has_mlp ? mlp_d : nullptr;
     return d;
   }
 };
@@ -92,7 +95,7 @@ static void plan_free(rrq_plan* p) {
   void* ptrs[] = {p->order_d, p->node_off_d, p->edge_off_d, p->node_xyz_d, p->node_nrm_d,
                   p->node_wt_d, p->frame_d, p->node_loc_d, p->edge_loc_d, p->edge_tan_d,
                   p->edge_coef_d, p->maps_d, p->map_off_d, p->tabs_d, p->tab_off_d,
-                  p->fit_ws_d, p->perm_d};
+                  p->fit_ws_d, p->perm_d, p->mlp_d};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int q = 0; q <= kMaxQ; ++q)
@@ -361,9 +364,9 @@ static TargetsDev tdev(const rrq_targets* tg) {
 
 // workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders] u64 |
-// sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4
+// sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials
 struct WsLayout {
-  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, total;
+  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P) {
@@ -380,6 +383,7 @@ static WsLayout ws_layout(int64_t nnz, int P) {
   w.queue = o; o = al(o + 8 * (2 * kNumOrders + 1));
   w.sorted = o; o = al(o + n * 8);
   w.tiles = o; o = al(o + (n / 4 + (size_t)P + 1) * 16);
+  w.part = o; o = al(o + (size_t)scan_partials((int64_t)n) * 8);
   w.total = o;
   return w;
 }
@@ -394,12 +398,15 @@ rrq_status rrq_workspace_size(const rrq_plan* p, const rrq_targets* tg, size_t* 
 }
 
 rrq_status rrq_pair_offsets(const rrq_plan* p, const rrq_targets* tg, int64_t* pair_off,
-                            int64_t* nweights, void* stream) {
+                            void* workspace, size_t workspace_bytes, int64_t* nweights,
+                            void* stream) {
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
-  if (!pair_off) return RRQ_ERR_ARG;
+  if (!pair_off || !workspace) return RRQ_ERR_ARG;
+  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
   hipStream_t st = (hipStream_t)stream;
-  if (launch_pair_offsets(p->dev(), tdev(tg), pair_off, nullptr, st) != hipSuccess)
+  int64_t* part = (int64_t*)((char*)workspace + ws_layout(tg->nnz, p->P).part);
+  if (launch_pair_offsets(p->dev(), tdev(tg), pair_off, part, st) != hipSuccess)
     return RRQ_ERR_DEVICE;
   if (nweights) {
     if (hipMemcpyAsync(nweights, pair_off + tg->nnz, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -420,7 +427,10 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
   for (int K = 0; K < 4; ++K)
     if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
-  if (flags & RRQ_F_LEARNED) return RRQ_ERR_UNSUPPORTED;
+  if (flags & RRQ_F_LEARNED) {
+    if (flags & RRQ_F_PLAIN) return RRQ_ERR_UNSUPPORTED;
+    if (!p->has_mlp) return RRQ_ERR_ARG;
+  }
   hipStream_t st = (hipStream_t)stream;
   const WsLayout wl = ws_layout(tg->nnz, p->P);
   char* wb = (char*)workspace;
@@ -503,6 +513,123 @@ rrq_status rrq_apply(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// learned initial guess
+// ---------------------------------------------------------------------------------------
+template <typename T>
+static bool talloc(std::vector<void*>& keep, T** p, size_t n) {
+  if (dalloc(p, n) != hipSuccess) return false;
+  keep.push_back((void*)*p);
+  return true;
+}
+static void tfree(std::vector<void*>& keep) {
+  for (void* q : keep) (void)hipFree(q);
+  keep.clear();
+}
+
+extern "C" rrq_status rrq_collect_roots(const rrq_plan* p, const rrq_targets* tg, int64_t cap,
+                                        float* feat, float* dt, double* t0, int64_t* count,
+                                        void* stream) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!count || cap < 0 || (cap > 0 && (!feat || !dt))) return RRQ_ERR_ARG;
+  *count = 0;
+  if (tg->nnz == 0) return RRQ_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nslot = 4 * tg->nnz;
+  std::vector<void*> keep;
+  int64_t *owner = nullptr, *flag = nullptr, *part = nullptr;
+  unsigned long long* counters = nullptr;
+  if (!talloc(keep, &owner, tg->nnz) || !talloc(keep, &counters, 8) ||
+      !talloc(keep, &flag, nslot + 1) || !talloc(keep, &part, scan_partials(nslot))) {
+    tfree(keep);
+    return RRQ_ERR_OOM;
+  }
+  CollectOpts co;
+  for (int q = 0; q <= kMaxQ; ++q) co.rho_far[q] = p->rho_far[q];
+  co.newton_tol = p->opt.newton_tol;
+  co.newton_maxit = p->opt.newton_maxit;
+  const PlanDev pd = p->dev();
+  const TargetsDev td = tdev(tg);
+  int64_t total = 0;
+  bool ok = launch_owner(td, owner, counters, st) == hipSuccess &&
+            hipMemsetAsync(flag, 0, 8, st) == hipSuccess &&
+            launch_collect(pd, td, owner, co, 0, flag, cap, feat, dt, t0, st) == hipSuccess &&
+            launch_scan_i64(flag, nslot, part, st) == hipSuccess &&
+            launch_collect(pd, td, owner, co, 1, flag, cap, feat, dt, t0, st) == hipSuccess &&
+            hipMemcpyAsync(&total, flag + nslot, 8, hipMemcpyDeviceToHost, st) == hipSuccess &&
+            hipStreamSynchronize(st) == hipSuccess;
+  tfree(keep);
+  if (!ok) return RRQ_ERR_DEVICE;
+  *count = total < cap ? total : cap;
+  return RRQ_OK;
+}
+
+static bool mlp_scratch(std::vector<void*>& keep, MlpScratch& s, int B) {
+  return talloc(keep, &s.part, (size_t)kMlpMomBlocks * 20) && talloc(keep, &s.stats, 20) &&
+         talloc(keep, &s.p, RRQ_MLP_PARAMS) && talloc(keep, &s.mo, 2 * RRQ_MLP_PARAMS) &&
+         talloc(keep, &s.g, RRQ_MLP_PARAMS) && talloc(keep, &s.Xn, (size_t)B * 8) &&
+         talloc(keep, &s.H1, (size_t)B * 64) && talloc(keep, &s.H2, (size_t)B * 64) &&
+         talloc(keep, &s.dY, (size_t)B * 2) && talloc(keep, &s.dH1, (size_t)B * 64) &&
+         talloc(keep, &s.dH2, (size_t)B * 64) && talloc(keep, &s.lossb, (size_t)B);
+}
+
+extern "C" rrq_status rrq_mlp_train(const float* feat, const float* dt, int64_t m,
+                                    const rrq_mlp_cfg* cfg, float* params, float* loss_curve,
+                                    void* stream) {
+  if (!feat || !dt || !cfg || !params || m < 1 || cfg->steps < 1 || cfg->batch < 1 ||
+      cfg->batch > 65536 || !(cfg->lr > 0.0f))
+    return RRQ_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<void*> keep;
+  MlpScratch s;
+  if (!mlp_scratch(keep, s, cfg->batch)) {
+    tfree(keep);
+    return RRQ_ERR_OOM;
+  }
+  const bool ok = mlp_train_run(feat, dt, m, cfg->steps, cfg->batch, cfg->lr,
+                                (uint64_t)cfg->seed, params, loss_curve, s, st) == hipSuccess &&
+                  hipStreamSynchronize(st) == hipSuccess;
+  tfree(keep);
+  return ok ? RRQ_OK : RRQ_ERR_DEVICE;
+}
+
+extern "C" rrq_status rrq_mlp_loss_grad(const float* params, const float* feat, const float* dt,
+                                        int64_t n, float* loss, float* grad, void* stream) {
+  if (!params || !feat || !dt || !loss || !grad || n < 1 || n > 65536) return RRQ_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<void*> keep;
+  MlpScratch s;
+  if (!mlp_scratch(keep, s, (int)n)) {
+    tfree(keep);
+    return RRQ_ERR_OOM;
+  }
+  const bool ok = mlp_loss_grad_run(params, feat, dt, n, loss, grad, s, st) == hipSuccess &&
+                  hipStreamSynchronize(st) == hipSuccess;
+  tfree(keep);
+  return ok ? RRQ_OK : RRQ_ERR_DEVICE;
+}
+
+extern "C" rrq_status rrq_mlp_predict(const float* params, const float* feat, int64_t n,
+                                      float* out, void* stream) {
+  if (!params || n < 0 || (n > 0 && (!feat || !out))) return RRQ_ERR_ARG;
+  return mlp_predict_run(params, feat, n, out, (hipStream_t)stream) == hipSuccess
+             ? RRQ_OK
+             : RRQ_ERR_DEVICE;
+}
+
+extern "C" rrq_status rrq_plan_set_mlp(rrq_plan* p, const float* params, void* stream) {
+  if (!p) return RRQ_ERR_ARG;
+  if (!params) {
+    p->has_mlp = false;
+    return RRQ_OK;
+  }
+  if (!p->mlp_d && dalloc(&p->mlp_d, RRQ_MLP_PARAMS) != hipSuccess) return RRQ_ERR_OOM;
+  if (mlp_pack_run(params, p->mlp_d, (hipStream_t)stream) != hipSuccess) return RRQ_ERR_DEVICE;
+  p->has_mlp = true;
+  return RRQ_OK;
+}
 
 // ---------------------------------------------------------------------------------------
 // autotuner and graph capture
@@ -602,7 +729,7 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RRQ_ERR_DEVICE;
   // one eager pass on the capture stream first: kernel attributes are set outside capture
   rrq_status r = rrq_plan_refit(p, s, cs);
-  if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, nullptr, cs);
+  if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, workspace, workspace_bytes, nullptr, cs);
   if (r == RRQ_OK)
     r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
                      workspace_bytes, cs, nullptr);
@@ -618,7 +745,7 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
     return RRQ_ERR_DEVICE;
   }
   r = rrq_plan_refit(p, s, cs);
-  if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, nullptr, cs);
+  if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, workspace, workspace_bytes, nullptr, cs);
   if (r == RRQ_OK)
     r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
                      workspace_bytes, cs, nullptr);

@@ -162,7 +162,8 @@ __device__ __forceinline__ double reduce_scatter16(double* x) {
   return v;
 }
 
-constexpr int kMaxLevel = 52;   // deepest dyadic level that still splits (panel width 2^-51)
+constexpr int kMaxLevel = 52;
+constexpr int kLearnedMaxit = 8;   // Newton iterations allowed from the learned start   // deepest dyadic level that still splits (panel width 2^-51)
 
 // Dyadic panels of [-1, 1] graded toward t0 = a + i b: a panel of half-width h and centre c
 // is split while (t0 - c) / h lies inside the Bernstein ellipse of radius rho (that is,
@@ -313,7 +314,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t tlo = qtile[0], thi = qtile[1];
-  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_max = 0;
+  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_max = 0, c_learn = 0;
+  const bool learned = (out.flags & RRQ_F_LEARNED) != 0 && pd.mlp != nullptr;
+  // network scratch of the learned guess, in the effective-weight area (free until then)
+  float* mx = (float*)(smem + L::o_td);          // [4T][8]
+  float* mh1 = mx + 4 * T * kMlpIn;              // [4T][64]
+  float* mh2 = mh1 + 4 * T * kMlpH;              // [4T][64]
+  float* mdt = mh2 + 4 * T * kMlpH;              // [4T][2]
+  static_assert(4 * T * (kMlpIn + 2 * kMlpH + kMlpOut) <= 2 * L::n_scrA, "network scratch");
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
     cgl_w[tid] = od.gl_w[tid];
@@ -396,53 +404,81 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
+      // ---- learned initial guess (RRQ_F_LEARNED): features of every (target, edge), then
+      // the network on all threads (float32, weights read from the plan)
+      if (learned) {
+        if (tid < 4 * nt) {
+          cplx tsd;
+          edge_features(ecoef + (tid & 3) * PT * 3, PT, sx + (tid >> 2) * 3, mx + tid * kMlpIn,
+                        &tsd);
+        }
+        __syncthreads();
+        const float* W = pd.mlp;
+        for (int idx = tid; idx < 4 * nt * kMlpH; idx += BNT) {
+          const int te = idx / kMlpH, u = idx % kMlpH;
+          float a = W[kMlpB1 + u];
+#pragma unroll
+          for (int c = 0; c < kMlpIn; ++c) a += W[kMlpW1 + c * kMlpH + u] * mx[te * kMlpIn + c];
+          mh1[idx] = tanhf(a);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < 4 * nt * kMlpH; idx += BNT) {
+          const int te = idx / kMlpH, u = idx % kMlpH;
+          float a = W[kMlpB2 + u];
+#pragma unroll 8
+          for (int k = 0; k < kMlpH; ++k) a += W[kMlpW2 + k * kMlpH + u] * mh1[te * kMlpH + k];
+          mh2[idx] = tanhf(a);
+        }
+        __syncthreads();
+        if (tid < 4 * nt * kMlpOut) {
+          const int te = tid / kMlpOut, o = tid % kMlpOut;
+          float a = W[kMlpB3 + o];
+#pragma unroll 8
+          for (int k = 0; k < kMlpH; ++k) a += W[kMlpW3 + o * kMlpH + k] * mh2[te * kMlpH + k];
+          mdt[tid] = a;
+        }
+        __syncthreads();
+      }
       // ---- Step 5: per (target, edge) classification and Newton root (wave 0); Step 4:
       // target harmonics (wave 1) at the same time
       if (tid < 4 * nt) {
         const int t = tid >> 2, e = tid & 3;
         const double* cf = ecoef + e * PT * 3;
         const double* xl = sx + t * 3;
-        double A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-        for (int kk = 0; kk < PT; ++kk)
-          for (int c = 0; c < 3; ++c) {
-            A[c] += (kk & 1) ? -cf[kk * 3 + c] : cf[kk * 3 + c];
-            B[c] += cf[kk * 3 + c];
-          }
-        double m[3], dv[3], v[3];
-        for (int c = 0; c < 3; ++c) {
-          m[c] = 0.5 * (A[c] + B[c]);
-          dv[c] = 0.5 * (B[c] - A[c]);
-          v[c] = xl[c] - m[c];
-        }
-        const double dd = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
-        const double cr0 = dv[1] * v[2] - dv[2] * v[1];
-        const double cr1 = dv[2] * v[0] - dv[0] * v[2];
-        const double cr2 = dv[0] * v[1] - dv[1] * v[0];
-        const cplx ts = mk((dv[0] * v[0] + dv[1] * v[1] + dv[2] * v[2]) / dd,
-                           sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2) / dd);
+        double m[3], dv[3];
+        edge_chord(cf, PT, m, dv);
+        const cplx ts = chord_root(m, dv, xl);
         int near = 0;
         cplx t0 = ts;
         if (bernstein_rho(ts) <= so.rho_far) {
-          int conv = 0, its;
-          for (its = 1; its <= so.newton_maxit; ++its) {
-            cplx r[3], dr[3];
-            leg3(cf, 3, PT, t0, r, dr);
-            cplx f = mk(0, 0), fp = mk(0, 0);
-            for (int c = 0; c < 3; ++c) {
-              const cplx ec = r[c] - mk(xl[c], 0.0);
-              f = f + ec * ec;
-              fp = fp + ec * dr[c];
+          int done = 0, its_all = 0;
+          if (learned) {
+            cplx tl = mk(ts.re + (double)mdt[tid * 2], ts.im + (double)mdt[tid * 2 + 1]);
+            if (isfinite(tl.re) && isfinite(tl.im)) {
+              int its;
+              const int conv = newton_solve(cf, PT, xl, &tl, so.newton_tol, kLearnedMaxit, &its);
+              its_all += its;
+              if (tl.im < 0) tl.im = -tl.im;
+              if (conv && bernstein_rho(tl) <= so.rho_far) {
+                t0 = tl;
+                near = 1;
+                done = 1;
+                ++c_learn;
+              }
             }
-            const cplx dt = cdiv(f, 2.0 * fp);
-            t0 = t0 - dt;
-            if (cabsd(dt) <= so.newton_tol * fmax(1.0, cabsd(t0))) { conv = 1; break; }
           }
-          if (its > so.newton_maxit) its = so.newton_maxit;
-          if (t0.im < 0) t0.im = -t0.im;
-          if (conv && bernstein_rho(t0) <= so.rho_far) near = 1;
-          c_iters += (unsigned long long)its;
-          if (!conv) ++c_fail;
-          if ((unsigned long long)its > c_max) c_max = its;
+          if (!done) {
+            int its;
+            cplx tp = ts;
+            const int conv = newton_solve(cf, PT, xl, &tp, so.newton_tol, so.newton_maxit, &its);
+            its_all += its;
+            if (tp.im < 0) tp.im = -tp.im;
+            t0 = tp;
+            if (conv && bernstein_rho(tp) <= so.rho_far) near = 1;
+            if (!conv) ++c_fail;
+          }
+          c_iters += (unsigned long long)its_all;
+          if ((unsigned long long)its_all > c_max) c_max = its_all;
           if (near) ++c_near;
         }
         snear[t * 4 + e] = near;
@@ -826,6 +862,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   if (c_fail) atomicAdd(&out.counters[2], c_fail);
   if (c_max) atomicMax(&out.counters[4], c_max);
   if (c_near) atomicAdd(&out.counters[0], c_near);
+  if (c_learn) atomicAdd(&out.counters[3], c_learn);
 }
 
 #define RRQ_TILE_CASES(X) X(4, 4) X(4, 8) X(5, 4) X(5, 8) X(6, 4) X(6, 8) X(8, 4) X(8, 8) X(10, 4)

@@ -209,4 +209,107 @@ __device__ __forceinline__ double omega0_at(const double* x, const double* u, co
   return num / (R * (R + d0 * u[0] + d1 * u[1] + d2 * u[2]));
 }
 
+// ---------------------------------------------------------------------------------------
+// singularity-swap root (Sec. 3.5, Step 5): chord start and Newton on
+// f(t) = sum_c (r_c(t) - x_c)^2 for an edge given by its Legendre coefficients cf[3k + c]
+// ---------------------------------------------------------------------------------------
+
+// r(-1) and r(1) of the edge, then the chord midpoint m and half-vector d
+__device__ __forceinline__ void edge_chord(const double* cf, int n, double* m, double* d) {
+  double A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+  for (int kk = 0; kk < n; ++kk)
+    for (int c = 0; c < 3; ++c) {
+      A[c] += (kk & 1) ? -cf[kk * 3 + c] : cf[kk * 3 + c];
+      B[c] += cf[kk * 3 + c];
+    }
+  for (int c = 0; c < 3; ++c) {
+    m[c] = 0.5 * (A[c] + B[c]);
+    d[c] = 0.5 * (B[c] - A[c]);
+  }
+}
+
+// root of the distance function of the straight chord
+__device__ __forceinline__ cplx chord_root(const double* m, const double* d, const double* x) {
+  const double v[3] = {x[0] - m[0], x[1] - m[1], x[2] - m[2]};
+  const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const double cr0 = d[1] * v[2] - d[2] * v[1];
+  const double cr1 = d[2] * v[0] - d[0] * v[2];
+  const double cr2 = d[0] * v[1] - d[1] * v[0];
+  return mk((d[0] * v[0] + d[1] * v[1] + d[2] * v[2]) / dd,
+            sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2) / dd);
+}
+
+// Newton from t: returns 1 when the step fell below tol * max(1, |t|) within maxit
+// iterations; *t is the last iterate (not canonicalised), *its the iterations taken
+__device__ __forceinline__ int newton_solve(const double* cf, int n, const double* x, cplx* t,
+                                            double tol, int maxit, int* its) {
+  cplx t0 = *t;
+  int it;
+  for (it = 1; it <= maxit; ++it) {
+    cplx r[3], dr[3];
+    leg3(cf, 3, n, t0, r, dr);
+    cplx f = mk(0, 0), fp = mk(0, 0);
+    for (int c = 0; c < 3; ++c) {
+      const cplx ec = r[c] - mk(x[c], 0.0);
+      f = f + ec * ec;
+      fp = fp + ec * dr[c];
+    }
+    const cplx dt = cdiv(f, 2.0 * fp);
+    t0 = t0 - dt;
+    if (cabsd(dt) <= tol * fmax(1.0, cabsd(t0))) {
+      *t = t0;
+      *its = it;
+      return 1;
+    }
+  }
+  *t = t0;
+  *its = maxit;
+  return 0;
+}
+
+// Features of (edge, target) for the learned initial guess: the chord root t_s, and the
+// quadratic and cubic Legendre coefficients over |d| in the chord frame (e1 along d, e2
+// toward the target's component perpendicular to the chord, e3 = e1 x e2).  Computed in
+// double, returned rounded to float.
+__device__ __forceinline__ void edge_features(const double* cf, int n, const double* x,
+                                              float* f, cplx* ts_out) {
+  double m[3], d[3];
+  edge_chord(cf, n, m, d);
+  const cplx ts = chord_root(m, d, x);
+  *ts_out = ts;
+  const double ld = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double e1[3] = {d[0] / ld, d[1] / ld, d[2] / ld};
+  const double v[3] = {x[0] - m[0], x[1] - m[1], x[2] - m[2]};
+  const double ve = v[0] * e1[0] + v[1] * e1[1] + v[2] * e1[2];
+  double e2[3] = {v[0] - ve * e1[0], v[1] - ve * e1[1], v[2] - ve * e1[2]};
+  double nv = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+  if (!(nv > 0.0)) {
+    const double a[3] = {fabs(e1[0]) < 0.9 ? 1.0 : 0.0, fabs(e1[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+    const double ae = a[0] * e1[0] + a[1] * e1[1] + a[2] * e1[2];
+    for (int c = 0; c < 3; ++c) e2[c] = a[c] - ae * e1[c];
+    nv = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+  }
+  for (int c = 0; c < 3; ++c) e2[c] /= nv;
+  const double e3[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                        e1[0] * e2[1] - e1[1] * e2[0]};
+  f[0] = (float)ts.re;
+  f[1] = (float)ts.im;
+  for (int j = 0; j < 2; ++j) {
+    double a[3] = {0, 0, 0};
+    if (2 + j < n)
+      for (int c = 0; c < 3; ++c) a[c] = cf[(2 + j) * 3 + c] / ld;
+    f[2 + 3 * j] = (float)(a[0] * e1[0] + a[1] * e1[1] + a[2] * e1[2]);
+    f[3 + 3 * j] = (float)(a[0] * e2[0] + a[1] * e2[1] + a[2] * e2[2]);
+    f[4 + 3 * j] = (float)(a[0] * e3[0] + a[1] * e3[1] + a[2] * e3[2]);
+  }
+}
+
+// Multilayer perceptron 8 -> 64 -> 64 -> 2 (tanh hidden units), parameters in the
+// device layout: W1t [8][64], b1 [64], W2t [64][64], b2 [64], W3 [2][64], b3 [2]
+constexpr int kMlpIn = 8, kMlpH = 64, kMlpOut = 2;
+constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
+constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpH * kMlpIn, kMlpW2 = kMlpB1 + kMlpH,
+              kMlpB2 = kMlpW2 + kMlpH * kMlpH, kMlpW3 = kMlpB2 + kMlpH,
+              kMlpB3 = kMlpW3 + kMlpOut * kMlpH;
+
 }  // namespace rrq

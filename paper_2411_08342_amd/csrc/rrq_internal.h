@@ -52,6 +52,7 @@ struct PlanDev {
   const int64_t* map_off;
   double* tabs;             // per patch: [4][pt][njk][12]: c (3 cplx), h (3 cplx)
   const int64_t* tab_off;
+  const float* mlp;         // learned-guess network, inference layout (or null)
 };
 
 struct TargetsDev {
@@ -87,7 +88,10 @@ hipError_t launch_fit(const PlanDev& pd, const OrderDev& od, const int32_t* patc
 hipError_t launch_owner(const TargetsDev& tg, int64_t* owner, unsigned long long* counters,
                         hipStream_t st);
 hipError_t launch_pair_offsets(const PlanDev& pd, const TargetsDev& tg, int64_t* pair_off,
-                               int64_t* scratch, hipStream_t st);
+                               int64_t* part, hipStream_t st);
+// inclusive scan of a[1..n] in place; part holds scan_partials(n) int64
+hipError_t launch_scan_i64(int64_t* a, int64_t n, int64_t* part, hipStream_t st);
+int64_t scan_partials(int64_t n);
 hipError_t launch_pair_plain(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
                              const AssembleOut& out, const SolveOpts& so, hipStream_t st);
 hipError_t launch_apply(const PlanDev& pd, const TargetsDev& tg, const double* const* w,
@@ -111,5 +115,33 @@ size_t tile_lds_bytes(int q, int T);
 int tile_supported(int q, int T);
 
 int64_t fit_ws_doubles(int q);
+
+// learned initial guess: sample collection and training
+struct CollectOpts {
+  double rho_far[kMaxQ + 1];
+  double newton_tol;
+  int newton_maxit;
+};
+constexpr int kMlpMomBlocks = 256;
+struct MlpScratch {
+  double* part;     // [kMlpMomBlocks][20] column sums
+  float* stats;     // mean[10], std[10] of features and targets
+  float* p;         // parameters of the normalised problem
+  float* mo;        // Adam first and second moments [2][params]
+  float* g;         // gradient
+  float *Xn, *H1, *H2, *dY, *dH1, *dH2, *lossb;   // per-batch buffers
+};
+hipError_t launch_collect(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
+                          const CollectOpts& co, int pass, int64_t* flag, int64_t cap,
+                          float* feat, float* dt, double* t0, hipStream_t st);
+hipError_t mlp_train_run(const float* feat, const float* dt, int64_t m, int steps, int B,
+                         float lr, uint64_t seed, float* params, float* loss_curve,
+                         MlpScratch& s, hipStream_t st);
+hipError_t mlp_loss_grad_run(const float* params, const float* feat, const float* dt,
+                             int64_t n, float* loss, float* grad, MlpScratch& s,
+                             hipStream_t st);
+hipError_t mlp_predict_run(const float* params, const float* feat, int64_t n, float* out,
+                           hipStream_t st);
+hipError_t mlp_pack_run(const float* params, float* dst, hipStream_t st);
 
 }  // namespace rrq

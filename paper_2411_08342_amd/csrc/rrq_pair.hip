@@ -26,7 +26,7 @@ hipError_t launch_owner(const TargetsDev& tg, int64_t* owner, unsigned long long
   return hipGetLastError();
 }
 
-// pair sizes q_P^2 then an inclusive scan (single workgroup, chunked)
+// pair sizes q_P^2, then an inclusive scan
 __global__ void k_pair_sizes(PlanDev pd, TargetsDev tg, int64_t* off) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tg.nnz;
        k += (int64_t)gridDim.x * blockDim.x) {
@@ -36,38 +36,90 @@ __global__ void k_pair_sizes(PlanDev pd, TargetsDev tg, int64_t* off) {
   if (blockIdx.x == 0 && threadIdx.x == 0) off[0] = 0;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_inplace(int64_t* a, int64_t n) {
-  // inclusive scan of a[1..n] by one workgroup of 1024 threads, chunk by chunk
-  __shared__ int64_t sm[1024];
+// Inclusive scan of a[1..n] in three passes: every workgroup scans a segment of kScanSeg
+// elements (8 consecutive per thread) and records the segment total; one workgroup scans
+// the totals (exclusive); every segment then adds its prefix.
+constexpr int kScanThreads = 1024, kScanPer = 8, kScanSeg = kScanThreads * kScanPer;
+
+int64_t scan_partials(int64_t n) { return (n + kScanSeg - 1) / kScanSeg + 1; }
+
+__device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t* sm) {
+  const int t = threadIdx.x;
+  sm[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const int64_t x = t >= o ? sm[t - o] : 0;
+    __syncthreads();
+    sm[t] += x;
+    __syncthreads();
+  }
+  return sm[t];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_seg(int64_t* a, int64_t n, int64_t* part) {
+  __shared__ int64_t sm[kScanThreads];
+  const int64_t base = 1 + (int64_t)blockIdx.x * kScanSeg + (int64_t)threadIdx.x * kScanPer;
+  int64_t v[kScanPer];
+  int64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    const int64_t idx = base + i;
+    sum += idx <= n ? a[idx] : 0;
+    v[i] = sum;
+  }
+  const int64_t incl = block_incl_scan(sum, sm);
+  const int64_t excl = incl - sum;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    const int64_t idx = base + i;
+    if (idx <= n) a[idx] = v[i] + excl;
+  }
+  if (threadIdx.x == kScanThreads - 1) part[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_part(int64_t* part, int64_t nseg) {
+  __shared__ int64_t sm[kScanThreads];
   __shared__ int64_t carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  for (int64_t base = 1; base <= n; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    int64_t v = i <= n ? a[i] : 0;
-    sm[threadIdx.x] = v;
+  for (int64_t b = 0; b < nseg; b += kScanThreads) {
+    const int64_t i = b + threadIdx.x;
+    const int64_t v = i < nseg ? part[i] : 0;
+    const int64_t incl = block_incl_scan(v, sm);
+    const int64_t c = carry;
+    if (i < nseg) part[i] = c + incl - v;       // exclusive
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      int64_t t = threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
-      __syncthreads();
-      sm[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i <= n) a[i] = sm[threadIdx.x] + carry;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += sm[1023];
+    if (threadIdx.x == kScanThreads - 1) carry = c + incl;
     __syncthreads();
   }
 }
 
+__global__ void k_scan_add(int64_t* a, int64_t n, const int64_t* part) {
+  const int64_t seg = blockIdx.x + 1;           // segment 0 has prefix 0
+  const int64_t add = part[seg];
+  const int64_t base = 1 + seg * kScanSeg;
+  for (int64_t i = base + threadIdx.x; i < base + kScanSeg && i <= n; i += blockDim.x) a[i] += add;
+}
+
+hipError_t launch_scan_i64(int64_t* a, int64_t n, int64_t* part, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nseg = (n + kScanSeg - 1) / kScanSeg;
+  hipLaunchKernelGGL(k_scan_seg, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a, n, part);
+  hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(kScanThreads), 0, st, part, nseg);
+  if (nseg > 1)
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)(nseg - 1)), dim3(256), 0, st, a, n, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_pair_offsets(const PlanDev& pd, const TargetsDev& tg, int64_t* pair_off,
-                               int64_t*, hipStream_t st) {
+                               int64_t* part, hipStream_t st) {
   int64_t g = (tg.nnz + 255) / 256;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_pair_sizes, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st,
                      pd, tg, pair_off);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, st, pair_off, tg.nnz);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scan_i64(pair_off, tg.nnz, part, st);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -19,7 +19,9 @@ KERNELS = ("S", "D", "Sp", "Dp")
 
 EXPORTED = ("rrq_plan_create", "rrq_plan_refit", "rrq_plan_destroy", "rrq_workspace_size",
             "rrq_pair_offsets", "rrq_assemble", "rrq_apply", "rrq_autotune", "rrq_graph_create",
-            "rrq_graph_launch", "rrq_graph_destroy", "rrq_status_string")
+            "rrq_graph_launch", "rrq_graph_destroy", "rrq_collect_roots", "rrq_mlp_train",
+            "rrq_mlp_loss_grad", "rrq_mlp_predict", "rrq_plan_set_mlp", "rrq_status_string")
+MLP_PARAMS = 4866
 
 
 class RRQError(RuntimeError):
@@ -57,6 +59,11 @@ class Stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class MlpCfg(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint32)]
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("tile_targets", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
@@ -78,7 +85,8 @@ def lib():
         L.rrq_plan_refit.argtypes = [vp, ctypes.POINTER(Surface), vp]
         L.rrq_plan_destroy.argtypes = [vp]
         L.rrq_workspace_size.argtypes = [vp, ctypes.POINTER(Targets), ctypes.POINTER(ctypes.c_size_t)]
-        L.rrq_pair_offsets.argtypes = [vp, ctypes.POINTER(Targets), vp, ctypes.POINTER(i64), vp]
+        L.rrq_pair_offsets.argtypes = [vp, ctypes.POINTER(Targets), vp, vp, ctypes.c_size_t,
+                                       ctypes.POINTER(i64), vp]
         L.rrq_assemble.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp, vp,
                                    ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
         L.rrq_apply.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -91,6 +99,12 @@ def lib():
                                        ctypes.POINTER(vp)]
         L.rrq_graph_launch.argtypes = [vp, vp]
         L.rrq_graph_destroy.argtypes = [vp]
+        L.rrq_collect_roots.argtypes = [vp, ctypes.POINTER(Targets), i64, vp, vp, vp,
+                                        ctypes.POINTER(i64), vp]
+        L.rrq_mlp_train.argtypes = [vp, vp, i64, ctypes.POINTER(MlpCfg), vp, vp, vp]
+        L.rrq_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.rrq_mlp_predict.argtypes = [vp, vp, i64, vp, vp]
+        L.rrq_plan_set_mlp.argtypes = [vp, vp, vp]
         L.rrq_status_string.argtypes = [i32]
         L.rrq_status_string.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -169,6 +183,11 @@ class Plan:
                                      ctypes.byref(h)))
         self.handle = h
 
+    def set_mlp(self, params):
+        """Install a trained network (float32 CUDA tensor of MLP_PARAMS) or remove it (None)."""
+        _check(lib().rrq_plan_set_mlp(self.handle, params.data_ptr() if params is not None else None,
+                                      _stream()))
+
     def refit(self, dsurf=None):
         if dsurf is not None:
             self.dsurf = dsurf
@@ -195,19 +214,21 @@ class Assembler:
         self.plan, self.dtg, self.kmask = plan, dtg, kmask
         self._t = dtg.cstruct()
         self.pair_off = torch.empty(dtg.nnz + 1, dtype=torch.int64, device="cuda")
-        nw = ctypes.c_int64()
-        _check(lib().rrq_pair_offsets(plan.handle, ctypes.byref(self._t), self.pair_off.data_ptr(),
-                                      ctypes.byref(nw), _stream()))
-        self.nweights = int(nw.value)
         sz = ctypes.c_size_t()
         _check(lib().rrq_workspace_size(plan.handle, ctypes.byref(self._t), ctypes.byref(sz)))
         self.workspace = torch.empty(int(sz.value), dtype=torch.uint8, device="cuda")
+        nw = ctypes.c_int64()
+        _check(lib().rrq_pair_offsets(plan.handle, ctypes.byref(self._t), self.pair_off.data_ptr(),
+                                      self.workspace.data_ptr(), self.workspace.numel(),
+                                      ctypes.byref(nw), _stream()))
+        self.nweights = int(nw.value)
         self.out = {k: (torch.empty(self.nweights, dtype=torch.float64, device="cuda")
                         if kmask & (1 << i) else None) for i, k in enumerate(KERNELS)}
 
     def pair_offsets(self):
         _check(lib().rrq_pair_offsets(self.plan.handle, ctypes.byref(self._t),
-                                      self.pair_off.data_ptr(), None, _stream()))
+                                      self.pair_off.data_ptr(), self.workspace.data_ptr(),
+                                      self.workspace.numel(), None, _stream()))
 
     def assemble(self, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV, stats=False):
         st = Stats() if stats else None
@@ -275,3 +296,57 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------------------
+# learned initial guess of the singularity-swap Newton solve
+# ---------------------------------------------------------------------------------------
+def collect_roots(plan, dtg, cap):
+    """rrq_collect_roots: (feat [8][n] float32, dt [2][n] float32, t0 [2][n] float64) for the
+    near (pair, edge) combinations of this near list, n <= cap."""
+    import torch
+    t = dtg.cstruct()
+    feat = torch.empty((8, cap), dtype=torch.float32, device="cuda")
+    dt = torch.empty((2, cap), dtype=torch.float32, device="cuda")
+    t0 = torch.empty((2, cap), dtype=torch.float64, device="cuda")
+    n = ctypes.c_int64()
+    _check(lib().rrq_collect_roots(plan.handle, ctypes.byref(t), cap, feat.data_ptr(),
+                                   dt.data_ptr(), t0.data_ptr(), ctypes.byref(n), _stream()))
+    n = int(n.value)
+    return (feat[:, :n].contiguous(), dt[:, :n].contiguous(), t0[:, :n].contiguous())
+
+
+def mlp_train(feat, dt, steps=3000, batch=4096, lr=3e-3, seed=1):
+    """rrq_mlp_train on samples feat [8][m], dt [2][m]: returns (params, loss_curve)."""
+    import torch
+    m = feat.shape[1]
+    assert feat.shape == (8, m) and dt.shape == (2, m)
+    feat, dt = feat.contiguous(), dt.contiguous()
+    params = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    curve = torch.empty(steps, dtype=torch.float32, device="cuda")
+    cfg = MlpCfg(steps, batch, lr, seed)
+    _check(lib().rrq_mlp_train(feat.data_ptr(), dt.data_ptr(), m, ctypes.byref(cfg),
+                               params.data_ptr(), curve.data_ptr(), _stream()))
+    return params, curve
+
+
+def mlp_loss_grad(params, feat, dt):
+    """rrq_mlp_loss_grad: (loss, gradient) of the mean squared error on n samples."""
+    import torch
+    n = feat.shape[1]
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    _check(lib().rrq_mlp_loss_grad(params.contiguous().data_ptr(), feat.contiguous().data_ptr(),
+                                   dt.contiguous().data_ptr(), n, loss.data_ptr(),
+                                   grad.data_ptr(), _stream()))
+    return loss, grad
+
+
+def mlp_predict(params, feat):
+    """rrq_mlp_predict: outputs [2][n] for features [8][n]."""
+    import torch
+    n = feat.shape[1]
+    out = torch.empty((2, n), dtype=torch.float32, device="cuda")
+    _check(lib().rrq_mlp_predict(params.contiguous().data_ptr(), feat.contiguous().data_ptr(), n,
+                                 out.data_ptr(), _stream()))
+    return out

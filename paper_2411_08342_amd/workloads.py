@@ -420,6 +420,32 @@ def config5(cloud=200_000, spheres=40, lattice=(4, 5, 2), spacing=2.3,
     return surf, tg, None
 
 
+def learned_guess_training(seed=SEED_BASE + 40, n=10, q=8, nt=20, nphi=40, per_patch=12):
+    """Seeded geometry for the learned Newton guess's training samples, kept apart from the
+    evaluation surfaces: a deformed sphere r = 1 + sum_{l<=5} a_lm Y_lm (a ~ N(0, 0.06^2))
+    and a torus (R = 1.1, r = 0.4) beside it, order q; targets all nodes plus per_patch
+    off-surface points per patch at distances log-U[1e-4, 0.5] patch diameters; near list
+    1.5 patch diameters."""
+    rng = np.random.default_rng(seed)
+    coeff = {(l, m): rng.normal(0, 0.06) for l in range(0, 6) for m in range(-l, l + 1)}
+
+    def radial(x, y, z):
+        Y = real_sph_harm_unit(5, x, y, z)
+        return 1.0 + sum(c * Y[key] for key, c in coeff.items())
+    s1 = discretize(cubed_sphere_patches(n, radial=radial), np.full(6 * n * n, q))
+    s2 = discretize(torus_patches(nt, nphi, R=1.1, r=0.4, center=(3.2, 0.0, 0.0)),
+                    np.full(nt * nphi, q))
+    surf = merge_surfaces([s1, s2])
+    x, nn, sp, sn = node_targets(surf)
+    xo, no = offsurface_targets(surf, rng, count_per_patch=per_patch, rel_dist=(1e-4, 0.5))
+    xyz = np.concatenate([x, xo], axis=1)
+    nrm = np.concatenate([nn, no], axis=1)
+    sp = np.concatenate([sp, np.full(xo.shape[1], -1, np.int32)])
+    sn = np.concatenate([sn, np.full(xo.shape[1], -1, np.int32)])
+    tg = make_targets(surf, xyz, nrm, sp, sn, eta=1.5)
+    return surf, tg, None
+
+
 def quadratic_patch(k=(0.35, -0.2, 0.25), scale=0.6, shift=(0.0, 0.0, 0.0)):
     """One curved patch r(u, v) = scale (u, v, k0 u^2 + k1 u v + k2 v^2) + shift; its edges are
     quadratic curves, so the edge interpolants reproduce them exactly."""
