@@ -19,6 +19,12 @@ sys.path.insert(0, ROOT)
 METRIC = "near-correction weights/sec (FP64, S/D/S'/D') at ≤1e-11 err; batched vs plain"
 FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
 
+# HBM traffic of the dominant kernel per launch, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
+# (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
+# source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
+TRAFFIC = {"src_sha256": None, "fetch_bytes": None, "write_bytes": None}
+
 
 def flops_per_pair(q):
     """Algorithmic FP64 flops of one (target, patch) pair at order q (ptilde = 2q), counting
@@ -44,6 +50,39 @@ def flops_per_pair(q):
                             tD += 1
     return (4 * pt * (16 * J1 + 76 * J2) + 4 * pt * 60 + 100 * tD + 10 * tS
             + 60 * (p + 1) ** 2 + 2 * q * q * 17 * n_p)
+
+
+def kernel_src_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2411_08342_amd", "csrc", "rrq_batch.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def learned_form(rrq, asm, flags, w_ref, reps=2):
+    """Train the learned Newton guess on its own seeded geometry (not the benchmark surface),
+    then time the batched form with it.  Returns a summary dict."""
+    import torch
+    from paper_2411_08342_amd import workloads as wl
+    t0 = time.perf_counter()
+    surf, tg, _ = wl.learned_guess_training()
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    feat, dt, _ = rrq.collect_roots(plan, rrq.DeviceTargets(tg), 4 * len(tg["near_patch"]))
+    plan.close()
+    params, curve = rrq.mlp_train(feat, dt, steps=4000, batch=8192, lr=3e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    asm.plan.set_mlp(params)
+    lf = flags | rrq.RRQ_F_LEARNED
+    st = [asm.assemble(flags=lf, stats=True) for _ in range(reps)]
+    dev = max(((asm.out[k] - w_ref[k]).abs().max() / w_ref[k].abs().max()).item()
+              for k in rrq.KERNELS)
+    asm.plan.set_mlp(None)
+    c = curve.cpu().numpy()
+    return {"kernel_ms": float(np.mean([x["kernel_ms"] for x in st])),
+            "newton_iters": st[-1]["newton_iters"], "learned_accept": st[-1]["learned_accept"],
+            "max_rel_weight_dev_vs_batched": dev, "train_samples": int(feat.shape[1]),
+            "train_s": t_train, "train_loss_first_last": [float(c[:10].mean()), float(c[-100:].mean())]}
 
 
 def build_workload(name):
@@ -113,6 +152,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the plain-form and learned-guess measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "known-size reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -147,8 +188,6 @@ def main():
     for _ in range(args.warmup):
         graph.launch()
     torch.cuda.synchronize()
-    stats = asm.assemble(flags=flags, stats=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         graph.launch()
@@ -157,19 +196,30 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
     value = nweights / (ms_per_step / 1e3)
-    # duration of the dominant kernel (assembly) on the stream it runs on, HIP events
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record()
-        asm.assemble(flags=flags)
-        b.record()
-    torch.cuda.synchronize()
-    asm_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    # duration of the dominant kernel (the pair kernel of the assembly), from HIP events the
+    # library records around it on the stream it runs on
+    runs = [asm.assemble(flags=flags, stats=True) for _ in range(args.steps)]
+    stats = runs[-1]
+    kern_ms = float(np.mean([r["kernel_ms"] for r in runs]))
+    w_ref = {k: asm.out[k].clone() for k in rrq.KERNELS}
+    forms = {args.form + "_kernel_ms": kern_ms, args.form + "_newton_iters": stats["newton_iters"]}
+    if not args.no_forms and args.form == "batched":
+        pr = [asm.assemble(flags=flags | rrq.RRQ_F_PLAIN, stats=True) for _ in range(2)]
+        forms["plain_kernel_ms"] = float(np.mean([r["kernel_ms"] for r in pr]))
+        forms["plain_max_rel_weight_dev_vs_batched"] = max(
+            ((asm.out[k] - w_ref[k]).abs().max() / w_ref[k].abs().max()).item() for k in rrq.KERNELS)
+        forms["learned"] = learned_form(rrq, asm, flags, w_ref)
+        print(f"[bench] forms: {forms}", flush=True)
+        asm.assemble(flags=flags)      # leave the batched weights in the outputs
 
     q = int(surf["order"][0])
     alg_tflop = len(tg["near_patch"]) * flops_per_pair(q) / 1e12
-    achieved = alg_tflop / (asm_ms / 1e3)
+    achieved = alg_tflop / (kern_ms / 1e3)
+    tr = TRAFFIC if TRAFFIC["src_sha256"] == kernel_src_sha() else None
+    traffic = None
+    if tr is not None and args.form == "batched":
+        traffic = {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
+                   "GB_per_s": (tr["fetch_bytes"] + tr["write_bytes"]) / (kern_ms / 1e3) / 1e9}
     out = {
         "metric": METRIC, "value": value, "unit": "weights/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -177,12 +227,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "form": args.form, "graph": True, "autotune": tune,
                    "pairs": int(len(tg["near_patch"])),
-                   "weights_per_step": int(nweights), "assemble_ms": asm_ms,
+                   "weights_per_step": int(nweights), "kernel_ms": kern_ms,
                    "newton_iters_per_near_edge": stats["newton_iters"] / max(1, stats["near_edges"]),
-                   "near_edges": stats["near_edges"], "newton_fail": stats["newton_fail"]},
+                   "near_edges": stats["near_edges"], "newton_fail": stats["newton_fail"],
+                   "forms": forms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
-                     "kernel": (f"k_pair_plain<{q}>" if args.form == "plain" else f"k_pair_tile<{q},T>"),
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": traffic,
+                     "kernel": (f"k_pair_plain<{q}>" if args.form == "plain"
+                                else f"k_pair_tile<{q},{tune['tile_targets'] if tune else 'T'}>"),
                      "flops_per_pair": flops_per_pair(q)},
     }
     if not args.no_cpu_baseline:

@@ -139,14 +139,15 @@ static rrq_status upload_consts(rrq_plan* p, int q) {
   o.slp_ptr = (const int32_t*)b;
   if (!up(T.slp.data(), T.slp.size() * sizeof(Term), &b)) return RRQ_ERR_OOM;
   o.slp = (const Term*)b;
-  if (!up(T.lag_c.data(), T.lag_c.size() * 8, &b)) return RRQ_ERR_OOM;
-  o.lag_c = (const double*)b;
   for (int32_t v : T.mrg_ptr)
     if (v < 0) return RRQ_ERR_DEVICE;   // term tables inconsistent (cannot happen)
   if (!up(T.mrg_ptr.data(), T.mrg_ptr.size() * 4, &b)) return RRQ_ERR_OOM;
   o.mrg_ptr = (const int32_t*)b;
   if (!up(T.mrg.data(), T.mrg.size() * sizeof(Term2), &b)) return RRQ_ERR_OOM;
   o.mrg = (const Term2*)b;
+  if (!up(T.tslot.data(), T.tslot.size() * 4, &b)) return RRQ_ERR_OOM;
+  o.tslot = (const int32_t*)b;
+  o.nslot = (int)T.tslot.size();
   return RRQ_OK;
 }
 
@@ -364,9 +365,10 @@ static TargetsDev tdev(const rrq_targets* tg) {
 
 // workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders] u64 |
-// sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials
+// sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | guess[4 nnz] float2
 struct WsLayout {
-  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, total;
+  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, guess,
+      total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P) {
@@ -384,6 +386,7 @@ static WsLayout ws_layout(int64_t nnz, int P) {
   w.sorted = o; o = al(o + n * 8);
   w.tiles = o; o = al(o + (n / 4 + (size_t)P + 1) * 16);
   w.part = o; o = al(o + (size_t)scan_partials((int64_t)n) * 8);
+  w.guess = o; o = al(o + 4 * n * 8);
   w.total = o;
   return w;
 }
@@ -445,8 +448,22 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   ao.pair_off = pair_off;
   ao.owner = owner;
   ao.counters = counters;
+  ao.guess = nullptr;
   PlanDev pd = p->dev();
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (stats) {
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+  }
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } evg{ev};
   if (flags & RRQ_F_PLAIN) {
+    if (stats && hipEventRecord(ev[0], st) != hipSuccess) return RRQ_ERR_DEVICE;
     for (int qi = 0; qi < kNumOrders; ++qi) {
       const int q = kOrders[qi];
       if (p->patches_h[q].empty()) continue;
@@ -467,6 +484,16 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
     if (launch_binning(td, p->P, tile, p->perm_d, p->bin_orders, cnt, fill, start, tstart,
                        ntiles, sorted, tiles, qtile, qctr, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
+    if (flags & RRQ_F_LEARNED) {
+      CollectOpts co;
+      for (int q = 0; q <= kMaxQ; ++q) co.rho_far[q] = p->rho_far[q];
+      co.newton_tol = p->opt.newton_tol;
+      co.newton_maxit = p->opt.newton_maxit;
+      float2* guess = (float2*)(wb + wl.guess);
+      if (launch_guess(pd, td, owner, co, guess, st) != hipSuccess) return RRQ_ERR_DEVICE;
+      ao.guess = guess;
+    }
+    if (stats && hipEventRecord(ev[0], st) != hipSuccess) return RRQ_ERR_DEVICE;
     for (int qi = 0; qi < kNumOrders; ++qi) {
       const int q = kOrders[qi];
       if (p->patches_h[q].empty()) continue;
@@ -481,9 +508,12 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   }
   if (stats) {
     unsigned long long h[8];
-    if (hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+    float ms = 0.f;
+    if (hipEventRecord(ev[1], st) != hipSuccess ||
+        hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess || hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
       return RRQ_ERR_DEVICE;
+    stats->kernel_ms = ms;
     stats->pairs = tg->nnz;
     stats->near_edges = (int64_t)h[0];
     stats->newton_iters = (int64_t)h[1];

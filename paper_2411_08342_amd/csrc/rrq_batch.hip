@@ -163,7 +163,7 @@ __device__ __forceinline__ double reduce_scatter16(double* x) {
 }
 
 constexpr int kMaxLevel = 52;
-constexpr int kLearnedMaxit = 8;   // Newton iterations allowed from the learned start   // deepest dyadic level that still splits (panel width 2^-51)
+constexpr int kLearnedMaxit = 8;   // Newton iterations allowed from the learned start
 
 // Dyadic panels of [-1, 1] graded toward t0 = a + i b: a panel of half-width h and centre c
 // is split while (t0 - c) / h lies inside the Bernstein ellipse of radius rho (that is,
@@ -260,7 +260,7 @@ struct TileLds {
   static constexpr int NPAN = wave_panel_cap(Q);
   static constexpr int o_pan = o_gs + 2 * T * NR;          // [4 waves][NPAN][2]
   static constexpr int o_red = o_pan + 4 * NPAN * 2;
-  static constexpr int o_cst = o_red + 8;                  // gl_t, gl_w, lag_c [PT] each
+  static constexpr int o_cst = o_red + 8;                  // gl_t, gl_w, bary [PT] each
   static constexpr int n_dbl = o_cst + 3 * PT;
   // ints
   static constexpr int i_near = 0;                         // [T][4]
@@ -307,7 +307,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   double* pan = smem + L::o_pan;
   double* cgl_t = smem + L::o_cst;
   double* cgl_w = cgl_t + PT;
-  double* clag = cgl_w + PT;
+  double* cbary = cgl_w + PT;
   int* ints = (int*)(smem + L::n_dbl);
   int* snear = ints + L::i_near;
   int* sself = ints + L::i_self;
@@ -315,17 +315,12 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t tlo = qtile[0], thi = qtile[1];
   unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_max = 0, c_learn = 0;
-  const bool learned = (out.flags & RRQ_F_LEARNED) != 0 && pd.mlp != nullptr;
-  // network scratch of the learned guess, in the effective-weight area (free until then)
-  float* mx = (float*)(smem + L::o_td);          // [4T][8]
-  float* mh1 = mx + 4 * T * kMlpIn;              // [4T][64]
-  float* mh2 = mh1 + 4 * T * kMlpH;              // [4T][64]
-  float* mdt = mh2 + 4 * T * kMlpH;              // [4T][2]
-  static_assert(4 * T * (kMlpIn + 2 * kMlpH + kMlpOut) <= 2 * L::n_scrA, "network scratch");
+  // learned initial guesses t_s + dt of every (pair, edge), from the network pre-pass
+  const float2* guess = (out.flags & RRQ_F_LEARNED) ? out.guess : nullptr;
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
     cgl_w[tid] = od.gl_w[tid];
-    clag[tid] = od.lag_c[tid];
+    cbary[tid] = od.bary[tid];
   }
   for (;;) {
     __syncthreads();
@@ -404,41 +399,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
-      // ---- learned initial guess (RRQ_F_LEARNED): features of every (target, edge), then
-      // the network on all threads (float32, weights read from the plan)
-      if (learned) {
-        if (tid < 4 * nt) {
-          cplx tsd;
-          edge_features(ecoef + (tid & 3) * PT * 3, PT, sx + (tid >> 2) * 3, mx + tid * kMlpIn,
-                        &tsd);
-        }
-        __syncthreads();
-        const float* W = pd.mlp;
-        for (int idx = tid; idx < 4 * nt * kMlpH; idx += BNT) {
-          const int te = idx / kMlpH, u = idx % kMlpH;
-          float a = W[kMlpB1 + u];
-#pragma unroll
-          for (int c = 0; c < kMlpIn; ++c) a += W[kMlpW1 + c * kMlpH + u] * mx[te * kMlpIn + c];
-          mh1[idx] = tanhf(a);
-        }
-        __syncthreads();
-        for (int idx = tid; idx < 4 * nt * kMlpH; idx += BNT) {
-          const int te = idx / kMlpH, u = idx % kMlpH;
-          float a = W[kMlpB2 + u];
-#pragma unroll 8
-          for (int k = 0; k < kMlpH; ++k) a += W[kMlpW2 + k * kMlpH + u] * mh1[te * kMlpH + k];
-          mh2[idx] = tanhf(a);
-        }
-        __syncthreads();
-        if (tid < 4 * nt * kMlpOut) {
-          const int te = tid / kMlpOut, o = tid % kMlpOut;
-          float a = W[kMlpB3 + o];
-#pragma unroll 8
-          for (int k = 0; k < kMlpH; ++k) a += W[kMlpW3 + o * kMlpH + k] * mh2[te * kMlpH + k];
-          mdt[tid] = a;
-        }
-        __syncthreads();
-      }
       // ---- Step 5: per (target, edge) classification and Newton root (wave 0); Step 4:
       // target harmonics (wave 1) at the same time
       if (tid < 4 * nt) {
@@ -451,31 +411,33 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         int near = 0;
         cplx t0 = ts;
         if (bernstein_rho(ts) <= so.rho_far) {
-          int done = 0, its_all = 0;
-          if (learned) {
-            cplx tl = mk(ts.re + (double)mdt[tid * 2], ts.im + (double)mdt[tid * 2 + 1]);
-            if (isfinite(tl.re) && isfinite(tl.im)) {
-              int its;
-              const int conv = newton_solve(cf, PT, xl, &tl, so.newton_tol, kLearnedMaxit, &its);
-              its_all += its;
-              if (tl.im < 0) tl.im = -tl.im;
-              if (conv && bernstein_rho(tl) <= so.rho_far) {
-                t0 = tl;
-                near = 1;
-                done = 1;
-                ++c_learn;
-              }
-            }
+          // attempt 0: Newton from the learned start (at most kLearnedMaxit iterations),
+          // accepted if it converges inside the ellipse; attempt 1: plain Newton from t_s
+          cplx tl = ts;
+          int first = 1;
+          if (guess) {
+            const float2 gd = guess[4 * sorted[tile.y + sub + t] + e];
+            tl = mk(ts.re + (double)gd.x, ts.im + (double)gd.y);
+            if (isfinite(tl.re) && isfinite(tl.im)) first = 0;
           }
-          if (!done) {
+          int its_all = 0;
+          for (int attempt = first; attempt < 2; ++attempt) {
+            cplx tp = attempt == 0 ? tl : ts;
             int its;
-            cplx tp = ts;
-            const int conv = newton_solve(cf, PT, xl, &tp, so.newton_tol, so.newton_maxit, &its);
+            const int conv = newton_solve(cf, PT, xl, &tp, so.newton_tol,
+                                          attempt == 0 ? kLearnedMaxit : so.newton_maxit, &its);
             its_all += its;
             if (tp.im < 0) tp.im = -tp.im;
+            const int inside = conv && bernstein_rho(tp) <= so.rho_far;
+            if (attempt == 0) {
+              if (!inside) continue;
+              ++c_learn;
+            } else if (!conv) {
+              ++c_fail;
+            }
             t0 = tp;
-            if (conv && bernstein_rho(tp) <= so.rho_far) near = 1;
-            if (!conv) ++c_fail;
+            near = inside;
+            break;
           }
           c_iters += (unsigned long long)its_all;
           if ((unsigned long long)its_all > c_max) c_max = its_all;
@@ -524,31 +486,29 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             leg3r(ecoef + e * PT * 3, PT, tau, r, dr);
             om += hw * omega0_at(sx + t * 3, su + t * 3, r, dr);
           }
-          // Lagrange basis at tau in product form, l_i = c_i prod_{j != i} (tau - t_j), by
-          // prefix and suffix products, 8 nodes at a time
-          double pre = 1.0;                  // prod_{j < 8 bI} (tau - t_j)
+          // Lagrange basis at tau, barycentric form
+          double den = 0.0;
+          int hit = -1;
+#pragma unroll
+          for (int j = 0; j < PT; ++j) {
+            const double dtj = tau - cgl_t[j];
+            if (dtj == 0.0) hit = j;
+            else den += cbary[j] / dtj;
+          }
+          const double rden = 1.0 / den;
 #pragma unroll
           for (int bI = 0; bI < NB8; ++bI) {
-            const int i0 = bI * 8;
-            double suf = 1.0;                // prod_{j >= i0 + 8} (tau - t_j)
-            for (int j = i0 + 8; j < PT; ++j) suf *= tau - cgl_t[j];
             double x[16];
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
-              x[v] = pre;
-              if (i0 + v < PT) pre *= tau - cgl_t[i0 + v];
-            }
-#pragma unroll
-            for (int v = 7; v >= 0; --v) {
-              if (i0 + v < PT) {
-                const double l = x[v] * suf * clag[i0 + v];
-                suf *= tau - cgl_t[i0 + v];
-                x[v] = w1p * l;
-                x[8 + v] = w3p * l;
-              } else {
-                x[v] = 0.0;
-                x[8 + v] = 0.0;
+              const int i = bI * 8 + v;
+              double l = 0.0;
+              if (i < PT) {
+                if (hit >= 0) l = hit == i ? 1.0 : 0.0;
+                else l = cbary[i] / (tau - cgl_t[i]) * rden;
               }
+              x[v] = w1p * l;
+              x[8 + v] = w3p * l;
             }
             lacc[bI] += reduce_scatter16(x);
           }
@@ -698,22 +658,32 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
-      // ---- Steps 7-8: translation and rows, items (target, l, m)
-      for (int idx = tid; idx < nt * NP; idx += BNT) {
-        const int t = idx / NP, lm = idx % NP;
+      // ---- Steps 7-8: translation and rows, items (target, slot): a slot holds the term list
+      // of one (l, m) or half of a long one; the two halves of a list sit on adjacent lanes
+      // and are added with one lane exchange
+      for (int idx = tid; idx < T * od.nslot; idx += BNT) {
+        const int t = idx / od.nslot, code = od.tslot[idx % od.nslot];
+        const int lm = code & 0xff, kind = code >> 8;
+        const bool act = t < nt && kind != 3;
         int l = 1;
         while (np_of(l) <= lm) ++l;
         const int m = lm - np_of(l - 1) + 1;
-        const cplx* R = Rt + t * NR;
-        const cplx* G = gS + t * NR;
-        const double* VQ = vq + t * NJK * 18;
+        const int tt = t < nt ? t : 0;
+        const cplx* R = Rt + tt * NR;
+        const cplx* G = gS + tt * NR;
+        const double* VQ = vq + tt * NJK * 18;
         cplx Ia[4] = {mk(0, 0), mk(0, 0), mk(0, 0), mk(0, 0)};
         cplx dIa[4] = {mk(0, 0), mk(0, 0), mk(0, 0), mk(0, 0)};
         cplx sl = mk(0, 0);
         // one pass over the (j, k) terms of this (l, m): single-layer sum (weights D_{j,l})
         // and double-layer sums (weights C_{j,l}, zero for j = 1)
-        const int m_end = od.mrg_ptr[lm + 1];
-        for (int it = od.mrg_ptr[lm]; it < m_end; ++it) {
+        int it0 = od.mrg_ptr[lm], it1 = od.mrg_ptr[lm + 1];
+        const int mid = (it0 + it1) >> 1;
+        if (kind == 1) it1 = mid;
+        else if (kind == 2) it0 = mid;
+        if (!act) it1 = it0;
+#pragma unroll 2
+        for (int it = it0; it < it1; ++it) {
           const Term2 tm = od.mrg[it];
           const cplx s_ = rget(R, tm.a, tm.b);
           const cplx cs = tm.cD * s_;
@@ -729,6 +699,18 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             dIa[c] = dIa[c] + (dX * cs + X * cg);
           }
         }
+        // first half += second half (the partner lane is idx ^ 1)
+        {
+          double o;
+#define RRQ_ADD_HALF(v) o = __shfl_xor(v, 1, 64); if (kind == 1) v += o;
+          for (int c = 0; c < 4; ++c) {
+            RRQ_ADD_HALF(Ia[c].re) RRQ_ADD_HALF(Ia[c].im)
+            RRQ_ADD_HALF(dIa[c].re) RRQ_ADD_HALF(dIa[c].im)
+          }
+          RRQ_ADD_HALF(sl.re) RRQ_ADD_HALF(sl.im)
+#undef RRQ_ADD_HALF
+        }
+        if (!act || kind == 2) continue;
         const double* nu = snu + t * 3;
         // gradient of S^{lm} and its normal derivative: nu'.grad (d_a S^{lm}) is the same
         // ladder combination applied to the table nu'.grad S^{ab}

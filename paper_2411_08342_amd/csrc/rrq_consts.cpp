@@ -122,14 +122,6 @@ OrderTables build_order_tables(int q, int pt) {
     T.bary[i] = (double)((i & 1 ? -1.0L : 1.0L) * sqrtl((1 - ti * ti) * (long double)T.gl_w[i]));
   }
 
-  T.lag_c.assign(pt, 0.0);
-  for (int i = 0; i < pt; ++i) {
-    long double pr = 1;
-    for (int j = 0; j < pt; ++j)
-      if (j != i) pr *= (long double)T.gl_t[i] - (long double)T.gl_t[j];
-    T.lag_c[i] = (double)(1.0L / pr);
-  }
-
   // translation terms, grouped by basis function (l, m), 1 <= m <= l <= q
   T.dlp_ptr.assign(1, 0);
   T.slp_ptr.assign(1, 0);
@@ -184,6 +176,21 @@ OrderTables build_order_tables(int q, int pt) {
     T.mrg_ptr.push_back((int32_t)T.mrg.size());
     if (d != T.dlp_ptr[lm + 1]) T.mrg_ptr.back() = -1;   // not a subset: flagged for the caller
   }
+  // translation slots: term lists longer than half of the longest are split in two halves,
+  // so that no slot carries much more than half of the longest list
+  int maxlen = 0;
+  for (int lm = 0; lm < T.np; ++lm) maxlen = std::max(maxlen, T.mrg_ptr[lm + 1] - T.mrg_ptr[lm]);
+  for (int lm = 0; lm < T.np; ++lm) {
+    const int len = T.mrg_ptr[lm + 1] - T.mrg_ptr[lm];
+    if (2 * len > maxlen + 1) {
+      if (T.tslot.size() & 1) T.tslot.push_back(3 << 8);
+      T.tslot.push_back(lm | (1 << 8));
+      T.tslot.push_back(lm | (2 << 8));
+    } else {
+      T.tslot.push_back(lm);
+    }
+  }
+  if (T.tslot.size() & 1) T.tslot.push_back(3 << 8);
   return T;
 }
 

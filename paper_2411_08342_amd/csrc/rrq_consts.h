@@ -43,11 +43,14 @@ struct OrderTables {
   std::vector<double> DP;             // [pt][pt]: DP[i*pt + k] = P_k'(t_i)
   std::vector<double> lag_m1;         // l_i(-1)
   std::vector<double> bary;           // barycentric weights (-1)^i sqrt((1 - t_i^2) w_i)
-  std::vector<double> lag_c;          // 1 / prod_{j != i} (t_i - t_j) (product-form Lagrange)
   std::vector<int32_t> dlp_ptr, slp_ptr;   // [np+1]
   std::vector<Term> dlp, slp;
   std::vector<int32_t> mrg_ptr;        // [np+1]
   std::vector<Term2> mrg;
+  // work slots of the translation step: lm | kind << 8, kind 0 = whole term list, 1 / 2 =
+  // first / second half (the two halves sit at an even and the next odd slot), 3 = padding;
+  // even length
+  std::vector<int32_t> tslot;
 };
 
 void gauss_legendre_ld(int n, std::vector<double>& t, std::vector<double>& w);

@@ -191,45 +191,137 @@ __global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
 }
 
 // ---------------------------------------------------------------------------------------
-// Weighted least squares by Householder QR on a row-major m x ncols matrix in global
-// workspace (first n columns: system, the rest: right-hand sides).  On exit the RHS columns
-// hold the solution in rows 0..n-1.
+// Least squares by blocked Householder QR (compact WY form) on a row-major m x ncols matrix
+// in global workspace: the first n columns are the system, the rest right-hand sides.  Each
+// panel of HNB columns is factorised in LDS; its reflectors H_1 ... H_nb = I - V T V^T are
+// then applied to all later columns in one pass (C <- C - V T^T V^T C), so the trailing
+// matrix is read and written once per panel.  On exit the right-hand-side columns hold the
+// solution in rows 0..n-1 (back substitution with R).
+// LDS: V [m][HNB], T [HNB][HNB], G [HNB][HNB], red [NT/64][HNB], beta [HNB], alpha [HNB].
 // ---------------------------------------------------------------------------------------
-__device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* sv, double* red) {
-  for (int k = 0; k < n; ++k) {
-    double part = 0.0;
-    for (int r = k + threadIdx.x; r < m; r += NT) {
-      const double a = A[(int64_t)r * ld + k];
-      part += a * a;
-    }
-    const double nrm2 = block_sum<NT>(part, red);
-    const double akk = A[(int64_t)k * ld + k];
-    const double nrm = sqrt(nrm2);
-    const double alpha = akk >= 0.0 ? -nrm : nrm;
-    const double vtv = 2.0 * nrm * (nrm + fabs(akk));
-    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-    for (int r = k + threadIdx.x; r < m; r += NT)
-      sv[r - k] = (r == k) ? akk - alpha : A[(int64_t)r * ld + k];
-    __syncthreads();
-    for (int j = k + 1 + threadIdx.x; j < ncols; j += NT) {
-      // 8 independent partial sums keep 8 loads in flight
-      double ps[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      int r = k;
-      for (; r + 8 <= m; r += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) ps[u] += sv[r + u - k] * A[(int64_t)(r + u) * ld + j];
-      }
-      for (; r < m; ++r) ps[0] += sv[r - k] * A[(int64_t)r * ld + j];
-      const double sdot = beta * (((ps[0] + ps[1]) + (ps[2] + ps[3])) + ((ps[4] + ps[5]) + (ps[6] + ps[7])));
-      r = k;
-      for (; r + 8 <= m; r += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) A[(int64_t)(r + u) * ld + j] -= sdot * sv[r + u - k];
-      }
-      for (; r < m; ++r) A[(int64_t)r * ld + j] -= sdot * sv[r - k];
+constexpr int HNB = 16;
+
+__device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, double* T,
+                       double* G, double* red, double* beta, double* alpha) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int k0 = 0; k0 < n; k0 += HNB) {
+    const int nb = min(HNB, n - k0);
+    const int mr = m - k0;
+    for (int idx = tid; idx < mr * HNB; idx += NT) {
+      const int r = idx / HNB, c = idx % HNB;
+      V[idx] = c < nb ? A[(int64_t)(k0 + r) * ld + k0 + c] : 0.0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) A[(int64_t)k * ld + k] = alpha;
+    // unblocked factorisation of the panel
+    for (int c = 0; c < nb; ++c) {
+      double part = 0.0;
+      for (int r = c + tid; r < mr; r += NT) {
+        const double a = V[r * HNB + c];
+        part += a * a;
+      }
+      const double nrm2 = block_sum<NT>(part, red);
+      const double akk = V[c * HNB + c];
+      const double nrm = sqrt(nrm2);
+      const double al = akk >= 0.0 ? -nrm : nrm;
+      const double vtv = 2.0 * nrm * (nrm + fabs(akk));
+      const double be = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      __syncthreads();
+      if (tid == 0) {
+        V[c * HNB + c] = akk - al;
+        beta[c] = be;
+        alpha[c] = al;
+      }
+      __syncthreads();
+      // w_j = v . V[:, j] for the panel columns c < j < nb (other columns get w_j = 0 and
+      // are left unchanged), then V[:, j] -= beta w_j v
+      double w[HNB];
+#pragma unroll
+      for (int j = 0; j < HNB; ++j) w[j] = 0.0;
+      for (int r = c + tid; r < mr; r += NT) {
+        const double vr = V[r * HNB + c];
+#pragma unroll
+        for (int j = 0; j < HNB; ++j) w[j] += vr * V[r * HNB + j];
+      }
+#pragma unroll
+      for (int j = 0; j < HNB; ++j) {
+        const double sj = wave_sum(w[j]);
+        if (lane == 0) red[wv * HNB + j] = sj;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < HNB; ++j) {
+        double sj = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) sj += red[q * HNB + j];
+        w[j] = (j > c && j < nb) ? be * sj : 0.0;
+      }
+      for (int r = c + tid; r < mr; r += NT) {
+        const double vr = V[r * HNB + c];
+#pragma unroll
+        for (int j = 0; j < HNB; ++j) V[r * HNB + j] -= w[j] * vr;
+      }
+      __syncthreads();
+    }
+    // R of the panel back to A (strict upper part from V, diagonal alpha); then V keeps only
+    // the reflectors (zero above the diagonal)
+    for (int idx = tid; idx < nb * nb; idx += NT) {
+      const int r = idx / nb, c = idx % nb;
+      if (r < c) A[(int64_t)(k0 + r) * ld + k0 + c] = V[r * HNB + c];
+      else if (r == c) A[(int64_t)(k0 + r) * ld + k0 + c] = alpha[c];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < HNB * HNB; idx += NT) {
+      const int r = idx / HNB, c = idx % HNB;
+      if (r < c && r < mr) V[r * HNB + c] = 0.0;
+    }
+    __syncthreads();
+    // G[l][i] = v_l . v_i (l < i), then T (forward, columnwise)
+    for (int idx = tid; idx < HNB * HNB; idx += NT) {
+      const int l = idx / HNB, i = idx % HNB;
+      double g = 0.0;
+      if (l < i && i < nb)
+        for (int r = i; r < mr; ++r) g += V[r * HNB + l] * V[r * HNB + i];
+      G[idx] = g;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = 0; i < HNB; ++i)
+        for (int j = 0; j < HNB; ++j) T[j * HNB + i] = 0.0;
+      for (int i = 0; i < nb; ++i) {
+        T[i * HNB + i] = beta[i];
+        for (int j = 0; j < i; ++j) {
+          double acc = 0.0;
+          for (int l = j; l < i; ++l) acc += T[j * HNB + l] * G[l * HNB + i];
+          T[j * HNB + i] = -beta[i] * acc;
+        }
+      }
+    }
+    __syncthreads();
+    // trailing update of every later column: C <- C - V T^T V^T C, one column per thread
+    for (int j = k0 + nb + tid; j < ncols; j += NT) {
+      double w[HNB];
+#pragma unroll
+      for (int c = 0; c < HNB; ++c) w[c] = 0.0;
+      for (int r = 0; r < mr; ++r) {
+        const double a = A[(int64_t)(k0 + r) * ld + j];
+#pragma unroll
+        for (int c = 0; c < HNB; ++c) w[c] += V[r * HNB + c] * a;
+      }
+      double wt[HNB];
+#pragma unroll
+      for (int c = 0; c < HNB; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l <= c; ++l) acc += T[l * HNB + c] * w[l];
+        wt[c] = acc;
+      }
+      for (int r = 0; r < mr; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < HNB; ++c) acc += V[r * HNB + c] * wt[c];
+        A[(int64_t)(k0 + r) * ld + j] -= acc;
+      }
+    }
     __syncthreads();
   }
   for (int j = n + threadIdx.x; j < ncols; j += NT) {
@@ -267,8 +359,8 @@ __global__ __launch_bounds__(NT) void k_fit(PlanDev pd, OrderDev od, const int32
   constexpr int M = 4 * Q2;
   constexpr int LDA = 4 * NP + Q2;
   constexpr int LDB = NP + Q2;
-  __shared__ double sv[M];
-  __shared__ double red[NT / 64];
+  __shared__ double sV[M * HNB];
+  __shared__ double sT[HNB * HNB], sG[HNB * HNB], sred[NT / 64 * HNB], sbeta[HNB], salpha[HNB];
   double* A = ws + (int64_t)blockIdx.x * ws_per_block;
   double* B = A + (int64_t)M * LDA;
   double* Hm = B + (int64_t)Q2 * LDB;
@@ -313,8 +405,8 @@ __global__ __launch_bounds__(NT) void k_fit(PlanDev pd, OrderDev od, const int32
       B[(int64_t)i * LDB + NP + i] = om;
     }
     __syncthreads();
-    hh_lsq(A, M, 4 * NP, LDA, LDA, sv, red);
-    hh_lsq(B, Q2, NP, LDB, LDB, sv, red);
+    hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sT, sG, sred, sbeta, salpha);
+    hh_lsq(B, Q2, NP, LDB, LDB, sV, sT, sG, sred, sbeta, salpha);
     double* maps = pd.maps + pd.map_off[P];
     double* MD = maps;
     double* MSp = maps + 4 * NP * Q2;

@@ -20,13 +20,14 @@ struct OrderDev {
   const double* DP;         // Legendre derivatives at the GL nodes
   const double* lag_m1;
   const double* bary;       // barycentric weights of the ptilde GL nodes
-  const double* lag_c;      // product-form Lagrange normalisation 1 / prod_{j != i}(t_i - t_j)
   const int32_t* dlp_ptr;
   const Term* dlp;
   const int32_t* slp_ptr;
   const Term* slp;
   const int32_t* mrg_ptr;
   const Term2* mrg;
+  const int32_t* tslot;     // translation work slots (see OrderTables::tslot)
+  int nslot;
 };
 
 // per-patch data layout constants
@@ -71,6 +72,7 @@ struct AssembleOut {
   const int64_t* pair_off;
   const int64_t* owner;     // [nnz] target of each pair
   unsigned long long* counters;   // [8] stats
+  const float2* guess;      // [4 nnz] learned Newton-start offsets (RRQ_F_LEARNED) or null
 };
 
 struct SolveOpts {
@@ -143,5 +145,7 @@ hipError_t mlp_loss_grad_run(const float* params, const float* feat, const float
 hipError_t mlp_predict_run(const float* params, const float* feat, int64_t n, float* out,
                            hipStream_t st);
 hipError_t mlp_pack_run(const float* params, float* dst, hipStream_t st);
+hipError_t launch_guess(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
+                        const CollectOpts& co, float2* guess, hipStream_t st);
 
 }  // namespace rrq

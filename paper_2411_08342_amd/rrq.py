@@ -53,10 +53,12 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("near_edges", ctypes.c_int64),
                 ("newton_iters", ctypes.c_int64), ("newton_fail", ctypes.c_int64),
-                ("learned_accept", ctypes.c_int64), ("newton_max", ctypes.c_int64)]
+                ("learned_accept", ctypes.c_int64), ("newton_max", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float(getattr(self, k)) if k == "kernel_ms" else int(getattr(self, k)))
+                for k, _ in self._fields_}
 
 
 class MlpCfg(ctypes.Structure):
