@@ -192,17 +192,21 @@ __global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
 
 // ---------------------------------------------------------------------------------------
 // Least squares by blocked Householder QR (compact WY form) on a row-major m x ncols matrix
-// in global workspace: the first n columns are the system, the rest right-hand sides.  Each
-// panel of HNB columns is factorised in LDS; its reflectors H_1 ... H_nb = I - V T V^T are
-// then applied to all later columns in one pass (C <- C - V T^T V^T C), so the trailing
-// matrix is read and written once per panel.  On exit the right-hand-side columns hold the
-// solution in rows 0..n-1 (back substitution with R).
-// LDS: V [m][HNB], T [HNB][HNB], G [HNB][HNB], red [NT/64][HNB], beta [HNB], alpha [HNB].
+// in global workspace: the first n columns are the system, the rest right-hand sides.
+//  - each panel of HNB columns is copied to LDS and factorised by one wave (lane l owns the
+//    panel rows r = l mod 64; reductions by lane exchanges, no workgroup barriers);
+//  - its reflectors H_1 ... H_nb = I - V T V^T are applied to every later column in one pass
+//    (C <- C - V T^T V^T C, one column per thread, loads issued 8 rows ahead);
+//  - the right-hand sides are then solved with R by column sweeps, kBackCols columns at a
+//    time held in LDS.
+// On exit the right-hand-side columns hold the solution in rows 0..n-1.
+// LDS: V [m][HNB], T [HNB][HNB], G [HNB][HNB], beta [HNB], alpha [HNB], X [n][kBackCols].
 // ---------------------------------------------------------------------------------------
 constexpr int HNB = 16;
+constexpr int kBackCols = 32;
 
-__device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, double* T,
-                       double* G, double* red, double* beta, double* alpha) {
+__device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, double* T,
+                       double* G, double* beta, double* alpha, double* X) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int k0 = 0; k0 < n; k0 += HNB) {
     const int nb = min(HNB, n - k0);
@@ -212,56 +216,49 @@ __device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, do
       V[idx] = c < nb ? A[(int64_t)(k0 + r) * ld + k0 + c] : 0.0;
     }
     __syncthreads();
-    // unblocked factorisation of the panel
-    for (int c = 0; c < nb; ++c) {
-      double part = 0.0;
-      for (int r = c + tid; r < mr; r += NT) {
-        const double a = V[r * HNB + c];
-        part += a * a;
-      }
-      const double nrm2 = block_sum<NT>(part, red);
-      const double akk = V[c * HNB + c];
-      const double nrm = sqrt(nrm2);
-      const double al = akk >= 0.0 ? -nrm : nrm;
-      const double vtv = 2.0 * nrm * (nrm + fabs(akk));
-      const double be = vtv > 0.0 ? 2.0 / vtv : 0.0;
-      __syncthreads();
-      if (tid == 0) {
-        V[c * HNB + c] = akk - al;
-        beta[c] = be;
-        alpha[c] = al;
-      }
-      __syncthreads();
-      // w_j = v . V[:, j] for the panel columns c < j < nb (other columns get w_j = 0 and
-      // are left unchanged), then V[:, j] -= beta w_j v
-      double w[HNB];
+    if (wv == 0) {
+      for (int c = 0; c < nb; ++c) {
+        double part = 0.0;
+        for (int r = lane; r < mr; r += 64)
+          if (r >= c) {
+            const double a = V[r * HNB + c];
+            part += a * a;
+          }
+        const double nrm2 = wave_sum(part);
+        const double akk = V[c * HNB + c];
+        const double nrm = sqrt(nrm2);
+        const double al = akk >= 0.0 ? -nrm : nrm;
+        const double vtv = 2.0 * nrm * (nrm + fabs(akk));
+        const double be = vtv > 0.0 ? 2.0 / vtv : 0.0;
+        // w_j = v . V[:, j]; only c < j < nb are used (the others get 0: unchanged)
+        double w[HNB];
 #pragma unroll
-      for (int j = 0; j < HNB; ++j) w[j] = 0.0;
-      for (int r = c + tid; r < mr; r += NT) {
-        const double vr = V[r * HNB + c];
+        for (int j = 0; j < HNB; ++j) w[j] = 0.0;
+        for (int r = lane; r < mr; r += 64)
+          if (r >= c) {
+            const double vr = r == c ? akk - al : V[r * HNB + c];
 #pragma unroll
-        for (int j = 0; j < HNB; ++j) w[j] += vr * V[r * HNB + j];
+            for (int j = 0; j < HNB; ++j) w[j] += vr * V[r * HNB + j];
+          }
+#pragma unroll
+        for (int j = 0; j < HNB; ++j) w[j] = (j > c && j < nb) ? be * wave_sum(w[j]) : 0.0;
+        for (int r = lane; r < mr; r += 64)
+          if (r >= c) {
+            const double vr = r == c ? akk - al : V[r * HNB + c];
+#pragma unroll
+            for (int j = 0; j < HNB; ++j) V[r * HNB + j] -= w[j] * vr;
+            if (r == c) V[r * HNB + c] = vr;
+          }
+        if (lane == 0) {
+          beta[c] = be;
+          alpha[c] = al;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-#pragma unroll
-      for (int j = 0; j < HNB; ++j) {
-        const double sj = wave_sum(w[j]);
-        if (lane == 0) red[wv * HNB + j] = sj;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < HNB; ++j) {
-        double sj = 0.0;
-#pragma unroll
-        for (int q = 0; q < NT / 64; ++q) sj += red[q * HNB + j];
-        w[j] = (j > c && j < nb) ? be * sj : 0.0;
-      }
-      for (int r = c + tid; r < mr; r += NT) {
-        const double vr = V[r * HNB + c];
-#pragma unroll
-        for (int j = 0; j < HNB; ++j) V[r * HNB + j] -= w[j] * vr;
-      }
-      __syncthreads();
     }
+    __syncthreads();
     // R of the panel back to A (strict upper part from V, diagonal alpha); then V keeps only
     // the reflectors (zero above the diagonal)
     for (int idx = tid; idx < nb * nb; idx += NT) {
@@ -275,26 +272,42 @@ __device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, do
       if (r < c && r < mr) V[r * HNB + c] = 0.0;
     }
     __syncthreads();
-    // G[l][i] = v_l . v_i (l < i), then T (forward, columnwise)
-    for (int idx = tid; idx < HNB * HNB; idx += NT) {
-      const int l = idx / HNB, i = idx % HNB;
+    // G[l][i] = v_l . v_i for l < i, two threads per entry (alternate rows)
+    {
+      const int pidx = tid >> 1, h = tid & 1;
+      int l = 0, i = 1, cnt = 0;
+      for (int ii = 1; ii < HNB; ++ii)
+        for (int ll = 0; ll < ii; ++ll, ++cnt)
+          if (cnt == pidx) { l = ll; i = ii; }
       double g = 0.0;
-      if (l < i && i < nb)
-        for (int r = i; r < mr; ++r) g += V[r * HNB + l] * V[r * HNB + i];
-      G[idx] = g;
+      if (pidx < HNB * (HNB - 1) / 2 && i < nb)
+        for (int r = i + h; r < mr; r += 2) g += V[r * HNB + l] * V[r * HNB + i];
+      g += __shfl_xor(g, 1, 64);
+      if (pidx < HNB * (HNB - 1) / 2 && h == 0) G[l * HNB + i] = g;
     }
     __syncthreads();
-    if (tid == 0) {
-      for (int i = 0; i < HNB; ++i)
-        for (int j = 0; j < HNB; ++j) T[j * HNB + i] = 0.0;
-      for (int i = 0; i < nb; ++i) {
-        T[i * HNB + i] = beta[i];
-        for (int j = 0; j < i; ++j) {
-          double acc = 0.0;
-          for (int l = j; l < i; ++l) acc += T[j * HNB + l] * G[l * HNB + i];
-          T[j * HNB + i] = -beta[i] * acc;
+    // T (forward, columnwise): lane j of wave 0 builds row j of T in registers
+    if (tid < HNB) {
+      const int j = tid;
+      double trow[HNB];
+#pragma unroll
+      for (int i = 0; i < HNB; ++i) {
+        double v = 0.0;
+        if (i < nb) {
+          if (i == j) {
+            v = beta[i];
+          } else if (i > j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < i; ++l)
+              if (l >= j) acc += trow[l] * G[l * HNB + i];
+            v = -beta[i] * acc;
+          }
         }
+        trow[i] = v;
       }
+#pragma unroll
+      for (int i = 0; i < HNB; ++i) T[j * HNB + i] = trow[i];
     }
     __syncthreads();
     // trailing update of every later column: C <- C - V T^T V^T C, one column per thread
@@ -302,7 +315,19 @@ __device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, do
       double w[HNB];
 #pragma unroll
       for (int c = 0; c < HNB; ++c) w[c] = 0.0;
-      for (int r = 0; r < mr; ++r) {
+      int r = 0;
+      for (; r + 8 <= mr; r += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(k0 + r + u) * ld + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          asm volatile("" ::: "memory");   // one row of V in registers at a time
+#pragma unroll
+          for (int c = 0; c < HNB; ++c) w[c] += V[(r + u) * HNB + c] * a[u];
+        }
+      }
+      for (; r < mr; ++r) {
         const double a = A[(int64_t)(k0 + r) * ld + j];
 #pragma unroll
         for (int c = 0; c < HNB; ++c) w[c] += V[r * HNB + c] * a;
@@ -315,7 +340,21 @@ __device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, do
         for (int l = 0; l <= c; ++l) acc += T[l * HNB + c] * w[l];
         wt[c] = acc;
       }
-      for (int r = 0; r < mr; ++r) {
+      r = 0;
+      for (; r + 8 <= mr; r += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(k0 + r + u) * ld + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          asm volatile("" ::: "memory");
+          double acc = 0.0;
+#pragma unroll
+          for (int c = 0; c < HNB; ++c) acc += V[(r + u) * HNB + c] * wt[c];
+          A[(int64_t)(k0 + r + u) * ld + j] = a[u] - acc;
+        }
+      }
+      for (; r < mr; ++r) {
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < HNB; ++c) acc += V[r * HNB + c] * wt[c];
@@ -324,14 +363,29 @@ __device__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, do
     }
     __syncthreads();
   }
-  for (int j = n + threadIdx.x; j < ncols; j += NT) {
-    for (int r = n - 1; r >= 0; --r) {
-      double acc = A[(int64_t)r * ld + j];
-      for (int c = r + 1; c < n; ++c) acc -= A[(int64_t)r * ld + c] * A[(int64_t)c * ld + j];
-      A[(int64_t)r * ld + j] = acc / A[(int64_t)r * ld + r];
+  // back substitution R x = b for the right-hand sides, kBackCols columns per sweep
+  for (int j0 = n; j0 < ncols; j0 += kBackCols) {
+    const int cw = min(kBackCols, ncols - j0);
+    for (int idx = tid; idx < n * kBackCols; idx += NT) {
+      const int r = idx / kBackCols, jj = idx % kBackCols;
+      X[idx] = jj < cw ? A[(int64_t)r * ld + j0 + jj] : 0.0;
     }
+    __syncthreads();
+    for (int c = n - 1; c >= 0; --c) {
+      if (tid < kBackCols) X[c * kBackCols + tid] /= A[(int64_t)c * ld + c];
+      __syncthreads();
+      for (int idx = tid; idx < c * kBackCols; idx += NT) {
+        const int r = idx / kBackCols, jj = idx % kBackCols;
+        X[idx] -= A[(int64_t)r * ld + c] * X[c * kBackCols + jj];
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < n * kBackCols; idx += NT) {
+      const int r = idx / kBackCols, jj = idx % kBackCols;
+      if (jj < cw) A[(int64_t)r * ld + j0 + jj] = X[idx];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 int64_t fit_ws_doubles(int q) {
@@ -360,7 +414,8 @@ __global__ __launch_bounds__(NT) void k_fit(PlanDev pd, OrderDev od, const int32
   constexpr int LDA = 4 * NP + Q2;
   constexpr int LDB = NP + Q2;
   __shared__ double sV[M * HNB];
-  __shared__ double sT[HNB * HNB], sG[HNB * HNB], sred[NT / 64 * HNB], sbeta[HNB], salpha[HNB];
+  __shared__ double sX[4 * NP * kBackCols];
+  __shared__ double sT[HNB * HNB], sG[HNB * HNB], sbeta[HNB], salpha[HNB];
   double* A = ws + (int64_t)blockIdx.x * ws_per_block;
   double* B = A + (int64_t)M * LDA;
   double* Hm = B + (int64_t)Q2 * LDB;
@@ -405,8 +460,8 @@ __global__ __launch_bounds__(NT) void k_fit(PlanDev pd, OrderDev od, const int32
       B[(int64_t)i * LDB + NP + i] = om;
     }
     __syncthreads();
-    hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sT, sG, sred, sbeta, salpha);
-    hh_lsq(B, Q2, NP, LDB, LDB, sV, sT, sG, sred, sbeta, salpha);
+    hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sT, sG, sbeta, salpha, sX);
+    hh_lsq(B, Q2, NP, LDB, LDB, sV, sT, sG, sbeta, salpha, sX);
     double* maps = pd.maps + pd.map_off[P];
     double* MD = maps;
     double* MSp = maps + 4 * NP * Q2;
