@@ -1,0 +1,87 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch configuration the
+benchmark times (batched form, autotuned tile and grid, correction weights, principal value
+on the surface): sampled pair blocks against the oracle, with the gates of the parity tests.
+Only the sampled blocks leave the device."""
+import numpy as np
+import pytest
+
+from paper_2411_08342_amd import workloads as wl
+from test_gpu_parity import _compare, KERNELS
+
+pytestmark = pytest.mark.gpu
+
+
+class _Blocks:
+    """Slices of a device weight array, copied to the host on demand."""
+
+    def __init__(self, t):
+        self.t = t
+
+    def __getitem__(self, s):
+        return self.t[s].cpu().numpy()
+
+
+def _assemble_bench_config(surf, tg):
+    import torch
+    from paper_2411_08342_amd import rrq
+    ds = rrq.DeviceSurface(surf)
+    dt = rrq.DeviceTargets(tg)
+    plan = rrq.Plan(ds)
+    asm = rrq.Assembler(plan, dt)
+    flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    tune = rrq.autotune(asm, flags)
+    stats = asm.assemble(flags=flags, stats=True)
+    torch.cuda.synchronize()
+    print(f"autotune {tune}; stats {stats}", flush=True)
+    gpu = {k: _Blocks(asm.out[k]) for k in KERNELS}
+    return gpu, asm.pair_off.cpu().numpy(), stats, (plan, asm, ds, dt)
+
+
+def _pairs(tg, rng, n, surf=None, per_order=0):
+    nnz = len(tg["near_patch"])
+    pick = set(int(i) for i in rng.choice(nnz, size=n, replace=False))
+    if surf is not None and per_order:
+        order = np.asarray(surf["order"])[np.asarray(tg["near_patch"])]
+        for q in np.unique(order):
+            idx = np.nonzero(order == q)[0]
+            pick.update(int(i) for i in rng.choice(idx, size=min(per_order, len(idx)), replace=False))
+    # the closest pairs: self pairs of on-surface targets and off-surface targets
+    sp = np.asarray(tg["self_patch"])
+    own = np.repeat(np.arange(len(tg["near_ptr"]) - 1), np.diff(tg["near_ptr"]))
+    selfk = np.nonzero(sp[own] == np.asarray(tg["near_patch"]))[0]
+    if len(selfk):
+        pick.update(int(i) for i in rng.choice(selfk, size=min(10, len(selfk)), replace=False))
+    offk = np.nonzero(sp[own] < 0)[0]
+    if len(offk):
+        pick.update(int(i) for i in rng.choice(offk, size=min(20, len(offk)), replace=False))
+    return sorted(pick)
+
+
+def test_star_full_size():
+    """1536-patch star surface, order 8, 98,304 node targets (the benchmark workload)."""
+    surf, tg, _ = wl.config2()
+    gpu, off, stats, keep = _assemble_bench_config(surf, tg)
+    pairs = _pairs(tg, np.random.default_rng(21), 70)
+    _compare(surf, tg, gpu, off, pairs)
+    assert stats["newton_fail"] == 0
+
+
+def test_uneven_ellipsoids_full_size():
+    """12 ellipsoids, per-patch orders 4/6/8/10 in one launch, Poisson off-surface targets
+    down to 1e-5 patch diameters."""
+    surf, tg, _ = wl.config3()
+    gpu, off, stats, keep = _assemble_bench_config(surf, tg)
+    pairs = _pairs(tg, np.random.default_rng(22), 40, surf, per_order=12)
+    _compare(surf, tg, gpu, off, pairs)
+    assert stats["newton_fail"] <= 1e-4 * stats["near_edges"]
+
+
+@pytest.mark.slow
+def test_forty_spheres_full_size():
+    """40 deformed spheres, 24,576 order-8 patches, node targets plus a 200k-point cloud
+    down to 1e-6 away (about 26 GB of weights on the device)."""
+    surf, tg, _ = wl.config5()
+    gpu, off, stats, keep = _assemble_bench_config(surf, tg)
+    pairs = _pairs(tg, np.random.default_rng(23), 40)
+    _compare(surf, tg, gpu, off, pairs)
+    assert stats["newton_fail"] <= 1e-4 * stats["near_edges"]
