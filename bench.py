@@ -23,7 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": None, "fetch_bytes": None, "write_bytes": None}
+TRAFFIC = {"src_sha256": "fea0b5a48a14d3df4f34cc493aba1d1afa2d5ef54a7a16373c1a45d9b9071420",
+           "fetch_bytes": 7545047296, "write_bytes": 4463734912}
 
 
 def flops_per_pair(q):
