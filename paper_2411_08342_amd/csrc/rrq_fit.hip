@@ -202,7 +202,7 @@ __global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
 // On exit the right-hand-side columns hold the solution in rows 0..n-1.
 // LDS: V [m][HNB], T [HNB][HNB], G [HNB][HNB], beta [HNB], alpha [HNB], X [n][kBackCols].
 // ---------------------------------------------------------------------------------------
-constexpr int HNB = 16;
+constexpr int HNB = 8;
 constexpr int kBackCols = 32;
 
 __device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, double* T,
@@ -406,7 +406,7 @@ int64_t fit_ws_doubles(int q) {
 //         M_S = [B^+; M_D Hmat B^+]
 // ---------------------------------------------------------------------------------------
 template <int Q>
-__global__ __launch_bounds__(NT) void k_fit(PlanDev pd, OrderDev od, const int32_t* patches,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_fit(PlanDev pd, OrderDev od, const int32_t* patches,
                                             int count, double* ws, int64_t ws_per_block) {
   constexpr int NP = np_of(Q);
   constexpr int Q2 = Q * Q;
