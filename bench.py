@@ -60,6 +60,20 @@ def kernel_src_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def assemble_ms(asm, flags, reps):
+    """Mean device time of whole rrq_assemble calls (binning, root pre-pass and pair kernels),
+    from events on the stream the calls run on."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        asm.assemble(flags=flags)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
 def learned_form(rrq, asm, flags, w_ref, reps=2):
     """Train the learned Newton guess on its own seeded geometry (not the benchmark surface),
     then time the batched form with it.  Returns a summary dict."""
@@ -76,11 +90,12 @@ def learned_form(rrq, asm, flags, w_ref, reps=2):
     asm.plan.set_mlp(params)
     lf = flags | rrq.RRQ_F_LEARNED
     st = [asm.assemble(flags=lf, stats=True) for _ in range(reps)]
+    a_ms = assemble_ms(asm, lf, reps)
     dev = max(((asm.out[k] - w_ref[k]).abs().max() / w_ref[k].abs().max()).item()
               for k in rrq.KERNELS)
     asm.plan.set_mlp(None)
     c = curve.cpu().numpy()
-    return {"kernel_ms": float(np.mean([x["kernel_ms"] for x in st])),
+    return {"assemble_ms": a_ms, "kernel_ms": float(np.mean([x["kernel_ms"] for x in st])),
             "newton_iters": st[-1]["newton_iters"], "learned_accept": st[-1]["learned_accept"],
             "max_rel_weight_dev_vs_batched": dev, "train_samples": int(feat.shape[1]),
             "train_s": t_train, "train_loss_first_last": [float(c[:10].mean()), float(c[-100:].mean())]}
@@ -202,11 +217,14 @@ def main():
     runs = [asm.assemble(flags=flags, stats=True) for _ in range(args.steps)]
     stats = runs[-1]
     kern_ms = float(np.mean([r["kernel_ms"] for r in runs]))
+    asm_ms = assemble_ms(asm, flags, args.steps)
     w_ref = {k: asm.out[k].clone() for k in rrq.KERNELS}
-    forms = {args.form + "_kernel_ms": kern_ms, args.form + "_newton_iters": stats["newton_iters"]}
+    forms = {args.form + "_assemble_ms": asm_ms, args.form + "_kernel_ms": kern_ms,
+             args.form + "_newton_iters": stats["newton_iters"]}
     if not args.no_forms and args.form == "batched":
         pr = [asm.assemble(flags=flags | rrq.RRQ_F_PLAIN, stats=True) for _ in range(2)]
         forms["plain_kernel_ms"] = float(np.mean([r["kernel_ms"] for r in pr]))
+        forms["plain_assemble_ms"] = assemble_ms(asm, flags | rrq.RRQ_F_PLAIN, 2)
         forms["plain_max_rel_weight_dev_vs_batched"] = max(
             ((asm.out[k] - w_ref[k]).abs().max() / w_ref[k].abs().max()).item() for k in rrq.KERNELS)
         forms["learned"] = learned_form(rrq, asm, flags, w_ref)
@@ -231,6 +249,7 @@ def main():
         "config": {"workload": desc, "form": args.form, "graph": True, "autotune": tune,
                    "pairs": int(len(tg["near_patch"])),
                    "weights_per_step": int(nweights), "kernel_ms": kern_ms,
+                   "assemble_ms": asm_ms,
                    "newton_iters_per_near_edge": stats["newton_iters"] / max(1, stats["near_edges"]),
                    "near_edges": stats["near_edges"], "newton_fail": stats["newton_fail"],
                    "forms": forms},

@@ -108,8 +108,10 @@ typedef struct {
   int64_t newton_fail;    /* edges whose Newton solve did not converge (plain rule used)   */
   int64_t learned_accept; /* edges whose learned initial guess was accepted                */
   int64_t newton_max;     /* largest iteration count of one edge                           */
-  double kernel_ms;       /* device time of the pair kernels of this call (plain or batched
-                             form; binning excluded), from HIP events on the call's stream  */
+  double kernel_ms;       /* device time of the pair kernels of this call (the per-pair
+                             kernel of the plain form or the tile kernels of the batched form;
+                             binning and the root pre-pass excluded), from HIP events on the
+                             call's stream                                                  */
 } rrq_stats;
 
 /* Create a plan for a surface: allocates the per-patch frames, coefficient maps and edge

@@ -365,10 +365,11 @@ static TargetsDev tdev(const rrq_targets* tg) {
 
 // workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders] u64 |
-// sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | guess[4 nnz] float2
+// sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
+// nearf[4 nnz] u8
 struct WsLayout {
-  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, guess,
-      total;
+  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, root,
+      nearf, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P) {
@@ -386,7 +387,8 @@ static WsLayout ws_layout(int64_t nnz, int P) {
   w.sorted = o; o = al(o + n * 8);
   w.tiles = o; o = al(o + (n / 4 + (size_t)P + 1) * 16);
   w.part = o; o = al(o + (size_t)scan_partials((int64_t)n) * 8);
-  w.guess = o; o = al(o + 4 * n * 8);
+  w.root = o; o = al(o + 4 * n * 16);
+  w.nearf = o; o = al(o + 4 * n);
   w.total = o;
   return w;
 }
@@ -448,7 +450,8 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   ao.pair_off = pair_off;
   ao.owner = owner;
   ao.counters = counters;
-  ao.guess = nullptr;
+  ao.root = nullptr;
+  ao.nearf = nullptr;
   PlanDev pd = p->dev();
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (stats) {
@@ -484,14 +487,18 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
     if (launch_binning(td, p->P, tile, p->perm_d, p->bin_orders, cnt, fill, start, tstart,
                        ntiles, sorted, tiles, qtile, qctr, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
-    if (flags & RRQ_F_LEARNED) {
-      CollectOpts co;
-      for (int q = 0; q <= kMaxQ; ++q) co.rho_far[q] = p->rho_far[q];
-      co.newton_tol = p->opt.newton_tol;
-      co.newton_maxit = p->opt.newton_maxit;
-      float2* guess = (float2*)(wb + wl.guess);
-      if (launch_guess(pd, td, owner, co, guess, st) != hipSuccess) return RRQ_ERR_DEVICE;
-      ao.guess = guess;
+    {
+      RootOpts ro;
+      for (int q = 0; q <= kMaxQ; ++q) ro.rho_far[q] = p->rho_far[q];
+      ro.newton_tol = p->opt.newton_tol;
+      ro.newton_maxit = p->opt.newton_maxit;
+      double2* root = (double2*)(wb + wl.root);
+      uint8_t* nearf = (uint8_t*)(wb + wl.nearf);
+      if (launch_root(pd, td, owner, ro, (flags & RRQ_F_LEARNED) != 0, root, nearf, counters,
+                      st) != hipSuccess)
+        return RRQ_ERR_DEVICE;
+      ao.root = root;
+      ao.nearf = nearf;
     }
     if (stats && hipEventRecord(ev[0], st) != hipSuccess) return RRQ_ERR_DEVICE;
     for (int qi = 0; qi < kNumOrders; ++qi) {

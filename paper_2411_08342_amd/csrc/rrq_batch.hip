@@ -163,7 +163,6 @@ __device__ __forceinline__ double reduce_scatter16(double* x) {
 }
 
 constexpr int kMaxLevel = 52;
-constexpr int kLearnedMaxit = 8;   // Newton iterations allowed from the learned start
 
 // Dyadic panels of [-1, 1] graded toward t0 = a + i b: a panel of half-width h and centre c
 // is split while (t0 - c) / h lies inside the Bernstein ellipse of radius rho (that is,
@@ -227,6 +226,127 @@ __device__ int wave_graded_panels(double a, double b, double rho, double* wpan, 
     if (pos < cap) { wpan[2 * pos] = -1.0 + w * (double)j; wpan[2 * pos + 1] = -1.0 + w * (double)(j + 1); }
   *over = total > cap;
   return total < cap ? total : cap;
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 5 for every (pair, edge), one per thread: chord root t_s; if it lies inside the
+// Bernstein ellipse of radius rho_far, Newton on the distance function.  With a network
+// (learned form) Newton first starts from t_s + dt(features) for at most kLearnedMaxit
+// iterations and keeps that root if it converges inside the ellipse; otherwise plain Newton
+// from t_s decides.  root[slot] = t0 (Im t0 >= 0), nearf[slot] = 1 for the singularity-swap
+// class.  Counters: near edges, iterations, failures, learned accepts, max iterations.
+// ---------------------------------------------------------------------------------------
+constexpr int kLearnedMaxit = 8;
+
+template <bool LEARNED>
+__global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const int64_t* owner,
+                                              RootOpts ro, double2* root, uint8_t* nearf,
+                                              unsigned long long* counters) {
+  __shared__ float w[LEARNED ? kMlpParams : 1];
+  __shared__ unsigned long long cs[5];
+  if (threadIdx.x < 5) cs[threadIdx.x] = 0;
+  if (LEARNED)
+    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) w[i] = pd.mlp[i];
+  __syncthreads();
+  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_learn = 0, c_max = 0;
+  const int64_t nslot = 4 * tg.nnz;
+  for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < nslot;
+       slot += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = slot >> 2;
+    const int e = (int)(slot & 3);
+    const int P = tg.near_patch[k];
+    const int q = pd.order[P];
+    const int PT = 2 * q;
+    const int64_t g = owner[k];
+    const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
+    double xl[3];
+    frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
+    double cf[3 * 2 * kMaxQ];
+    const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
+    for (int i = 0; i < PT; ++i)
+      for (int c = 0; c < 3; ++c) cf[i * 3 + c] = pd.edge_coef[c * pd.E + e0 + i];
+    cplx ts, tl;
+    bool try_learned = false;
+    if (LEARNED) {
+      float x[kMlpIn];
+      edge_features(cf, PT, xl, x, &ts);
+      if (bernstein_rho(ts) <= ro.rho_far[q]) {
+        float h1[kMlpH];
+        for (int u = 0; u < kMlpH; ++u) {
+          float a = w[kMlpB1 + u];
+#pragma unroll
+          for (int c = 0; c < kMlpIn; ++c) a += w[kMlpW1 + c * kMlpH + u] * x[c];
+          h1[u] = tanhf(a);
+        }
+        float y0 = w[kMlpB3], y1 = w[kMlpB3 + 1];
+        for (int u = 0; u < kMlpH; ++u) {
+          float a = w[kMlpB2 + u];
+#pragma unroll 16
+          for (int kk = 0; kk < kMlpH; ++kk) a += w[kMlpW2 + kk * kMlpH + u] * h1[kk];
+          const float h2 = tanhf(a);
+          y0 += w[kMlpW3 + u] * h2;
+          y1 += w[kMlpW3 + kMlpH + u] * h2;
+        }
+        tl = mk(ts.re + (double)y0, ts.im + (double)y1);
+        try_learned = isfinite(tl.re) && isfinite(tl.im);
+      }
+    } else {
+      double m[3], dv[3];
+      edge_chord(cf, PT, m, dv);
+      ts = chord_root(m, dv, xl);
+    }
+    cplx t0 = ts;
+    int near = 0;
+    if (bernstein_rho(ts) <= ro.rho_far[q]) {
+      int its_all = 0;
+      for (int attempt = try_learned ? 0 : 1; attempt < 2; ++attempt) {
+        cplx tp = attempt == 0 ? tl : ts;
+        int its;
+        const int conv = newton_solve(cf, PT, xl, &tp, ro.newton_tol,
+                                      attempt == 0 ? kLearnedMaxit : ro.newton_maxit, &its);
+        its_all += its;
+        if (tp.im < 0) tp.im = -tp.im;
+        const int inside = conv && bernstein_rho(tp) <= ro.rho_far[q];
+        if (attempt == 0) {
+          if (!inside) continue;
+          ++c_learn;
+        } else if (!conv) {
+          ++c_fail;
+        }
+        t0 = tp;
+        near = inside;
+        break;
+      }
+      c_iters += (unsigned long long)its_all;
+      if ((unsigned long long)its_all > c_max) c_max = its_all;
+      c_near += near;
+    }
+    root[slot] = make_double2(t0.re, t0.im);
+    nearf[slot] = (uint8_t)near;
+  }
+  if (c_near) atomicAdd(&cs[0], c_near);
+  if (c_iters) atomicAdd(&cs[1], c_iters);
+  if (c_fail) atomicAdd(&cs[2], c_fail);
+  if (c_learn) atomicAdd(&cs[3], c_learn);
+  if (c_max) atomicMax(&cs[4], c_max);
+  __syncthreads();
+  if (threadIdx.x < 5 && cs[threadIdx.x]) {
+    if (threadIdx.x == 4) atomicMax(&counters[4], cs[4]);
+    else atomicAdd(&counters[threadIdx.x], cs[threadIdx.x]);
+  }
+}
+
+hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
+                       const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
+                       unsigned long long* counters, hipStream_t st) {
+  int64_t g = (4 * tg.nnz + 255) / 256;
+  if (g < 1) g = 1;
+  const dim3 grid((unsigned)(g < 8192 ? g : 8192));
+  if (learned)
+    hipLaunchKernelGGL(k_root<true>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, counters);
+  else
+    hipLaunchKernelGGL(k_root<false>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, counters);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -314,9 +434,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t tlo = qtile[0], thi = qtile[1];
-  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_max = 0, c_learn = 0;
-  // learned initial guesses t_s + dt of every (pair, edge), from the network pre-pass
-  const float2* guess = (out.flags & RRQ_F_LEARNED) ? out.guess : nullptr;
+  unsigned long long c_fail = 0;
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
     cgl_w[tid] = od.gl_w[tid];
@@ -350,15 +468,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         const int64_t k = sorted[tile.y + sub + t];
         const int64_t g = out.owner[k];
         const int self = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
-        const double inv_s = 1.0 / fr[12];
-        double dx[3], nv[3], xl[3], nl[3];
+        double xg[3], nv[3], xl[3], nl[3];
         for (int c = 0; c < 3; ++c) {
-          dx[c] = tg.xyz[c * tg.T + g] - fr[c];
+          xg[c] = tg.xyz[c * tg.T + g];
           nv[c] = tg.nrm[c * tg.T + g];
         }
+        frame_point(fr, xg, xl);
         for (int a = 0; a < 3; ++a) {
           const double* ax = fr + 3 + 3 * a;
-          xl[a] = (dx[0] * ax[0] + dx[1] * ax[1] + dx[2] * ax[2]) * inv_s;
           nl[a] = nv[0] * ax[0] + nv[1] * ax[1] + nv[2] * ax[2];
         }
         double bd = 1e300;
@@ -399,53 +516,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
-      // ---- Step 5: per (target, edge) classification and Newton root (wave 0); Step 4:
-      // target harmonics (wave 1) at the same time
+      // ---- Step 5 results (root pre-pass) per (target, edge); Step 4: target harmonics
       if (tid < 4 * nt) {
         const int t = tid >> 2, e = tid & 3;
-        const double* cf = ecoef + e * PT * 3;
-        const double* xl = sx + t * 3;
-        double m[3], dv[3];
-        edge_chord(cf, PT, m, dv);
-        const cplx ts = chord_root(m, dv, xl);
-        int near = 0;
-        cplx t0 = ts;
-        if (bernstein_rho(ts) <= so.rho_far) {
-          // attempt 0: Newton from the learned start (at most kLearnedMaxit iterations),
-          // accepted if it converges inside the ellipse; attempt 1: plain Newton from t_s
-          cplx tl = ts;
-          int first = 1;
-          if (guess) {
-            const float2 gd = guess[4 * sorted[tile.y + sub + t] + e];
-            tl = mk(ts.re + (double)gd.x, ts.im + (double)gd.y);
-            if (isfinite(tl.re) && isfinite(tl.im)) first = 0;
-          }
-          int its_all = 0;
-          for (int attempt = first; attempt < 2; ++attempt) {
-            cplx tp = attempt == 0 ? tl : ts;
-            int its;
-            const int conv = newton_solve(cf, PT, xl, &tp, so.newton_tol,
-                                          attempt == 0 ? kLearnedMaxit : so.newton_maxit, &its);
-            its_all += its;
-            if (tp.im < 0) tp.im = -tp.im;
-            const int inside = conv && bernstein_rho(tp) <= so.rho_far;
-            if (attempt == 0) {
-              if (!inside) continue;
-              ++c_learn;
-            } else if (!conv) {
-              ++c_fail;
-            }
-            t0 = tp;
-            near = inside;
-            break;
-          }
-          c_iters += (unsigned long long)its_all;
-          if ((unsigned long long)its_all > c_max) c_max = its_all;
-          if (near) ++c_near;
-        }
-        snear[t * 4 + e] = near;
-        st0[(t * 4 + e) * 2] = t0.re;
-        st0[(t * 4 + e) * 2 + 1] = t0.im;
+        const int64_t slot = 4 * sorted[tile.y + sub + t] + e;
+        const double2 r = out.root[slot];
+        snear[t * 4 + e] = out.nearf[slot];
+        st0[(t * 4 + e) * 2] = r.x;
+        st0[(t * 4 + e) * 2 + 1] = r.y;
         som0e[t * 4 + e] = 0.0;
       } else if (tid >= 64 && tid < 64 + nt) {
         const int t = tid - 64;
@@ -840,11 +918,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       }
     }
   }
-  if (c_iters) atomicAdd(&out.counters[1], c_iters);
   if (c_fail) atomicAdd(&out.counters[2], c_fail);
-  if (c_max) atomicMax(&out.counters[4], c_max);
-  if (c_near) atomicAdd(&out.counters[0], c_near);
-  if (c_learn) atomicAdd(&out.counters[3], c_learn);
 }
 
 #define RRQ_TILE_CASES(X) X(4, 4) X(4, 8) X(5, 4) X(5, 8) X(6, 4) X(6, 8) X(8, 4) X(8, 8) X(10, 4)

@@ -209,6 +209,17 @@ __device__ __forceinline__ double omega0_at(const double* x, const double* u, co
   return num / (R * (R + d0 * u[0] + d1 * u[1] + d2 * u[2]));
 }
 
+// patch-local coordinates of a point: R^T (x - o) / s for the frame fr = o[3], e_x[3],
+// e_y[3], e_z[3], s
+__device__ __forceinline__ void frame_point(const double* fr, const double* x, double* xl) {
+  const double inv_s = 1.0 / fr[12];
+  const double dx[3] = {x[0] - fr[0], x[1] - fr[1], x[2] - fr[2]};
+  for (int a = 0; a < 3; ++a) {
+    const double* ax = fr + 3 + 3 * a;
+    xl[a] = (dx[0] * ax[0] + dx[1] * ax[1] + dx[2] * ax[2]) * inv_s;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // singularity-swap root (Sec. 3.5, Step 5): chord start and Newton on
 // f(t) = sum_c (r_c(t) - x_c)^2 for an edge given by its Legendre coefficients cf[3k + c]

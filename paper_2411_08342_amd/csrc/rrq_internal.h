@@ -72,7 +72,8 @@ struct AssembleOut {
   const int64_t* pair_off;
   const int64_t* owner;     // [nnz] target of each pair
   unsigned long long* counters;   // [8] stats
-  const float2* guess;      // [4 nnz] learned Newton-start offsets (RRQ_F_LEARNED) or null
+  const double2* root;      // [4 nnz] singularity-swap roots t0 (root pre-pass)
+  const uint8_t* nearf;     // [4 nnz] 1: singularity-swap class, 0: plain rule
 };
 
 struct SolveOpts {
@@ -118,6 +119,15 @@ int tile_supported(int q, int T);
 
 int64_t fit_ws_doubles(int q);
 
+struct RootOpts {
+  double rho_far[kMaxQ + 1];
+  double newton_tol;
+  int newton_maxit;
+};
+hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
+                       const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
+                       unsigned long long* counters, hipStream_t st);
+
 // learned initial guess: sample collection and training
 struct CollectOpts {
   double rho_far[kMaxQ + 1];
@@ -145,7 +155,6 @@ hipError_t mlp_loss_grad_run(const float* params, const float* feat, const float
 hipError_t mlp_predict_run(const float* params, const float* feat, int64_t n, float* out,
                            hipStream_t st);
 hipError_t mlp_pack_run(const float* params, float* dst, hipStream_t st);
-hipError_t launch_guess(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
-                        const CollectOpts& co, float2* guess, hipStream_t st);
+
 
 }  // namespace rrq

@@ -32,11 +32,9 @@ __global__ void k_collect(PlanDev pd, TargetsDev tg, const int64_t* owner, Colle
     const int q = pd.order[P];
     const int PT = 2 * q;
     const int64_t g = owner[k];
-    const double* fr = pd.frame + (int64_t)P * kFrame;
-    double dx[3], xl[3];
-    for (int c = 0; c < 3; ++c) dx[c] = tg.xyz[c * tg.T + g] - fr[c];
-    for (int a = 0; a < 3; ++a)
-      xl[a] = (dx[0] * fr[3 + 3 * a] + dx[1] * fr[4 + 3 * a] + dx[2] * fr[5 + 3 * a]) / fr[12];
+    const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
+    double xl[3];
+    frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
     double cf[3 * 2 * kMaxQ];
     const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
     for (int i = 0; i < PT; ++i)
@@ -81,68 +79,6 @@ hipError_t launch_collect(const PlanDev& pd, const TargetsDev& tg, const int64_t
   else
     hipLaunchKernelGGL(k_collect, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st, pd,
                        tg, owner, co, 1, flag, cap, feat, dt, t0);
-  return hipGetLastError();
-}
-
-// Learned Newton-start offsets for every (pair, edge): features, then the network (one
-// slot per thread, weights in LDS in the inference layout).  Slots whose chord root lies
-// outside the Bernstein ellipse of radius rho_far get NaN (no Newton solve there).
-__global__ __launch_bounds__(256) void k_guess(PlanDev pd, TargetsDev tg, const int64_t* owner,
-                                               CollectOpts co, float2* guess) {
-  __shared__ float w[kMlpParams];
-  for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) w[i] = pd.mlp[i];
-  __syncthreads();
-  const int64_t nslot = 4 * tg.nnz;
-  for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < nslot;
-       slot += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = slot >> 2;
-    const int e = (int)(slot & 3);
-    const int P = tg.near_patch[k];
-    const int q = pd.order[P];
-    const int PT = 2 * q;
-    const int64_t g = owner[k];
-    const double* fr = pd.frame + (int64_t)P * kFrame;
-    double dx[3], xl[3];
-    for (int c = 0; c < 3; ++c) dx[c] = tg.xyz[c * tg.T + g] - fr[c];
-    for (int a = 0; a < 3; ++a)
-      xl[a] = (dx[0] * fr[3 + 3 * a] + dx[1] * fr[4 + 3 * a] + dx[2] * fr[5 + 3 * a]) / fr[12];
-    double cf[3 * 2 * kMaxQ];
-    const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
-    for (int i = 0; i < PT; ++i)
-      for (int c = 0; c < 3; ++c) cf[i * 3 + c] = pd.edge_coef[c * pd.E + e0 + i];
-    float x[kMlpIn];
-    cplx ts;
-    edge_features(cf, PT, xl, x, &ts);
-    float2 out = make_float2(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000));
-    if (bernstein_rho(ts) <= co.rho_far[q]) {
-      float h1[kMlpH];
-      for (int u = 0; u < kMlpH; ++u) {
-        float a = w[kMlpB1 + u];
-#pragma unroll
-        for (int c = 0; c < kMlpIn; ++c) a += w[kMlpW1 + c * kMlpH + u] * x[c];
-        h1[u] = tanhf(a);
-      }
-      float y0 = w[kMlpB3], y1 = w[kMlpB3 + 1];
-      for (int u = 0; u < kMlpH; ++u) {
-        float a = w[kMlpB2 + u];
-#pragma unroll 16
-        for (int kk = 0; kk < kMlpH; ++kk) a += w[kMlpW2 + kk * kMlpH + u] * h1[kk];
-        const float h2 = tanhf(a);
-        y0 += w[kMlpW3 + u] * h2;
-        y1 += w[kMlpW3 + kMlpH + u] * h2;
-      }
-      out = make_float2(y0, y1);
-    }
-    guess[slot] = out;
-  }
-}
-
-hipError_t launch_guess(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
-                        const CollectOpts& co, float2* guess, hipStream_t st) {
-  int64_t g = (4 * tg.nnz + 255) / 256;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_guess, dim3((unsigned)(g < 16384 ? g : 16384)), dim3(256), 0, st, pd, tg,
-                     owner, co, guess);
   return hipGetLastError();
 }
 
