@@ -242,35 +242,71 @@ template <bool LEARNED>
 __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const int64_t* owner,
                                               RootOpts ro, double2* root, uint8_t* nearf,
                                               unsigned long long* counters) {
+  constexpr int kQ = 1024;               // slots per chunk of a workgroup
   __shared__ float w[LEARNED ? kMlpParams : 1];
+  __shared__ int64_t qslot[kQ];          // chunk slots whose chord root needs Newton
+  __shared__ int qn;
   __shared__ unsigned long long cs[5];
-  if (threadIdx.x < 5) cs[threadIdx.x] = 0;
+  const int tid = threadIdx.x;
+  if (tid < 5) cs[tid] = 0;
   if (LEARNED)
-    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) w[i] = pd.mlp[i];
-  __syncthreads();
+    for (int i = tid; i < kMlpParams; i += blockDim.x) w[i] = pd.mlp[i];
   unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_learn = 0, c_max = 0;
   const int64_t nslot = 4 * tg.nnz;
-  for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < nslot;
-       slot += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = slot >> 2;
-    const int e = (int)(slot & 3);
-    const int P = tg.near_patch[k];
-    const int q = pd.order[P];
-    const int PT = 2 * q;
-    const int64_t g = owner[k];
-    const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
-    double xl[3];
-    frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
-    double cf[3 * 2 * kMaxQ];
-    const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
-    for (int i = 0; i < PT; ++i)
-      for (int c = 0; c < 3; ++c) cf[i * 3 + c] = pd.edge_coef[c * pd.E + e0 + i];
-    cplx ts, tl;
-    bool try_learned = false;
-    if (LEARNED) {
-      float x[kMlpIn];
-      edge_features(cf, PT, xl, x, &ts);
+  for (int64_t base = (int64_t)blockIdx.x * kQ; base < nslot; base += (int64_t)gridDim.x * kQ) {
+    __syncthreads();
+    if (tid == 0) qn = 0;
+    __syncthreads();
+    // classify the chunk; slots with the chord root outside the ellipse are done here
+    for (int i = tid; i < kQ; i += blockDim.x) {
+      const int64_t slot = base + i;
+      if (slot >= nslot) break;
+      const int64_t k = slot >> 2;
+      const int e = (int)(slot & 3);
+      const int P = tg.near_patch[k];
+      const int q = pd.order[P];
+      const int PT = 2 * q;
+      const int64_t g = owner[k];
+      const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
+      double xl[3];
+      frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
+      double cf[3 * 2 * kMaxQ];
+      const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
+      for (int j = 0; j < PT; ++j)
+        for (int c = 0; c < 3; ++c) cf[j * 3 + c] = pd.edge_coef[c * pd.E + e0 + j];
+      double m[3], dv[3];
+      edge_chord(cf, PT, m, dv);
+      const cplx ts = chord_root(m, dv, xl);
       if (bernstein_rho(ts) <= ro.rho_far[q]) {
+        qslot[atomicAdd(&qn, 1)] = slot;
+      } else {
+        root[slot] = make_double2(ts.re, ts.im);
+        nearf[slot] = 0;
+      }
+    }
+    __syncthreads();
+    // Newton (from the learned start first, if any) on the queued slots, all lanes busy
+    const int nq = qn;
+    for (int i = tid; i < nq; i += blockDim.x) {
+      const int64_t slot = qslot[i];
+      const int64_t k = slot >> 2;
+      const int e = (int)(slot & 3);
+      const int P = tg.near_patch[k];
+      const int q = pd.order[P];
+      const int PT = 2 * q;
+      const int64_t g = owner[k];
+      const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
+      double xl[3];
+      frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
+      double cf[3 * 2 * kMaxQ];
+      const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
+      for (int j = 0; j < PT; ++j)
+        for (int c = 0; c < 3; ++c) cf[j * 3 + c] = pd.edge_coef[c * pd.E + e0 + j];
+      cplx ts, tl = mk(0.0, 0.0);
+      bool try_learned = false;
+      if (LEARNED) {
+        float x[kMlpIn];
+        edge_features(cf, PT, xl, x, &ts);
         float h1[kMlpH];
         for (int u = 0; u < kMlpH; ++u) {
           float a = w[kMlpB1 + u];
@@ -289,16 +325,13 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
         }
         tl = mk(ts.re + (double)y0, ts.im + (double)y1);
         try_learned = isfinite(tl.re) && isfinite(tl.im);
+      } else {
+        double m[3], dv[3];
+        edge_chord(cf, PT, m, dv);
+        ts = chord_root(m, dv, xl);
       }
-    } else {
-      double m[3], dv[3];
-      edge_chord(cf, PT, m, dv);
-      ts = chord_root(m, dv, xl);
-    }
-    cplx t0 = ts;
-    int near = 0;
-    if (bernstein_rho(ts) <= ro.rho_far[q]) {
-      int its_all = 0;
+      cplx t0 = ts;
+      int near = 0, its_all = 0;
       for (int attempt = try_learned ? 0 : 1; attempt < 2; ++attempt) {
         cplx tp = attempt == 0 ? tl : ts;
         int its;
@@ -320,9 +353,9 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
       c_iters += (unsigned long long)its_all;
       if ((unsigned long long)its_all > c_max) c_max = its_all;
       c_near += near;
+      root[slot] = make_double2(t0.re, t0.im);
+      nearf[slot] = (uint8_t)near;
     }
-    root[slot] = make_double2(t0.re, t0.im);
-    nearf[slot] = (uint8_t)near;
   }
   if (c_near) atomicAdd(&cs[0], c_near);
   if (c_iters) atomicAdd(&cs[1], c_iters);
@@ -330,18 +363,18 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
   if (c_learn) atomicAdd(&cs[3], c_learn);
   if (c_max) atomicMax(&cs[4], c_max);
   __syncthreads();
-  if (threadIdx.x < 5 && cs[threadIdx.x]) {
-    if (threadIdx.x == 4) atomicMax(&counters[4], cs[4]);
-    else atomicAdd(&counters[threadIdx.x], cs[threadIdx.x]);
+  if (tid < 5 && cs[tid]) {
+    if (tid == 4) atomicMax(&counters[4], cs[4]);
+    else atomicAdd(&counters[tid], cs[tid]);
   }
 }
 
 hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
                        const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
                        unsigned long long* counters, hipStream_t st) {
-  int64_t g = (4 * tg.nnz + 255) / 256;
+  int64_t g = (4 * tg.nnz + 1023) / 1024;
   if (g < 1) g = 1;
-  const dim3 grid((unsigned)(g < 8192 ? g : 8192));
+  const dim3 grid((unsigned)(g < 4096 ? g : 4096));
   if (learned)
     hipLaunchKernelGGL(k_root<true>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, counters);
   else
