@@ -564,8 +564,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       }
       __syncthreads();
       // ---- Lagrange-basis moments of near edges on graded panels: one wave per near item
-      for (int item = wv; item < 4 * nt; item += BNT / 64) {
-        if (!snear[item]) continue;          // wave-uniform
+      // near items ranked by a ballot; wave w takes ranks w, w + 4, ... (near edges of one
+      // edge index cluster, so assigning by item index would load one wave)
+      const unsigned long long nmask = __ballot(lane < 4 * nt && snear[lane < 4 * nt ? lane : 0]);
+      const int nnear = __popcll(nmask);
+      for (int rk = wv; rk < nnear; rk += BNT / 64) {
+        unsigned long long mm = nmask;
+        for (int j = 0; j < rk; ++j) mm &= mm - 1;
+        const int item = __builtin_ctzll(mm);
         const int t = item >> 2, e = item & 3;
         const double a = st0[item * 2], b = st0[item * 2 + 1];
         double* wpan = pan + wv * L::NPAN * 2;
