@@ -101,6 +101,33 @@ def learned_form(rrq, asm, flags, w_ref, reps=2):
             "train_s": t_train, "train_loss_first_last": [float(c[:10].mean()), float(c[-100:].mean())]}
 
 
+def potentials_form(rrq, asm, flags, w_ref, reps=3):
+    """Potentials mode on the same near list: the correction applied to a smooth density
+    without storing weights, timed like the assembly, and compared with rrq_apply on the
+    assembled weights (max |difference| over targets relative to the largest potential)."""
+    import torch
+    x, y, z = asm.plan.dsurf.node_xyz
+    dens = (0.7 + x * x - 0.4 * y * z + 0.3 * z + 0.2 * x * y * z).contiguous()
+    ev = rrq.Evaluator(asm.plan, asm.dtg)
+    st = [ev.potentials(dens, flags=flags, stats=True)[1] for _ in range(reps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        got = ev.potentials(dens, flags=flags)
+        b.record()
+    torch.cuda.synchronize()
+    for k in rrq.KERNELS:
+        asm.out[k].copy_(w_ref[k])
+    ref = asm.apply(dens)
+    torch.cuda.synchronize()
+    dev = max(((got[k] - ref[k]).abs().max() / ref[k].abs().max()).item() for k in rrq.KERNELS)
+    del ev
+    return {"call_ms": float(np.mean([a.elapsed_time(b) for a, b in evs])),
+            "kernel_ms": float(np.mean([r["kernel_ms"] for r in st])),
+            "max_rel_dev_vs_apply_of_weights": dev}
+
+
 def build_workload(name):
     from paper_2411_08342_amd import workloads as wl
     if name == "star":
@@ -228,6 +255,7 @@ def main():
         forms["plain_max_rel_weight_dev_vs_batched"] = max(
             ((asm.out[k] - w_ref[k]).abs().max() / w_ref[k].abs().max()).item() for k in rrq.KERNELS)
         forms["learned"] = learned_form(rrq, asm, flags, w_ref)
+        forms["potentials"] = potentials_form(rrq, asm, flags, w_ref)
         print(f"[bench] forms: {forms}", flush=True)
         asm.assemble(flags=flags)      # leave the batched weights in the outputs
 

@@ -153,6 +153,31 @@ rrq_status rrq_apply(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask
                      double* pot_S, double* pot_D, double* pot_Sp, double* pot_Dp,
                      void* stream);
 
+/* Potentials mode (the correction applied on the fly, without storing weights): pot_K[t] =
+ * sum over the near pairs (t, P) of W_K[t, P] . density[nodes of P], the same numbers that
+ * rrq_assemble followed by rrq_apply gives, up to rounding order.  Each pair's row of
+ * integrals (the output of the translation, Sec. 3.4-3.7) is contracted with the patch
+ * coefficients c_K = M_K density_P (Sec. 3.2: the fit applied to the density once per
+ * patch) instead of with M_K itself, so the work per pair drops from a row-by-matrix
+ * product to a dot product; with RRQ_F_CORRECTION the smooth rule over the patch nodes
+ * (self node excluded) is subtracted per pair.  density is [N] (device, the surface's node
+ * order); pot_* are [T] device arrays (NULL for a kernel not in kmask).  Batched form only
+ * (RRQ_F_PLAIN -> RRQ_ERR_UNSUPPORTED); RRQ_F_LEARNED needs an installed network.  Uses the
+ * rrq_assemble workspace; needs no pair offsets.  `stats` as for rrq_assemble. */
+rrq_status rrq_potentials(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
+                          uint32_t flags, const double* density, double* pot_S, double* pot_D,
+                          double* pot_Sp, double* pot_Dp, void* workspace,
+                          size_t workspace_bytes, void* stream, rrq_stats* stats);
+
+/* The smooth quadrature rule summed directly over every surface node (the self node of an
+ * on-surface target excluded): pot_K[t] = sum_j w_j K(x_t, y_j) density[j] (the far-field
+ * rule of Sec. 4; O(T N) work, meant for small meshes and end-to-end checks, where a fast
+ * summation method would serve a large one).  Adding rrq_potentials with RRQ_F_CORRECTION
+ * gives the layer potentials at the targets.  Asynchronous. */
+rrq_status rrq_smooth_potentials(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
+                                 const double* density, double* pot_S, double* pot_D,
+                                 double* pot_Sp, double* pot_Dp, void* stream);
+
 /* Autotuner of the batched form: times rrq_assemble on this near list for every supported
  * tile size (targets per workgroup: 4, 8) and grid size (1024, 2048, 4096 workgroups) with
  * HIP events on `stream`, keeps the fastest in the plan and returns it.  If `cache_path`

@@ -366,10 +366,10 @@ static TargetsDev tdev(const rrq_targets* tg) {
 // workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders] u64 |
 // sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
-// nearf[4 nnz] u8
+// nearf[4 nnz] u8 | pairpot[nnz][4] f64 | pcoef[P][kCoefStride] f64
 struct WsLayout {
   size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, root,
-      nearf, total;
+      nearf, pairpot, pcoef, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P) {
@@ -389,6 +389,8 @@ static WsLayout ws_layout(int64_t nnz, int P) {
   w.part = o; o = al(o + (size_t)scan_partials((int64_t)n) * 8);
   w.root = o; o = al(o + 4 * n * 16);
   w.nearf = o; o = al(o + 4 * n);
+  w.pairpot = o; o = al(o + 4 * n * 8);
+  w.pcoef = o; o = al(o + (size_t)P * kCoefStride * 8);
   w.total = o;
   return w;
 }
@@ -421,22 +423,12 @@ rrq_status rrq_pair_offsets(const rrq_plan* p, const rrq_targets* tg, int64_t* p
   return RRQ_OK;
 }
 
-rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
-                        uint32_t flags, double* out_S, double* out_D, double* out_Sp,
-                        double* out_Dp, const int64_t* pair_off, void* workspace,
-                        size_t workspace_bytes, void* stream, rrq_stats* stats) {
-  rrq_status c = check_targets(p, tg);
-  if (c != RRQ_OK) return c;
-  if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
-  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
-  double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
-  for (int K = 0; K < 4; ++K)
-    if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
-  if (flags & RRQ_F_LEARNED) {
-    if (flags & RRQ_F_PLAIN) return RRQ_ERR_UNSUPPORTED;
-    if (!p->has_mlp) return RRQ_ERR_ARG;
-  }
-  hipStream_t st = (hipStream_t)stream;
+// Assembly of the near pairs: weights (outs) or, with a density, the potentials (pots).
+static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                            uint32_t flags, double* const* outs, const int64_t* pair_off,
+                            const double* density, double* const* pots, void* workspace,
+                            hipStream_t st, rrq_stats* stats) {
+  const bool pot = pots != nullptr;
   const WsLayout wl = ws_layout(tg->nnz, p->P);
   char* wb = (char*)workspace;
   int64_t* owner = (int64_t*)(wb + wl.owner);
@@ -444,7 +436,7 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   TargetsDev td = tdev(tg);
   if (launch_owner(td, owner, counters, st) != hipSuccess) return RRQ_ERR_DEVICE;
   AssembleOut ao;
-  for (int K = 0; K < 4; ++K) ao.w[K] = (kmask & (1u << K)) ? outs[K] : nullptr;
+  for (int K = 0; K < 4; ++K) ao.w[K] = (!pot && (kmask & (1u << K))) ? outs[K] : nullptr;
   ao.kmask = kmask;
   ao.flags = flags;
   ao.pair_off = pair_off;
@@ -452,6 +444,9 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   ao.counters = counters;
   ao.root = nullptr;
   ao.nearf = nullptr;
+  ao.dens = density;
+  ao.pcoef = pot ? (const double*)(wb + wl.pcoef) : nullptr;
+  ao.pairpot = pot ? (double*)(wb + wl.pairpot) : nullptr;
   PlanDev pd = p->dev();
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (stats) {
@@ -500,6 +495,8 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
       ao.root = root;
       ao.nearf = nearf;
     }
+    if (pot && launch_patch_coef(pd, density, (double*)(wb + wl.pcoef), st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
     if (stats && hipEventRecord(ev[0], st) != hipSuccess) return RRQ_ERR_DEVICE;
     for (int qi = 0; qi < kNumOrders; ++qi) {
       const int q = kOrders[qi];
@@ -508,10 +505,12 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
       int T = tile;
       while (T > 4 && !tile_supported(q, T)) T /= 2;
       if (!tile_supported(q, T)) return RRQ_ERR_UNSUPPORTED;
-      if (launch_pair_tile(q, T, p->grid[q], pd, p->od[q], td, ao, so, tiles, qtile + qi,
+      if (launch_pair_tile(q, T, pot, p->grid[q], pd, p->od[q], td, ao, so, tiles, qtile + qi,
                            qctr + qi, sorted, st) != hipSuccess)
         return RRQ_ERR_DEVICE;
     }
+    if (pot && launch_pot_reduce(td, kmask, ao.pairpot, pots, st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
   }
   if (stats) {
     unsigned long long h[8];
@@ -529,6 +528,57 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
     stats->newton_max = (int64_t)h[4];
   }
   return RRQ_OK;
+}
+
+rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                        uint32_t flags, double* out_S, double* out_D, double* out_Sp,
+                        double* out_Dp, const int64_t* pair_off, void* workspace,
+                        size_t workspace_bytes, void* stream, rrq_stats* stats) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
+  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
+  double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
+  for (int K = 0; K < 4; ++K)
+    if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
+  if (flags & RRQ_F_LEARNED) {
+    if (flags & RRQ_F_PLAIN) return RRQ_ERR_UNSUPPORTED;
+    if (!p->has_mlp) return RRQ_ERR_ARG;
+  }
+  return run_pairs(p, tg, kmask, flags, outs, pair_off, nullptr, nullptr, workspace,
+                   (hipStream_t)stream, stats);
+}
+
+rrq_status rrq_potentials(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                          uint32_t flags, const double* density, double* pot_S, double* pot_D,
+                          double* pot_Sp, double* pot_Dp, void* workspace,
+                          size_t workspace_bytes, void* stream, rrq_stats* stats) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!density || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
+  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
+  double* pots[4] = {pot_S, pot_D, pot_Sp, pot_Dp};
+  for (int K = 0; K < 4; ++K)
+    if ((kmask & (1u << K)) && !pots[K]) return RRQ_ERR_ARG;
+  if (flags & RRQ_F_PLAIN) return RRQ_ERR_UNSUPPORTED;
+  if ((flags & RRQ_F_LEARNED) && !p->has_mlp) return RRQ_ERR_ARG;
+  return run_pairs(p, tg, kmask, flags, nullptr, nullptr, density, pots, workspace,
+                   (hipStream_t)stream, stats);
+}
+
+rrq_status rrq_smooth_potentials(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                                 const double* density, double* pot_S, double* pot_D,
+                                 double* pot_Sp, double* pot_Dp, void* stream) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!density || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
+  double* pots[4] = {pot_S, pot_D, pot_Sp, pot_Dp};
+  for (int K = 0; K < 4; ++K)
+    if ((kmask & (1u << K)) && !pots[K]) return RRQ_ERR_ARG;
+  return launch_smooth_direct(p->dev(), tdev(tg), kmask, density, pots, (hipStream_t)stream) ==
+                 hipSuccess
+             ? RRQ_OK
+             : RRQ_ERR_DEVICE;
 }
 
 rrq_status rrq_apply(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,

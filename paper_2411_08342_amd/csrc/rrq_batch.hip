@@ -425,7 +425,7 @@ struct TileLds {
 // Persistent workgroups take tiles of this order from a queue, so that the workgroups in
 // flight work on a narrow window of consecutive tiles (tiles of one patch are consecutive)
 // and the patch's maps and edge tables are served from L2.
-template <int Q, int T>
+template <int Q, int T, bool POT>
 __global__ __launch_bounds__(BNT)
 __attribute__((amdgpu_waves_per_eu(TileLds<Q, T>::bytes <= 80 * 1024 ? 2 : 1)))
 void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
@@ -883,75 +883,129 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
-      // ---- Step 8 (matrix rows): weights = rows x maps on FP64 MFMA 16x16x4.
-      // Jobs (group, 16-column tile): group 0 = [rD; rDp] x M_D, 1 = rSp x M_Sp, 2 = rS x M_S.
-      // MFMA operand layout: lane l holds A[l%16][l/16], B[l/16][l%16]; result element v of
-      // lane l is D[l/16 + 4v][l%16].
-      {
-        constexpr int NCT = (Q2 + 15) / 16;
-        const double* maps = pd.maps + pd.map_off[P];
+      // ---- Step 8 with the density (potentials mode): pair potentials rows . c_K with the
+      // patch coefficients c_K = M_K sigma_P, minus the smooth rule over the patch nodes
+      if constexpr (POT) {
+        // one wave per target: lanes stride over the row entries and the patch nodes, then
+        // one wave sum per kernel
+        const double* cP = out.pcoef + (int64_t)P * kCoefStride;
+        const bool corr = (out.flags & RRQ_F_CORRECTION) != 0;
         const double sc = fr[12];
-        const int arow = lane & 15, akk = lane >> 4;
-        for (int job = wv; job < 3 * NCT; job += BNT / 64) {
-          const int grp = job / NCT, ct = job % NCT;
-          const double* M = grp == 0 ? maps : (grp == 1 ? maps + 4 * NP * Q2 : maps + 8 * NP * Q2);
-          const int KR = grp == 2 ? 5 * NP : 4 * NP;
-          const double* rowp = nullptr;
-          if (grp == 0) {
-            if (arow < T) rowp = rows + arow * 4 * NP;
-            else if (arow < 2 * T) rowp = rows + T * 13 * NP + (arow - T) * 4 * NP;
-          } else if (arow < T) {
-            rowp = grp == 1 ? rows + T * 4 * NP + arow * 4 * NP : rows + T * 8 * NP + arow * 5 * NP;
+        for (int t = wv; t < nt; t += BNT / 64) {
+          const int64_t k = sorted[tile.y + sub + t];
+          const int64_t g = out.owner[k];
+          const double* rD = rows + t * 4 * NP;
+          const double* rSp = rows + T * 4 * NP + t * 4 * NP;
+          const double* rS = rows + T * 8 * NP + t * 5 * NP;
+          const double* rDp = rows + T * 13 * NP + t * 4 * NP;
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          for (int i = lane; i < 5 * NP; i += 64) a0 += rS[i] * cP[8 * NP + i];
+          for (int i = lane; i < 4 * NP; i += 64) {
+            const double cD = cP[i];
+            a1 += rD[i] * cD;
+            a2 += rSp[i] * cP[4 * NP + i];
+            a3 += rDp[i] * cD;
           }
-          const int bcol = ct * 16 + (lane & 15);
-          const bool bval = bcol < Q2;
-          v4d acc = {0.0, 0.0, 0.0, 0.0};
-          // 8 k-steps per batch: operands loaded first (8 map loads in flight), then 8 MFMAs
-          for (int kb = 0; kb < KR; kb += 32) {
-            double av[8], bv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int k = kb + 4 * u + akk;
-              const bool ok = k < KR;
-              av[u] = (rowp != nullptr && ok) ? rowp[k] : 0.0;
-              bv[u] = (bval && ok) ? M[k * Q2 + bcol] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
-          }
-          if (!bval) continue;
-          const int j = bcol;
-          const int64_t nj = n0 + j;
-          const double rx = pd.node_xyz[nj], ry = pd.node_xyz[pd.N + nj], rz = pd.node_xyz[2 * pd.N + nj];
-          const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
-          const double wj = pd.node_wt[nj] * kInv4Pi;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = (lane >> 4) + 4 * v;
-            int K, t;
-            if (grp == 0) { K = i < T ? 1 : 3; t = i < T ? i : i - T; if (i >= 2 * T) t = T; }
-            else { K = grp == 1 ? 2 : 0; t = i < T ? i : T; }
-            if (t >= nt || !(out.kmask & (1u << K)) || out.w[K] == nullptr) continue;
-            const int64_t k = sorted[tile.y + sub + t];
-            const int64_t g = out.owner[k];
-            double val = acc[v];
-            if (K == 0) val *= sc;
-            else if (K == 3) val /= sc;
-            if ((out.flags & RRQ_F_CORRECTION) && j != sself[t]) {
-              const double d0 = tg.xyz[g] - rx, d1 = tg.xyz[tg.T + g] - ry, d2 = tg.xyz[2 * tg.T + g] - rz;
+          a0 *= sc;
+          a3 /= sc;
+          if (corr) {
+            const double x0 = tg.xyz[g], x1 = tg.xyz[tg.T + g], x2 = tg.xyz[2 * tg.T + g];
+            const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
+            for (int j = lane; j < Q2; j += 64) {
+              if (j == sself[t]) continue;
+              const int64_t nj = n0 + j;
+              const double d0 = x0 - pd.node_xyz[nj];
+              const double d1 = x1 - pd.node_xyz[pd.N + nj];
+              const double d2 = x2 - pd.node_xyz[2 * pd.N + nj];
+              const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
               const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
-              const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
               const double dn = d0 * v0 + d1 * v1 + d2 * v2;
               const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
-              double kv;
-              if (K == 0) kv = 1.0 / R;
-              else if (K == 1) kv = dn / R3;
-              else if (K == 2) kv = -dnt / R3;
-              else kv = (v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2);
-              val -= kv * wj;
+              const double f = pd.node_wt[nj] * kInv4Pi * out.dens[nj];
+              a0 -= f / R;
+              a1 -= f * (dn / R3);
+              a2 -= f * (-dnt / R3);
+              a3 -= f * ((v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2));
             }
-            out.w[K][out.pair_off[k] + j] = val;
+          }
+          a0 = wave_sum(a0);
+          a1 = wave_sum(a1);
+          a2 = wave_sum(a2);
+          a3 = wave_sum(a3);
+          if (lane < 4 && (out.kmask & (1u << lane)))
+            out.pairpot[k * 4 + lane] = lane == 0 ? a0 : (lane == 1 ? a1 : (lane == 2 ? a2 : a3));
+        }
+      } else {
+        // ---- Step 8 (matrix rows): weights = rows x maps on FP64 MFMA 16x16x4.
+        // Jobs (group, 16-column tile): group 0 = [rD; rDp] x M_D, 1 = rSp x M_Sp, 2 = rS x M_S.
+        // MFMA operand layout: lane l holds A[l%16][l/16], B[l/16][l%16]; result element v of
+        // lane l is D[l/16 + 4v][l%16].
+        {
+          constexpr int NCT = (Q2 + 15) / 16;
+          const double* maps = pd.maps + pd.map_off[P];
+          const double sc = fr[12];
+          const int arow = lane & 15, akk = lane >> 4;
+          for (int job = wv; job < 3 * NCT; job += BNT / 64) {
+            const int grp = job / NCT, ct = job % NCT;
+            const double* M = grp == 0 ? maps : (grp == 1 ? maps + 4 * NP * Q2 : maps + 8 * NP * Q2);
+            const int KR = grp == 2 ? 5 * NP : 4 * NP;
+            const double* rowp = nullptr;
+            if (grp == 0) {
+              if (arow < T) rowp = rows + arow * 4 * NP;
+              else if (arow < 2 * T) rowp = rows + T * 13 * NP + (arow - T) * 4 * NP;
+            } else if (arow < T) {
+              rowp = grp == 1 ? rows + T * 4 * NP + arow * 4 * NP : rows + T * 8 * NP + arow * 5 * NP;
+            }
+            const int bcol = ct * 16 + (lane & 15);
+            const bool bval = bcol < Q2;
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            // 8 k-steps per batch: operands loaded first (8 map loads in flight), then 8 MFMAs
+            for (int kb = 0; kb < KR; kb += 32) {
+              double av[8], bv[8];
+  #pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const int k = kb + 4 * u + akk;
+                const bool ok = k < KR;
+                av[u] = (rowp != nullptr && ok) ? rowp[k] : 0.0;
+                bv[u] = (bval && ok) ? M[k * Q2 + bcol] : 0.0;
+              }
+  #pragma unroll
+              for (int u = 0; u < 8; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+            }
+            if (!bval) continue;
+            const int j = bcol;
+            const int64_t nj = n0 + j;
+            const double rx = pd.node_xyz[nj], ry = pd.node_xyz[pd.N + nj], rz = pd.node_xyz[2 * pd.N + nj];
+            const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
+            const double wj = pd.node_wt[nj] * kInv4Pi;
+  #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int i = (lane >> 4) + 4 * v;
+              int K, t;
+              if (grp == 0) { K = i < T ? 1 : 3; t = i < T ? i : i - T; if (i >= 2 * T) t = T; }
+              else { K = grp == 1 ? 2 : 0; t = i < T ? i : T; }
+              if (t >= nt || !(out.kmask & (1u << K)) || out.w[K] == nullptr) continue;
+              const int64_t k = sorted[tile.y + sub + t];
+              const int64_t g = out.owner[k];
+              double val = acc[v];
+              if (K == 0) val *= sc;
+              else if (K == 3) val /= sc;
+              if ((out.flags & RRQ_F_CORRECTION) && j != sself[t]) {
+                const double d0 = tg.xyz[g] - rx, d1 = tg.xyz[tg.T + g] - ry, d2 = tg.xyz[2 * tg.T + g] - rz;
+                const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
+                const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
+                const double dn = d0 * v0 + d1 * v1 + d2 * v2;
+                const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
+                double kv;
+                if (K == 0) kv = 1.0 / R;
+                else if (K == 1) kv = dn / R3;
+                else if (K == 2) kv = -dnt / R3;
+                else kv = (v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2);
+                val -= kv * wj;
+              }
+              out.w[K][out.pair_off[k] + j] = val;
+            }
           }
         }
       }
@@ -973,30 +1027,132 @@ size_t tile_lds_bytes(int q, int T) {
 
 int tile_supported(int q, int T) { return tile_lds_bytes(q, T) > 0 && tile_lds_bytes(q, T) <= 160 * 1024; }
 
-hipError_t launch_pair_tile(int q, int T, int grid, const PlanDev& pd, const OrderDev& od,
-                            const TargetsDev& tg, const AssembleOut& out, const SolveOpts& so,
-                            const int4* tiles, const int64_t* qtile, unsigned long long* qctr,
-                            const int64_t* sorted, hipStream_t st) {
+template <int Q, int TT, bool POT>
+static hipError_t launch_tile_case(int grid, const PlanDev& pd, const OrderDev& od,
+                                   const TargetsDev& tg, const AssembleOut& out,
+                                   const SolveOpts& so, const int4* tiles, const int64_t* qtile,
+                                   unsigned long long* qctr, const int64_t* sorted,
+                                   hipStream_t st) {
+  const size_t lds = TileLds<Q, TT>::bytes;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pair_tile<Q, TT, POT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_pair_tile<Q, TT, POT>), dim3(grid), dim3(BNT), lds, st, pd, od, tg, out,
+                     so, tiles, qtile, qctr, sorted);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_tile(int q, int T, bool pot, int grid, const PlanDev& pd,
+                            const OrderDev& od, const TargetsDev& tg, const AssembleOut& out,
+                            const SolveOpts& so, const int4* tiles, const int64_t* qtile,
+                            unsigned long long* qctr, const int64_t* sorted, hipStream_t st) {
   if (tg.nnz <= 0) return hipSuccess;
   switch (q * 100 + T) {
-#define X(Q, TT)                                                                               \
-  case Q * 100 + TT: {                                                                        \
-    const size_t lds = TileLds<Q, TT>::bytes;                                                 \
-    static bool attr = false;                                                                 \
-    if (!attr) {                                                                              \
-      hipError_t e = hipFuncSetAttribute((const void*)k_pair_tile<Q, TT>,                     \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-      if (e != hipSuccess) return e;                                                          \
-      attr = true;                                                                            \
-    }                                                                                         \
-    hipLaunchKernelGGL((k_pair_tile<Q, TT>), dim3(grid), dim3(BNT), lds, st, pd, od, tg, out, \
-                       so, tiles, qtile, qctr, sorted);                                            \
-    break;                                                                                    \
-  }
+#define X(Q, TT)                                                                              \
+  case Q * 100 + TT:                                                                         \
+    return pot ? launch_tile_case<Q, TT, true>(grid, pd, od, tg, out, so, tiles, qtile, qctr, \
+                                               sorted, st)                                    \
+               : launch_tile_case<Q, TT, false>(grid, pd, od, tg, out, so, tiles, qtile,      \
+                                                qctr, sorted, st);
     RRQ_TILE_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// potentials mode: patch coefficients c = maps . sigma_P, per-target sums of the pair
+// potentials, and the direct smooth-rule sum over all nodes (small meshes)
+// ---------------------------------------------------------------------------------------
+__global__ void k_patch_coef(PlanDev pd, const double* dens, double* pcoef) {
+  for (int P = blockIdx.x; P < pd.npatch; P += gridDim.x) {
+    const int q = pd.order[P], q2 = q * q, nr = 13 * np_of(q);
+    const double* M = pd.maps + pd.map_off[P];
+    const double* s = dens + pd.node_off[P];
+    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+      double acc = 0.0;
+      for (int j = 0; j < q2; ++j) acc += M[(int64_t)r * q2 + j] * s[j];
+      pcoef[(int64_t)P * kCoefStride + r] = acc;
+    }
+  }
+}
+
+__global__ void k_pot_reduce(TargetsDev tg, uint32_t kmask, const double* pairpot, double* p0,
+                             double* p1, double* p2, double* p3) {
+  double* Pp[4] = {p0, p1, p2, p3};
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tg.T;
+       t += (int64_t)gridDim.x * blockDim.x)
+    for (int K = 0; K < 4; ++K) {
+      if (!(kmask & (1u << K))) continue;
+      double acc = 0.0;
+      for (int64_t k = tg.near_ptr[t]; k < tg.near_ptr[t + 1]; ++k) acc += pairpot[k * 4 + K];
+      Pp[K][t] = acc;
+    }
+}
+
+__global__ void k_smooth_direct(PlanDev pd, TargetsDev tg, uint32_t kmask, const double* dens,
+                                double* p0, double* p1, double* p2, double* p3) {
+  __shared__ double red[4][BNT / 64];
+  double* Pp[4] = {p0, p1, p2, p3};
+  for (int64_t t = blockIdx.x; t < tg.T; t += gridDim.x) {
+    const double x0 = tg.xyz[t], x1 = tg.xyz[tg.T + t], x2 = tg.xyz[2 * tg.T + t];
+    const double nt0 = tg.nrm[t], nt1 = tg.nrm[tg.T + t], nt2 = tg.nrm[2 * tg.T + t];
+    const int sp = tg.self_patch[t];
+    const int64_t self = sp >= 0 ? pd.node_off[sp] + tg.self_node[t] : -1;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = threadIdx.x; j < pd.N; j += blockDim.x) {
+      if (j == self) continue;
+      const double d0 = x0 - pd.node_xyz[j], d1 = x1 - pd.node_xyz[pd.N + j],
+                   d2 = x2 - pd.node_xyz[2 * pd.N + j];
+      const double v0 = pd.node_nrm[j], v1 = pd.node_nrm[pd.N + j], v2 = pd.node_nrm[2 * pd.N + j];
+      const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
+      const double dn = d0 * v0 + d1 * v1 + d2 * v2;
+      const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
+      const double f = pd.node_wt[j] * kInv4Pi * dens[j];
+      acc[0] += f / R;
+      acc[1] += f * (dn / R3);
+      acc[2] += f * (-dnt / R3);
+      acc[3] += f * ((v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2));
+    }
+    for (int K = 0; K < 4; ++K) {
+      const double v = wave_sum(acc[K]);
+      if ((threadIdx.x & 63) == 0) red[K][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && (kmask & (1u << threadIdx.x))) {
+      double s = 0.0;
+      for (int w = 0; w < BNT / 64; ++w) s += red[threadIdx.x][w];
+      Pp[threadIdx.x][t] = s;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_patch_coef(const PlanDev& pd, const double* dens, double* pcoef, hipStream_t st) {
+  const int g = pd.npatch < 4096 ? pd.npatch : 4096;
+  hipLaunchKernelGGL(k_patch_coef, dim3(g > 0 ? g : 1), dim3(256), 0, st, pd, dens, pcoef);
+  return hipGetLastError();
+}
+
+hipError_t launch_pot_reduce(const TargetsDev& tg, uint32_t kmask, const double* pairpot,
+                             double* const* pot, hipStream_t st) {
+  if (tg.T <= 0) return hipSuccess;
+  int64_t g = (tg.T + 255) / 256;
+  hipLaunchKernelGGL(k_pot_reduce, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st, tg,
+                     kmask, pairpot, pot[0], pot[1], pot[2], pot[3]);
+  return hipGetLastError();
+}
+
+hipError_t launch_smooth_direct(const PlanDev& pd, const TargetsDev& tg, uint32_t kmask,
+                                const double* dens, double* const* pot, hipStream_t st) {
+  if (tg.T <= 0) return hipSuccess;
+  const int64_t g = tg.T < 65535 ? tg.T : 65535;
+  hipLaunchKernelGGL(k_smooth_direct, dim3((unsigned)g), dim3(BNT), 0, st, pd, tg, kmask, dens,
+                     pot[0], pot[1], pot[2], pot[3]);
   return hipGetLastError();
 }
 

@@ -74,7 +74,12 @@ struct AssembleOut {
   unsigned long long* counters;   // [8] stats
   const double2* root;      // [4 nnz] singularity-swap roots t0 (root pre-pass)
   const uint8_t* nearf;     // [4 nnz] 1: singularity-swap class, 0: plain rule
+  // potentials mode
+  const double* dens;       // [N] nodal density
+  const double* pcoef;      // [P][kCoefStride] c_D, c_S', c_S of every patch
+  double* pairpot;          // [nnz][4] potential of every pair
 };
+constexpr int kCoefStride = 13 * np_of(kMaxQ);
 
 struct SolveOpts {
   double rho_far, newton_tol;
@@ -110,10 +115,15 @@ hipError_t launch_binning(const TargetsDev& tg, int P, int tile, const int32_t* 
                           const BinOrders& bo, int32_t* cnt, int32_t* fill, int64_t* start,
                           int64_t* tstart, int64_t* ntiles, int64_t* sorted, int4* tiles,
                           int64_t* qtile, unsigned long long* qctr, hipStream_t st);
-hipError_t launch_pair_tile(int q, int T, int grid, const PlanDev& pd, const OrderDev& od,
-                            const TargetsDev& tg, const AssembleOut& out, const SolveOpts& so,
-                            const int4* tiles, const int64_t* qtile, unsigned long long* qctr,
-                            const int64_t* sorted, hipStream_t st);
+hipError_t launch_pair_tile(int q, int T, bool pot, int grid, const PlanDev& pd,
+                            const OrderDev& od, const TargetsDev& tg, const AssembleOut& out,
+                            const SolveOpts& so, const int4* tiles, const int64_t* qtile,
+                            unsigned long long* qctr, const int64_t* sorted, hipStream_t st);
+hipError_t launch_patch_coef(const PlanDev& pd, const double* dens, double* pcoef, hipStream_t st);
+hipError_t launch_pot_reduce(const TargetsDev& tg, uint32_t kmask, const double* pairpot,
+                             double* const* pot, hipStream_t st);
+hipError_t launch_smooth_direct(const PlanDev& pd, const TargetsDev& tg, uint32_t kmask,
+                                const double* dens, double* const* pot, hipStream_t st);
 size_t tile_lds_bytes(int q, int T);
 int tile_supported(int q, int T);
 

@@ -20,7 +20,8 @@ KERNELS = ("S", "D", "Sp", "Dp")
 EXPORTED = ("rrq_plan_create", "rrq_plan_refit", "rrq_plan_destroy", "rrq_workspace_size",
             "rrq_pair_offsets", "rrq_assemble", "rrq_apply", "rrq_autotune", "rrq_graph_create",
             "rrq_graph_launch", "rrq_graph_destroy", "rrq_collect_roots", "rrq_mlp_train",
-            "rrq_mlp_loss_grad", "rrq_mlp_predict", "rrq_plan_set_mlp", "rrq_status_string")
+            "rrq_mlp_loss_grad", "rrq_mlp_predict", "rrq_plan_set_mlp", "rrq_potentials",
+            "rrq_smooth_potentials", "rrq_status_string")
 MLP_PARAMS = 4866
 
 
@@ -93,6 +94,10 @@ def lib():
                                    ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
         L.rrq_apply.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp]
+        L.rrq_potentials.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp,
+                                     vp, ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
+        L.rrq_smooth_potentials.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp,
+                                            vp]
         L.rrq_autotune.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp, vp,
                                    ctypes.c_size_t, ctypes.c_char_p, vp,
                                    ctypes.POINTER(TuneResult)]
@@ -252,6 +257,46 @@ class Assembler:
                                ptr(self.out, "Dp"), self.pair_off.data_ptr(), dens.data_ptr(),
                                ptr(pots, "S"), ptr(pots, "D"), ptr(pots, "Sp"), ptr(pots, "Dp"),
                                _stream()))
+        return pots
+
+
+class Evaluator:
+    """Potentials mode: the correction (rrq_potentials) and the direct smooth rule
+    (rrq_smooth_potentials) applied to a density without storing weights."""
+
+    def __init__(self, plan, dtg, kmask=RRQ_K_ALL):
+        import torch
+        self.plan, self.dtg, self.kmask = plan, dtg, kmask
+        self._t = dtg.cstruct()
+        sz = ctypes.c_size_t()
+        _check(lib().rrq_workspace_size(plan.handle, ctypes.byref(self._t), ctypes.byref(sz)))
+        self.workspace = torch.empty(int(sz.value), dtype=torch.uint8, device="cuda")
+
+    def _pots(self):
+        import torch
+        return {k: (torch.empty(self.dtg.ntarget, dtype=torch.float64, device="cuda")
+                    if self.kmask & (1 << i) else None) for i, k in enumerate(KERNELS)}
+
+    def potentials(self, density, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV, stats=False):
+        import torch
+        dens = torch.as_tensor(density, dtype=torch.float64, device="cuda").contiguous()
+        pots = self._pots()
+        ptr = [pots[k].data_ptr() if pots[k] is not None else None for k in KERNELS]
+        st = Stats() if stats else None
+        _check(lib().rrq_potentials(self.plan.handle, ctypes.byref(self._t), self.kmask, flags,
+                                    dens.data_ptr(), ptr[0], ptr[1], ptr[2], ptr[3],
+                                    self.workspace.data_ptr(), self.workspace.numel(), _stream(),
+                                    ctypes.byref(st) if st is not None else None))
+        return (pots, st.as_dict()) if stats else pots
+
+    def smooth(self, density):
+        import torch
+        dens = torch.as_tensor(density, dtype=torch.float64, device="cuda").contiguous()
+        pots = self._pots()
+        ptr = [pots[k].data_ptr() if pots[k] is not None else None for k in KERNELS]
+        _check(lib().rrq_smooth_potentials(self.plan.handle, ctypes.byref(self._t), self.kmask,
+                                           dens.data_ptr(), ptr[0], ptr[1], ptr[2], ptr[3],
+                                           _stream()))
         return pots
 
 

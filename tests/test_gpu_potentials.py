@@ -1,0 +1,403 @@
+"""GPU tests of the potentials mode (the correction applied to a density without storing the
+weights) and of the whole method end to end:
+
+* pair potentials against the oracle, with the weights parity gate carried to the potential
+  level: |p_gpu - W_or . f| <= 1e-11 sum_j |W_raw,j f_j| + 30 |dW_ulp . f| (dW_ulp as in the
+  weights parity tests: the larger change of the oracle under rounding-level perturbations);
+* per-target potentials against rrq_assemble followed by rrq_apply (same numbers, another
+  rounding order);
+* the direct smooth rule against a host sum;
+* Green's representation formula for a harmonic function on the star surface: smooth rule +
+  correction reproduces u/2 (principal value) or 0 (exterior limit) on the surface, u inside
+  and 0 outside, with the error falling as the patches are refined.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2411_08342_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ("S", "D", "Sp", "Dp")
+TOL = 1e-11
+ULP_FACTOR = 30.0
+
+
+def _density(surf):
+    x, y, z = surf["node_xyz"]
+    return 0.7 + x * x - 0.4 * y * z + 0.3 * z + 0.2 * x * y * z
+
+
+def _one_pair_targets(tg, pairs):
+    """Targets that each own exactly one near pair: the per-target potential is then the pair
+    potential."""
+    owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
+    t = owner[pairs]
+    return dict(ntarget=len(pairs), xyz=np.ascontiguousarray(tg["xyz"][:, t]),
+                nrm=np.ascontiguousarray(tg["nrm"][:, t]),
+                self_patch=np.ascontiguousarray(tg["self_patch"][t]),
+                self_node=np.ascontiguousarray(tg["self_node"][t]),
+                near_ptr=np.arange(len(pairs) + 1, dtype=np.int64),
+                near_patch=np.ascontiguousarray(tg["near_patch"][pairs]))
+
+
+def _evaluate(surf, tg, dens, flags=None, smooth=False):
+    import torch
+    from paper_2411_08342_amd import rrq
+    if flags is None:
+        flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    ev = rrq.Evaluator(plan, rrq.DeviceTargets(tg))
+    pots = ev.potentials(dens, flags=flags)
+    sm = ev.smooth(dens) if smooth else None
+    torch.cuda.synchronize()
+    out = {k: pots[k].cpu().numpy() for k in KERNELS}
+    if sm is not None:
+        sm = {k: sm[k].cpu().numpy() for k in KERNELS}
+    plan.close()
+    return out, sm
+
+
+def _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=True):
+    from oracle.assemble import pair_block
+    from paper_2411_08342_amd import rrq
+    f = _density(surf)
+    one = _one_pair_targets(tg, pairs)
+    flags = rrq.RRQ_F_CORRECTION | (rrq.RRQ_F_ONSURF_PV if onsurf_pv else 0)
+    gpu, _ = _evaluate(surf, one, f, flags)
+    fits, fits_svd = {}, {}
+    worst = {k: 0.0 for k in KERNELS}
+    limited = 0
+    for i in range(len(pairs)):
+        P = int(one["near_patch"][i])
+        n0, n1 = surf["node_off"][P], surf["node_off"][P + 1]
+        fi = f[n0:n1]
+        ref, _ = pair_block(surf, one, fits, i, P, True, onsurf_pv)
+        raw, _ = pair_block(surf, one, fits, i, P, False, onsurf_pv)
+        pert = None
+        for k in KERNELS:
+            assert np.isfinite(gpu[k][i]), (k, i)
+            ep = abs(gpu[k][i] - ref[k] @ fi)
+            sp = np.sum(np.abs(raw[k] * fi))
+            worst[k] = max(worst[k], ep / sp)
+            if ep <= TOL * sp:
+                continue
+            if pert is None:
+                one2 = dict(one)
+                x = np.array(one["xyz"], copy=True)
+                x[:, i] *= 1.0 + 2.0 ** -52
+                one2["xyz"] = x
+                s2 = dict(surf)
+                e = np.array(surf["edge_xyz"], copy=True)
+                sg = np.random.default_rng(i).choice([-1.0, 1.0], size=e.shape)
+                s2["edge_xyz"] = e * (1.0 + 2.0 ** -52 * sg)
+                pert = (pair_block(surf, one2, fits, i, P, True, onsurf_pv)[0],
+                        pair_block(surf, one, fits_svd, i, P, True, onsurf_pv, "svd")[0],
+                        pair_block(s2, one, {}, i, P, True, onsurf_pv)[0])
+                limited += 1
+            dpot = max(abs((pp[k] - ref[k]) @ fi) for pp in pert)
+            assert ep <= TOL * sp + ULP_FACTOR * dpot, (k, i, ep, sp, dpot)
+    print(f"pair potentials over {len(pairs)} pairs: worst |dp| / sum|W_raw f| "
+          + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()) + f"; ulp-limited pairs {limited}")
+
+
+def test_pair_potentials_match_oracle_sphere():
+    surf, tg, _ = wl.config1()
+    rng = np.random.default_rng(11)
+    nnz = len(tg["near_patch"])
+    pairs = np.sort(rng.choice(nnz, size=min(240, nnz), replace=False))
+    _pair_potentials_vs_oracle(surf, tg, pairs)
+
+
+def test_pair_potentials_match_oracle_star_exterior_limit():
+    surf, tg, _ = wl.config2(n=3)
+    rng = np.random.default_rng(12)
+    pairs = np.sort(rng.choice(len(tg["near_patch"]), size=160, replace=False))
+    _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=False)
+
+
+def _weight_scale(surf, tg, w_raw, f):
+    """sum over the near pairs of a target of sum_j |W_raw,j f_j|, per target."""
+    order = np.asarray(surf["order"])[tg["near_patch"]].astype(np.int64)
+    sizes = order * order
+    pair = np.repeat(np.arange(len(sizes)), sizes)
+    within = np.arange(sizes.sum()) - np.repeat(np.cumsum(sizes) - sizes, sizes)
+    node = surf["node_off"][tg["near_patch"]][pair] + within
+    owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
+    return np.bincount(owner[pair], weights=np.abs(w_raw * f[node]), minlength=tg["ntarget"])
+
+
+def _rounding_scale(surf, tg, targets, f, correction, onsurf_pv):
+    """Per target: sum over its near pairs of sum_i |r_i| (|M| |f|)_i (+ sum_j |s_j f_j|, the
+    smooth rule, with the correction): the sum of the absolute values of every product the two
+    contraction orders add up (rows r from the oracle; M the patch maps)."""
+    from oracle import rrq as orr
+    from oracle.assemble import fit_patch, patch_arrays
+    owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
+    fits = {}
+    out = {k: np.zeros(len(targets)) for k in KERNELS}
+    for n, t in enumerate(targets):
+        for i in range(tg["near_ptr"][t], tg["near_ptr"][t + 1]):
+            P = int(tg["near_patch"][i])
+            if P not in fits:
+                fits[P] = fit_patch(surf, P)
+            fit = fits[P]
+            xl, nl = fit.frame.point(tg["xyz"][:, t]), fit.frame.vector(tg["nrm"][:, t])
+            sn = int(tg["self_node"][t]) if int(tg["self_patch"][t]) == P else -1
+            u = orr.choose_u(fit, xl, nl, sn)
+            V, Q, dQ, Om, dOm, _ = orr.line_integrals(fit, xl, nl, u, 2 * fit.p)
+            rD, rSp, rS, rDp = orr.moments_rows(fit, xl, nl, V, Q, dQ, Om, dOm)
+            fi = np.abs(f[surf["node_off"][P]:surf["node_off"][P + 1]])
+            sc = fit.frame.s
+            big = {"S": np.abs(rS) @ (np.abs(fit.M_S) @ fi) * sc,
+                   "D": np.abs(rD) @ (np.abs(fit.M_D) @ fi),
+                   "Sp": np.abs(rSp) @ (np.abs(fit.M_Sp) @ fi),
+                   "Dp": np.abs(rDp) @ (np.abs(fit.M_D) @ fi) / sc}
+            if sn >= 0 and onsurf_pv:                  # jump rows of the principal values
+                _, g = orr.H_basis(fit.p, xl)
+                z = np.zeros(g.shape[1])
+                big["D"] += 0.5 * np.abs(np.concatenate([z, g[0], g[1], g[2]])) @ (np.abs(fit.M_D) @ fi)
+                cr = np.abs(np.concatenate([nl @ g, np.cross(nl[None, :], g.T).T.reshape(-1)]))
+                big["Sp"] += 0.5 * cr @ (np.abs(fit.M_Sp) @ fi)
+            if correction:
+                xyz, nrm, wt, _ = patch_arrays(surf, P)
+                keep = np.ones(len(wt), bool)
+                if sn >= 0:
+                    keep[sn] = False
+                sm = orr.smooth_kernels(tg["xyz"][:, t], tg["nrm"][:, t], xyz[keep], nrm[keep],
+                                        wt[keep])
+                for k in KERNELS:
+                    big[k] += np.sum(np.abs(sm[k]) * fi[keep])
+            for k in KERNELS:
+                out[k][n] += big[k]
+    return out
+
+
+@pytest.mark.parametrize("case", ["sphere", "star", "mixed"])
+def test_potentials_match_assemble_apply(case):
+    """rrq_potentials = rrq_apply(rrq_assemble) per target.  Both add up the same products,
+    the first as rows . (maps . f), the second as (rows . maps) . f, so they differ by
+    rounding: at most 2 gamma_n times the sum of the absolute products (gamma_n = n u / (1 -
+    n u), u = 2^-53, n = terms of one pair + pairs of the target), checked on a sample of
+    targets with that sum from the oracle's rows; every target is checked against a loose
+    bound (1e-9 of sum_j |W_raw,j f_j|) that catches a missing or misplaced pair."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    if case == "sphere":
+        surf, tg, _ = wl.config1()
+    elif case == "star":
+        surf, tg, _ = wl.config2(n=4)
+    else:
+        surf, tg, _ = wl.config3(n_ell=2, nmin=2, nmax=3, mean_targets=40)
+    f = _density(surf)
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    dtg = rrq.DeviceTargets(tg)
+    asm = rrq.Assembler(plan, dtg)
+    ev = rrq.Evaluator(plan, dtg)
+    rng = np.random.default_rng(21)
+    sample = np.sort(rng.choice(tg["ntarget"], size=min(24, tg["ntarget"]), replace=False))
+    qmax = int(np.max(surf["order"]))
+    npair = int(np.max(np.diff(tg["near_ptr"])))
+    n = 17 * qmax * (qmax + 1) // 2 + qmax * qmax + npair + 4
+    gamma = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+    for flags in (rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV, rrq.RRQ_F_CORRECTION, 0):
+        asm.assemble(flags=flags)
+        ref = asm.apply(f)
+        got, st = ev.potentials(f, flags=flags, stats=True)
+        if flags & rrq.RRQ_F_CORRECTION:
+            asm.assemble(flags=flags & ~rrq.RRQ_F_CORRECTION)
+        torch.cuda.synchronize()
+        assert st["pairs"] == len(tg["near_patch"])
+        big = _rounding_scale(surf, tg, sample, f, bool(flags & rrq.RRQ_F_CORRECTION),
+                              bool(flags & rrq.RRQ_F_ONSURF_PV))
+        for k in KERNELS:
+            g, r = got[k].cpu().numpy(), ref[k].cpu().numpy()
+            assert np.all(np.isfinite(g))
+            e = np.abs(g - r)
+            sc = _weight_scale(surf, tg, asm.out[k].cpu().numpy(), f)
+            es = e[sample] / (2 * gamma * big[k])
+            print(f"{case} flags {flags} {k}: max |pot - apply| / sum|W_raw f| "
+                  f"{np.max(e / np.maximum(sc, 1e-300)):.2e}; sample, / (2 gamma_n sum|products|) "
+                  f"{np.max(es):.2e}")
+            assert np.all(es <= 1.0), (k, np.max(es))
+            assert np.all(e <= 1e-9 * sc), (k, np.max(e / np.maximum(sc, 1e-300)))
+    with pytest.raises(rrq.RRQError):
+        ev.potentials(f, flags=rrq.RRQ_F_PLAIN)
+    with pytest.raises(rrq.RRQError):
+        ev.potentials(f, flags=rrq.RRQ_F_LEARNED)         # no network installed
+    plan.close()
+
+
+def test_potentials_kernel_mask_and_empty_rows():
+    """Kernels outside the mask are not written; targets without near patches get zero."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    # drop the near lists of every third target
+    keep = np.arange(tg["ntarget"]) % 3 != 0
+    cnt = np.diff(tg["near_ptr"]) * keep
+    owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
+    tg2 = dict(tg, near_ptr=np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64),
+               near_patch=np.ascontiguousarray(tg["near_patch"][keep[owner]]))
+    f = _density(surf)
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    dtg = rrq.DeviceTargets(tg2)
+    full = rrq.Evaluator(plan, dtg).potentials(f)
+    ev = rrq.Evaluator(plan, dtg, kmask=rrq.RRQ_K_D | rrq.RRQ_K_SP)
+    part = ev.potentials(f)
+    torch.cuda.synchronize()
+    assert part["S"] is None and part["Dp"] is None
+    for k in ("D", "Sp"):
+        assert torch.equal(part[k], full[k])
+    for k in KERNELS:
+        assert torch.all(full[k][torch.tensor(~keep, device="cuda")] == 0)
+        assert torch.all(full[k][torch.tensor(keep, device="cuda")] != 0)
+    plan.close()
+
+
+def test_smooth_direct_matches_host_sum():
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    f = _density(surf)
+    _, sm = _evaluate(surf, tg, f, smooth=True)
+    y, nu, w = surf["node_xyz"], surf["node_nrm"], surf["node_wt"]
+    for t in range(tg["ntarget"]):
+        x, nt = tg["xyz"][:, t], tg["nrm"][:, t]
+        m = np.ones(y.shape[1], bool)
+        if tg["self_patch"][t] >= 0:
+            m[surf["node_off"][tg["self_patch"][t]] + tg["self_node"][t]] = False
+        d = x[:, None] - y[:, m]
+        R = np.linalg.norm(d, axis=0)
+        dn = np.sum(d * nu[:, m], axis=0)
+        dnt = nt @ d
+        wf = w[m] * f[m] / (4 * math.pi)
+        ref = {"S": np.sum(wf / R), "D": np.sum(wf * dn / R ** 3), "Sp": np.sum(-wf * dnt / R ** 3),
+               "Dp": np.sum(wf * ((nt @ nu[:, m]) / R ** 3 - 3 * dn * dnt / R ** 5))}
+        for k in KERNELS:
+            sc = np.sum(np.abs(wf)) / np.min(R) ** (1 if k == "S" else 2 if k != "Dp" else 3)
+            assert abs(sm[k][t] - ref[k]) <= 1e-13 * sc, (t, k, sm[k][t], ref[k])
+
+
+X0 = np.array([1.9, 0.7, -1.2])          # source of the harmonic function, outside the star
+
+
+def _harmonic(y, nu):
+    d = y - X0[:, None]
+    r = np.linalg.norm(d, axis=0)
+    return 1.0 / r, -np.sum(d * nu, axis=0) / r ** 3
+
+
+def _green_errors(n, q=8):
+    """Max errors of Green's formula for u = 1/|y - X0| (harmonic inside the star surface),
+    sigma = du/dnu, mu = u, with the smooth rule + RRQ correction:
+      on the surface, principal values:  S sigma - D mu - u/2,  S' sigma - D' mu - sigma/2;
+      on the surface, exterior limits:   S sigma - D mu,        S' sigma - D' mu;
+      inside near the surface:           S sigma - D mu - u;    outside:  S sigma - D mu."""
+    from paper_2411_08342_amd import rrq
+    surf = wl.discretize(wl.cubed_sphere_patches(n, radial=wl.star_radius), np.full(6 * n * n, q))
+    x, nn, sp, sn = wl.node_targets(surf)
+    assert np.all(np.sum(x * nn, axis=0) > 0)             # outward normals
+    # off-surface targets: random nodes moved along the normal by 1e-3 .. 0.1 patch diameters,
+    # either side; the node lies on both the exact and the discretised surface, so the side
+    # of the target is the same for both (checked against the radial test of the star)
+    rng = np.random.default_rng(40 + n)
+    _, diam = wl.patch_center_diam(surf)
+    pick = rng.choice(x.shape[1], size=24 * n * n, replace=False)
+    dist = np.exp(rng.uniform(math.log(1e-3), math.log(0.1), len(pick))) * diam[sp[pick]]
+    side = np.where(rng.uniform(size=len(pick)) < 0.5, -1.0, 1.0)
+    xo = x[:, pick] + side * dist * nn[:, pick]
+    no = nn[:, pick]
+    inside = side < 0
+    r = np.linalg.norm(xo, axis=0)
+    assert np.array_equal(inside, r < wl.star_radius(*(xo / r)))
+    xyz = np.concatenate([x, xo], axis=1)
+    nrm = np.concatenate([nn, no], axis=1)
+    m = xo.shape[1]
+    tg = wl.make_targets(surf, xyz, nrm, np.concatenate([sp, np.full(m, -1, np.int32)]),
+                         np.concatenate([sn, np.full(m, -1, np.int32)]), eta=1.5)
+    u, dudn = _harmonic(surf["node_xyz"], surf["node_nrm"])
+    ut, dut = _harmonic(xyz, nrm)
+    N = x.shape[1]
+    scale = np.max(np.abs(u)), np.max(np.abs(dudn))
+    out = {}
+    for pv in (True, False):
+        flags = rrq.RRQ_F_CORRECTION | (rrq.RRQ_F_ONSURF_PV if pv else 0)
+        ps, sm = _evaluate(surf, tg, dudn, flags, smooth=True)
+        pd, smd = _evaluate(surf, tg, u, flags, smooth=True)
+        S = ps["S"] + sm["S"]
+        Sp = ps["Sp"] + sm["Sp"]
+        D = pd["D"] + smd["D"]
+        Dp = pd["Dp"] + smd["Dp"]
+        half = 0.5 if pv else 0.0
+        out["onsurf_pv" if pv else "onsurf_ext"] = (
+            np.max(np.abs(S[:N] - D[:N] - half * ut[:N])) / scale[0],
+            np.max(np.abs(Sp[:N] - Dp[:N] - half * dut[:N])) / scale[1])
+        if pv:
+            e = S[N:] - D[N:] - np.where(inside, ut[N:], 0.0)
+            out["inside"] = np.max(np.abs(e[inside])) / scale[0]
+            out["outside"] = np.max(np.abs(e[~inside])) / scale[0]
+    return out
+
+
+def test_green_identity_star_converges():
+    """Discretisation error of the whole method (smooth rule + RRQ correction) on the star
+    surface, q = 8, 96 and 384 patches.  Gates: the measured errors at 384 patches with a
+    factor 3 of margin, and a convergence factor between the two meshes of at least 8 for
+    S - D (about h^6 was measured) and 4 for the hypersingular S' - D'."""
+    errs = {n: _green_errors(n) for n in (4, 8)}
+    for n, e in errs.items():
+        print(f"n={n} ({6 * n * n} patches, q=8): " + ", ".join(
+            f"{k} {v[0]:.2e}/{v[1]:.2e}" if isinstance(v, tuple) else f"{k} {v:.2e}"
+            for k, v in e.items()))
+    c, f = errs[4], errs[8]
+    for key in ("onsurf_pv", "onsurf_ext"):
+        assert f[key][0] < 3e-5 and f[key][0] < c[key][0] / 8, key
+        assert f[key][1] < 1.5e-2 and f[key][1] < c[key][1] / 4, key
+    for key in ("inside", "outside"):
+        assert f[key] < 3e-5 and f[key] < c[key] / 8, key
+
+
+def _solid_harmonic_8(p):
+    """0.70 Re (x + iy)^8 + z Im (x + iy)^7 (harmonic) and its gradient."""
+    x, y, z = p
+    w = x + 1j * y
+    u = 0.70 * (w ** 8).real + z * (w ** 7).imag
+    g = np.stack([0.70 * (8 * w ** 7).real + z * (7 * w ** 6).imag,
+                  -0.70 * (8 * w ** 7).imag + z * (7 * w ** 6).real,
+                  (w ** 7).imag])
+    return u, g
+
+
+def test_green_extinction_on_exterior_grid_sphere():
+    """The accuracy protocol of the unit-sphere example of Sec. 6 with quadrilateral patches:
+    S[du/dnu] - D[u] = 0 at exterior points for u harmonic inside (u a degree-8 solid
+    harmonic), relative max error over an equispaced grid on [-1.5, 1.5]^3 outside the
+    sphere (52^3 here).  Gates: the measured errors with a factor 10 of margin."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    g = np.linspace(-1.5, 1.5, 52)
+    P = np.stack([a.ravel() for a in np.meshgrid(g, g, g, indexing="ij")])
+    P = np.ascontiguousarray(P[:, np.linalg.norm(P, axis=0) > 1.0])
+    m = P.shape[1]
+    umax = np.max(np.abs(_solid_harmonic_8(P)[0]))
+    res = {}
+    for q, n in ((8, 6), (8, 8), (10, 6)):
+        surf = wl.discretize(wl.cubed_sphere_patches(n), np.full(6 * n * n, q))
+        mu, gu = _solid_harmonic_8(surf["node_xyz"])
+        sig = np.sum(gu * surf["node_nrm"], axis=0)
+        tg = wl.make_targets(surf, P, np.zeros_like(P), np.full(m, -1, np.int32),
+                             np.full(m, -1, np.int32), eta=1.5)
+        plan = rrq.Plan(rrq.DeviceSurface(surf))
+        ev = rrq.Evaluator(plan, rrq.DeviceTargets(tg), kmask=rrq.RRQ_K_S | rrq.RRQ_K_D)
+        ps = ev.potentials(sig, flags=rrq.RRQ_F_CORRECTION)
+        pdd = ev.potentials(mu, flags=rrq.RRQ_F_CORRECTION)
+        ss, sd = ev.smooth(sig), ev.smooth(mu)
+        torch.cuda.synchronize()
+        e = (ps["S"] + ss["S"] - pdd["D"] - sd["D"]).abs().max().item() / umax
+        res[(q, n)] = e
+        print(f"sphere q={q}, {6 * n * n} patches, {m} exterior points, "
+              f"{len(tg['near_patch'])} near pairs: E_inf {e:.2e}", flush=True)
+        plan.close()
+    assert res[(8, 6)] < 6e-9 and res[(8, 8)] < 3e-9 and res[(10, 6)] < 5e-10
