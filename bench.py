@@ -23,8 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": "6956501a6f92631caa7f32c803d97b9e22af3052e1536212a46a440d01327eb3",
-           "fetch_bytes": 7795757783, "write_bytes": 4433518400}
+TRAFFIC = {"src_sha256": "5500f8e7b262ff586dad061e9c4ecdfc49b54b5b13edca80c677f35d762c8de4",
+           "fetch_bytes": 1495295279, "write_bytes": 3892236544}
 
 
 def flops_per_pair(q):

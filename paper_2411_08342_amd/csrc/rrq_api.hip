@@ -364,7 +364,7 @@ static TargetsDev tdev(const rrq_targets* tg) {
 }
 
 // workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
-// start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders] u64 |
+// start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders][xcds] u64 |
 // sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
 // nearf[4 nnz] u8 | pairpot[nnz][4] f64 | pcoef[P][kCoefStride] f64
 struct WsLayout {
@@ -383,7 +383,7 @@ static WsLayout ws_layout(int64_t nnz, int P) {
   w.start = o; o = al(o + (size_t)(P + 1) * 8);
   w.tstart = o; o = al(o + (size_t)(P + 1) * 8);
   w.ntiles = o; o = al(o + 8);
-  w.queue = o; o = al(o + 8 * (2 * kNumOrders + 1));
+  w.queue = o; o = al(o + 8 * (kNumOrders + 1 + kNumOrders * kXcds));
   w.sorted = o; o = al(o + n * 8);
   w.tiles = o; o = al(o + (n / 4 + (size_t)P + 1) * 16);
   w.part = o; o = al(o + (size_t)scan_partials((int64_t)n) * 8);
@@ -506,7 +506,7 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       while (T > 4 && !tile_supported(q, T)) T /= 2;
       if (!tile_supported(q, T)) return RRQ_ERR_UNSUPPORTED;
       if (launch_pair_tile(q, T, pot, p->grid[q], pd, p->od[q], td, ao, so, tiles, qtile + qi,
-                           qctr + qi, sorted, st) != hipSuccess)
+                           qctr + qi * kXcds, sorted, st) != hipSuccess)
         return RRQ_ERR_DEVICE;
     }
     if (pot && launch_pot_reduce(td, kmask, ao.pairpot, pots, st) != hipSuccess)

@@ -16,15 +16,16 @@ __host__ __device__ constexpr int wave_panel_cap(int q) {
 
 // ---------------------------------------------------------------------------------------
 // binning: count pairs per patch, scan in order-grouped patch order, scatter pair indices by
-// patch, emit tiles.  Tiles of one order are contiguous, [qtile[qi], qtile[qi+1]), and each
-// order's kernel takes them from its own queue counter qctr[qi] (zeroed here).
+// patch, emit tiles.  Tiles of one order are contiguous, [qtile[qi], qtile[qi+1]); each
+// order's kernel takes them from its own kXcds queue counters qctr[qi * kXcds + c], one per
+// contiguous chunk of the range (zeroed here).
 // ---------------------------------------------------------------------------------------
 __global__ void k_bin_clear(int32_t* cnt, int32_t* fill, int P, unsigned long long* qctr) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
     cnt[i] = 0;
     fill[i] = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x < kNumOrders) qctr[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kNumOrders * kXcds) qctr[threadIdx.x] = 0;
 }
 
 __global__ void k_bin_count(TargetsDev tg, int32_t* cnt) {
@@ -473,12 +474,31 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
     cgl_w[tid] = od.gl_w[tid];
     cbary[tid] = od.bary[tid];
   }
+  // chunk c of the order's tiles is [tlo + len c / kXcds, tlo + len (c+1) / kXcds); the
+  // workgroup starts with its own die's chunk and moves on to the next one when it is empty
+  // (at most kXcds empty draws per workgroup, so every workgroup leaves the loop)
+  const int64_t len = thi - tlo;
+  const int xcd = blockIdx.x % kXcds;
+  int round = 0;
   for (;;) {
     __syncthreads();
-    if (tid == 0) s_ti = tlo + (long long)atomicAdd(qctr, 1ull);
+    if (tid == 0) {
+      long long next = -1;
+      while (round < kXcds) {
+        const int c = (xcd + round) % kXcds;
+        const int64_t chi = tlo + len * (c + 1) / kXcds;
+        const long long v = tlo + len * c / kXcds + (long long)atomicAdd(qctr + c, 1ull);
+        if (v < chi) {
+          next = v;
+          break;
+        }
+        ++round;
+      }
+      s_ti = next;
+    }
     __syncthreads();
     const int64_t ti = s_ti;
-    if (ti >= thi) break;
+    if (ti < 0) break;
     const int4 tile = tiles[ti];
     const int P = tile.x;
     if (pd.order[P] != Q) continue;

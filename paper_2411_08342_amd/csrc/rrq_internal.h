@@ -107,6 +107,13 @@ hipError_t launch_apply(const PlanDev& pd, const TargetsDev& tg, const double* c
                         const double* density, double* const* pot, hipStream_t st);
 
 // first position of each order's patches in the order-grouped patch permutation; off[n] = P
+// The accelerator has 8 compute dies (XCDs), each with its own L2.  The workgroups of a launch
+// are handed to the dies round-robin, so blockIdx.x % kXcds names a workgroup's die.  Each
+// order's tile range is cut into kXcds contiguous chunks with one queue counter each; a
+// workgroup drains its own die's chunk first, so a patch's maps and tables are fetched into
+// one L2 instead of all of them.
+constexpr int kXcds = 8;
+
 struct BinOrders {
   int32_t off[kNumOrders + 1];
 };
