@@ -271,12 +271,10 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
       const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
       double xl[3];
       frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
-      double cf[3 * 2 * kMaxQ];
-      const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
-      for (int j = 0; j < PT; ++j)
-        for (int c = 0; c < 3; ++c) cf[j * 3 + c] = pd.edge_coef[c * pd.E + e0 + j];
+      // the edge's Legendre coefficients are read in place (component-major plan arrays)
+      const double* cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * PT;
       double m[3], dv[3];
-      edge_chord(cf, PT, m, dv);
+      edge_chord(cf, PT, m, dv, 1, pd.E);
       const cplx ts = chord_root(m, dv, xl);
       if (bernstein_rho(ts) <= ro.rho_far[q]) {
         qslot[atomicAdd(&qn, 1)] = slot;
@@ -299,15 +297,12 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
       const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
       double xl[3];
       frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
-      double cf[3 * 2 * kMaxQ];
-      const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
-      for (int j = 0; j < PT; ++j)
-        for (int c = 0; c < 3; ++c) cf[j * 3 + c] = pd.edge_coef[c * pd.E + e0 + j];
+      const double* cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * PT;
       cplx ts, tl = mk(0.0, 0.0);
       bool try_learned = false;
       if (LEARNED) {
         float x[kMlpIn];
-        edge_features(cf, PT, xl, x, &ts);
+        edge_features(cf, PT, xl, x, &ts, 1, pd.E);
         float h1[kMlpH];
         for (int u = 0; u < kMlpH; ++u) {
           float a = w[kMlpB1 + u];
@@ -328,7 +323,7 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
         try_learned = isfinite(tl.re) && isfinite(tl.im);
       } else {
         double m[3], dv[3];
-        edge_chord(cf, PT, m, dv);
+        edge_chord(cf, PT, m, dv, 1, pd.E);
         ts = chord_root(m, dv, xl);
       }
       cplx t0 = ts;
@@ -337,7 +332,8 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
         cplx tp = attempt == 0 ? tl : ts;
         int its;
         const int conv = newton_solve(cf, PT, xl, &tp, ro.newton_tol,
-                                      attempt == 0 ? kLearnedMaxit : ro.newton_maxit, &its);
+                                      attempt == 0 ? kLearnedMaxit : ro.newton_maxit, &its, 1,
+                                      pd.E);
         its_all += its;
         if (tp.im < 0) tp.im = -tp.im;
         const int inside = conv && bernstein_rho(tp) <= ro.rho_far[q];

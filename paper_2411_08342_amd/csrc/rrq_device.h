@@ -176,13 +176,14 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// value and derivative of the Legendre series sum_k coef[k*stride + c] P_k(t), c = 0..2,
-// at complex t: P_{k+1} = ((2k+1) t P_k - k P_{k-1})/(k+1), P'_{k+1} = P'_{k-1} + (2k+1) P_k
+// value and derivative of the Legendre series sum_k coef[k*stride + c*cstride] P_k(t),
+// c = 0..2, at complex t: P_{k+1} = ((2k+1) t P_k - k P_{k-1})/(k+1),
+// P'_{k+1} = P'_{k-1} + (2k+1) P_k
 __device__ __forceinline__ void leg3(const double* coef, int stride, int n, cplx t, cplx* r,
-                                     cplx* dr) {
+                                     cplx* dr, int64_t cstride = 1) {
   cplx p0 = mk(0, 0), p1 = mk(1, 0), d0 = mk(0, 0), d1 = mk(0, 0);
   for (int c = 0; c < 3; ++c) {
-    r[c] = mk(coef[c], 0.0);
+    r[c] = mk(coef[c * cstride], 0.0);
     dr[c] = mk(0, 0);
   }
   for (int k = 0; k < n - 1; ++k) {
@@ -190,7 +191,7 @@ __device__ __forceinline__ void leg3(const double* coef, int stride, int n, cplx
     const cplx d2 = d0 + (2.0 * k + 1.0) * p1;
     p0 = p1; p1 = p2; d0 = d1; d1 = d2;
     for (int c = 0; c < 3; ++c) {
-      const double ck = coef[(k + 1) * stride + c];
+      const double ck = coef[(k + 1) * stride + c * cstride];
       r[c] = r[c] + ck * p1;
       dr[c] = dr[c] + ck * d1;
     }
@@ -222,16 +223,20 @@ __device__ __forceinline__ void frame_point(const double* fr, const double* x, d
 
 // ---------------------------------------------------------------------------------------
 // singularity-swap root (Sec. 3.5, Step 5): chord start and Newton on
-// f(t) = sum_c (r_c(t) - x_c)^2 for an edge given by its Legendre coefficients cf[3k + c]
+// f(t) = sum_c (r_c(t) - x_c)^2 for an edge given by its Legendre coefficients
+// cf[k ks + c cs] (ks = 3, cs = 1 for an interleaved copy; ks = 1, cs = E for the plan's
+// component-major edge arrays)
 // ---------------------------------------------------------------------------------------
 
 // r(-1) and r(1) of the edge, then the chord midpoint m and half-vector d
-__device__ __forceinline__ void edge_chord(const double* cf, int n, double* m, double* d) {
+__device__ __forceinline__ void edge_chord(const double* cf, int n, double* m, double* d,
+                                           int ks = 3, int64_t cs = 1) {
   double A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
   for (int kk = 0; kk < n; ++kk)
     for (int c = 0; c < 3; ++c) {
-      A[c] += (kk & 1) ? -cf[kk * 3 + c] : cf[kk * 3 + c];
-      B[c] += cf[kk * 3 + c];
+      const double v = cf[kk * ks + c * cs];
+      A[c] += (kk & 1) ? -v : v;
+      B[c] += v;
     }
   for (int c = 0; c < 3; ++c) {
     m[c] = 0.5 * (A[c] + B[c]);
@@ -253,12 +258,13 @@ __device__ __forceinline__ cplx chord_root(const double* m, const double* d, con
 // Newton from t: returns 1 when the step fell below tol * max(1, |t|) within maxit
 // iterations; *t is the last iterate (not canonicalised), *its the iterations taken
 __device__ __forceinline__ int newton_solve(const double* cf, int n, const double* x, cplx* t,
-                                            double tol, int maxit, int* its) {
+                                            double tol, int maxit, int* its, int ks = 3,
+                                            int64_t cs = 1) {
   cplx t0 = *t;
   int it;
   for (it = 1; it <= maxit; ++it) {
     cplx r[3], dr[3];
-    leg3(cf, 3, n, t0, r, dr);
+    leg3(cf, ks, n, t0, r, dr, cs);
     cplx f = mk(0, 0), fp = mk(0, 0);
     for (int c = 0; c < 3; ++c) {
       const cplx ec = r[c] - mk(x[c], 0.0);
@@ -283,9 +289,10 @@ __device__ __forceinline__ int newton_solve(const double* cf, int n, const doubl
 // toward the target's component perpendicular to the chord, e3 = e1 x e2).  Computed in
 // double, returned rounded to float.
 __device__ __forceinline__ void edge_features(const double* cf, int n, const double* x,
-                                              float* f, cplx* ts_out) {
+                                              float* f, cplx* ts_out, int ks = 3,
+                                              int64_t cs = 1) {
   double m[3], d[3];
-  edge_chord(cf, n, m, d);
+  edge_chord(cf, n, m, d, ks, cs);
   const cplx ts = chord_root(m, d, x);
   *ts_out = ts;
   const double ld = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -308,7 +315,7 @@ __device__ __forceinline__ void edge_features(const double* cf, int n, const dou
   for (int j = 0; j < 2; ++j) {
     double a[3] = {0, 0, 0};
     if (2 + j < n)
-      for (int c = 0; c < 3; ++c) a[c] = cf[(2 + j) * 3 + c] / ld;
+      for (int c = 0; c < 3; ++c) a[c] = cf[(2 + j) * ks + c * cs] / ld;
     f[2 + 3 * j] = (float)(a[0] * e1[0] + a[1] * e1[1] + a[2] * e1[2]);
     f[3 + 3 * j] = (float)(a[0] * e2[0] + a[1] * e2[1] + a[2] * e2[2]);
     f[4 + 3 * j] = (float)(a[0] * e3[0] + a[1] * e3[1] + a[2] * e3[2]);

@@ -35,19 +35,17 @@ __global__ void k_collect(PlanDev pd, TargetsDev tg, const int64_t* owner, Colle
     const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
     double xl[3];
     frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
-    double cf[3 * 2 * kMaxQ];
-    const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
-    for (int i = 0; i < PT; ++i)
-      for (int c = 0; c < 3; ++c) cf[i * 3 + c] = pd.edge_coef[c * pd.E + e0 + i];
+    const double* cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * PT;   // read in place
     float f[8];
     cplx ts;
-    edge_features(cf, PT, xl, f, &ts);
+    edge_features(cf, PT, xl, f, &ts, 1, pd.E);
     const double rf = co.rho_far[q];
     int keep = 0;
     cplx t = ts;
     if (bernstein_rho(ts) <= rf) {
       int its;
-      const int conv = newton_solve(cf, PT, xl, &t, co.newton_tol, co.newton_maxit, &its);
+      const int conv = newton_solve(cf, PT, xl, &t, co.newton_tol, co.newton_maxit, &its, 1,
+                                    pd.E);
       if (t.im < 0) t.im = -t.im;
       keep = conv && bernstein_rho(t) <= rf;
     }
