@@ -8,7 +8,6 @@
 namespace rrq {
 
 constexpr int BNT = 256;
-typedef double v4d __attribute__((ext_vector_type(4)));
 // panel capacity per wave: enough for every level down to kMaxLevel at the order's rho_far
 __host__ __device__ constexpr int wave_panel_cap(int q) {
   return q <= 4 ? 320 : (q <= 5 ? 224 : (q <= 6 ? 144 : 112));
@@ -952,42 +951,58 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             out.pairpot[k * 4 + lane] = lane == 0 ? a0 : (lane == 1 ? a1 : (lane == 2 ? a2 : a3));
         }
       } else {
-        // ---- Step 8 (matrix rows): weights = rows x maps on FP64 MFMA 16x16x4.
-        // Jobs (group, 16-column tile): group 0 = [rD; rDp] x M_D, 1 = rSp x M_Sp, 2 = rS x M_S.
-        // MFMA operand layout: lane l holds A[l%16][l/16], B[l/16][l%16]; result element v of
-        // lane l is D[l/16 + 4v][l%16].
+        // ---- Step 8 (matrix rows): weights = rows x maps on the four-block 4x4x4 FP64 MFMA.
+        // Jobs (group, 16-column tile): group 0 = rD and rDp x M_D (two accumulators sharing
+        // the map operand), 1 = rSp x M_Sp, 2 = rS x M_S.  Operand layout: block b = (l % 16)
+        // / 4 of lane l takes columns 4b..4b+3 of the tile; lane l supplies A[m = l % 4][k =
+        // l / 16] (a target row) and B[k = l / 16][n = l % 4] (a map entry) and receives
+        // D[m = l / 16][n = l % 4]: the weight of target l / 16 (of a quad of targets) at
+        // column l % 16 of the tile.
         {
           constexpr int NCT = (Q2 + 15) / 16;
+          constexpr int TQ = T / 4;
           const double* maps = pd.maps + pd.map_off[P];
           const double sc = fr[12];
-          const int arow = lane & 15, akk = lane >> 4;
+          const int am = lane & 3, kr = lane >> 4;
           for (int job = wv; job < 3 * NCT; job += BNT / 64) {
             const int grp = job / NCT, ct = job % NCT;
             const double* M = grp == 0 ? maps : (grp == 1 ? maps + 4 * NP * Q2 : maps + 8 * NP * Q2);
             const int KR = grp == 2 ? 5 * NP : 4 * NP;
-            const double* rowp = nullptr;
-            if (grp == 0) {
-              if (arow < T) rowp = rows + arow * 4 * NP;
-              else if (arow < 2 * T) rowp = rows + T * 13 * NP + (arow - T) * 4 * NP;
-            } else if (arow < T) {
-              rowp = grp == 1 ? rows + T * 4 * NP + arow * 4 * NP : rows + T * 8 * NP + arow * 5 * NP;
-            }
+            const int NA = grp == 0 ? 2 * TQ : TQ;          // accumulators: (kind, target quad)
             const int bcol = ct * 16 + (lane & 15);
             const bool bval = bcol < Q2;
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
-            // 8 k-steps per batch: operands loaded first (8 map loads in flight), then 8 MFMAs
+            double acc[2 * TQ];
+#pragma unroll
+            for (int a = 0; a < 2 * TQ; ++a) acc[a] = 0.0;
+            // 8 k-steps per batch: map operands loaded first (8 loads in flight), then the
+            // row operands and MFMAs of every accumulator
             for (int kb = 0; kb < KR; kb += 32) {
-              double av[8], bv[8];
-  #pragma unroll
+              double bv[8];
+#pragma unroll
               for (int u = 0; u < 8; ++u) {
-                const int k = kb + 4 * u + akk;
-                const bool ok = k < KR;
-                av[u] = (rowp != nullptr && ok) ? rowp[k] : 0.0;
-                bv[u] = (bval && ok) ? M[k * Q2 + bcol] : 0.0;
+                const int k = kb + 4 * u + kr;
+                bv[u] = (bval && k < KR) ? M[k * Q2 + bcol] : 0.0;
               }
-  #pragma unroll
-              for (int u = 0; u < 8; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+#pragma unroll
+              for (int a = 0; a < 2 * TQ; ++a) {
+                if (a >= NA) break;
+                const int t = (a % TQ) * 4 + am;
+                const double* rowp = nullptr;
+                if (t < nt) {
+                  if (grp == 0) rowp = a < TQ ? rows + t * 4 * NP : rows + T * 13 * NP + t * 4 * NP;
+                  else if (grp == 1) rowp = rows + T * 4 * NP + t * 4 * NP;
+                  else rowp = rows + T * 8 * NP + t * 5 * NP;
+                }
+                double av[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                  const int k = kb + 4 * u + kr;
+                  av[u] = (rowp != nullptr && k < KR) ? rowp[k] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                  acc[a] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[u], bv[u], acc[a], 0, 0, 0);
+              }
             }
             if (!bval) continue;
             const int j = bcol;
@@ -995,16 +1010,15 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             const double rx = pd.node_xyz[nj], ry = pd.node_xyz[pd.N + nj], rz = pd.node_xyz[2 * pd.N + nj];
             const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
             const double wj = pd.node_wt[nj] * kInv4Pi;
-  #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int i = (lane >> 4) + 4 * v;
-              int K, t;
-              if (grp == 0) { K = i < T ? 1 : 3; t = i < T ? i : i - T; if (i >= 2 * T) t = T; }
-              else { K = grp == 1 ? 2 : 0; t = i < T ? i : T; }
+#pragma unroll
+            for (int a = 0; a < 2 * TQ; ++a) {
+              if (a >= NA) break;
+              const int t = (a % TQ) * 4 + kr;
+              const int K = grp == 0 ? (a < TQ ? 1 : 3) : (grp == 1 ? 2 : 0);
               if (t >= nt || !(out.kmask & (1u << K)) || out.w[K] == nullptr) continue;
               const int64_t k = sorted[tile.y + sub + t];
               const int64_t g = out.owner[k];
-              double val = acc[v];
+              double val = acc[a];
               if (K == 0) val *= sc;
               else if (K == 3) val /= sc;
               if ((out.flags & RRQ_F_CORRECTION) && j != sself[t]) {
