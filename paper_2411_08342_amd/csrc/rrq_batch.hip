@@ -618,14 +618,15 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             leg3r(ecoef + e * PT * 3, PT, tau, r, dr);
             om += hw * omega0_at(sx + t * 3, su + t * 3, r, dr);
           }
-          // Lagrange basis at tau, barycentric form
+          // Lagrange basis at tau, barycentric form; 1/(tau - t_j) by the hardware reciprocal
+          // and one Newton step (relative error a few ulp, against a correctly rounded divide)
           double den = 0.0;
           int hit = -1;
 #pragma unroll
           for (int j = 0; j < PT; ++j) {
             const double dtj = tau - cgl_t[j];
             if (dtj == 0.0) hit = j;
-            else den += cbary[j] / dtj;
+            else den += cbary[j] * rcp_nr(dtj);
           }
           const double rden = 1.0 / den;
 #pragma unroll
@@ -637,7 +638,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
               double l = 0.0;
               if (i < PT) {
                 if (hit >= 0) l = hit == i ? 1.0 : 0.0;
-                else l = cbary[i] / (tau - cgl_t[i]) * rden;
+                else l = cbary[i] * rcp_nr(tau - cgl_t[i]) * rden;
               }
               x[v] = w1p * l;
               x[8 + v] = w3p * l;
@@ -762,25 +763,26 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             const double a0 = tdp[4], a1 = tdp[5], a2 = tdp[6];
             const double c0r = o[0], c0i = o[1], c1r = o[2], c1i = o[3], c2r = o[4], c2i = o[5];
             const double h0r = o[6], h0i = o[7], h1r = o[8], h1i = o[9], h2r = o[10], h2i = o[11];
-            V0 += w1 * (d0 * c0r + d1 * c1r + d2 * c2r);
-            V1 += w1 * (d0 * c0i + d1 * c1i + d2 * c2i);
+            // every product is accumulated with its own FMA (no temporary sums)
             const double v0 = w1 * d0, v1 = w1 * d1, v2 = w1 * d2;
-            Qr[0] -= v0 * h0r + v1 * h1r + v2 * h2r;
-            Qi[0] -= v0 * h0i + v1 * h1i + v2 * h2i;
-            Qr[1] += v1 * h2r - v2 * h1r;
-            Qi[1] += v1 * h2i - v2 * h1i;
-            Qr[2] += v2 * h0r - v0 * h2r;
-            Qi[2] += v2 * h0i - v0 * h2i;
-            Qr[3] += v0 * h1r - v1 * h0r;
-            Qi[3] += v0 * h1i - v1 * h0i;
-            Dr[0] -= a0 * h0r + a1 * h1r + a2 * h2r;
-            Di[0] -= a0 * h0i + a1 * h1i + a2 * h2i;
-            Dr[1] += a1 * h2r - a2 * h1r;
-            Di[1] += a1 * h2i - a2 * h1i;
-            Dr[2] += a2 * h0r - a0 * h2r;
-            Di[2] += a2 * h0i - a0 * h2i;
-            Dr[3] += a0 * h1r - a1 * h0r;
-            Di[3] += a0 * h1i - a1 * h0i;
+            V0 = fma(v0, c0r, fma(v1, c1r, fma(v2, c2r, V0)));
+            V1 = fma(v0, c0i, fma(v1, c1i, fma(v2, c2i, V1)));
+            Qr[0] = fma(-v0, h0r, fma(-v1, h1r, fma(-v2, h2r, Qr[0])));
+            Qi[0] = fma(-v0, h0i, fma(-v1, h1i, fma(-v2, h2i, Qi[0])));
+            Qr[1] = fma(v1, h2r, fma(-v2, h1r, Qr[1]));
+            Qi[1] = fma(v1, h2i, fma(-v2, h1i, Qi[1]));
+            Qr[2] = fma(v2, h0r, fma(-v0, h2r, Qr[2]));
+            Qi[2] = fma(v2, h0i, fma(-v0, h2i, Qi[2]));
+            Qr[3] = fma(v0, h1r, fma(-v1, h0r, Qr[3]));
+            Qi[3] = fma(v0, h1i, fma(-v1, h0i, Qi[3]));
+            Dr[0] = fma(-a0, h0r, fma(-a1, h1r, fma(-a2, h2r, Dr[0])));
+            Di[0] = fma(-a0, h0i, fma(-a1, h1i, fma(-a2, h2i, Di[0])));
+            Dr[1] = fma(a1, h2r, fma(-a2, h1r, Dr[1]));
+            Di[1] = fma(a1, h2i, fma(-a2, h1i, Di[1]));
+            Dr[2] = fma(a2, h0r, fma(-a0, h2r, Dr[2]));
+            Di[2] = fma(a2, h0i, fma(-a0, h2i, Di[2]));
+            Dr[3] = fma(a0, h1r, fma(-a1, h0r, Dr[3]));
+            Di[3] = fma(a0, h1i, fma(-a1, h0i, Di[3]));
           }
         double* o = vq + (t * NJK + n) * 18;
         o[0] = V0; o[1] = V1;
@@ -823,12 +825,13 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
           const double* q = VQ + tm.n * 18;
           cplx V = mk(q[0], q[1]);
           if (tm.neg) V = conjg(V);
-          sl = sl + tm.cS * (V * s_);
+          cfma(sl, tm.cS * V, s_);
           for (int c = 0; c < 4; ++c) {
             cplx X = mk(q[2 + 2 * c], q[3 + 2 * c]), dX = mk(q[10 + 2 * c], q[11 + 2 * c]);
             if (tm.neg) { X = conjg(X); dX = conjg(dX); }
-            Ia[c] = Ia[c] + X * cs;
-            dIa[c] = dIa[c] + (dX * cs + X * cg);
+            cfma(Ia[c], X, cs);
+            cfma(dIa[c], dX, cs);
+            cfma(dIa[c], X, cg);
           }
         }
         // first half += second half (the partner lane is idx ^ 1)
