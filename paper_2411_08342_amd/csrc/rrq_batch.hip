@@ -936,14 +936,15 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
               const double d1 = x1 - pd.node_xyz[pd.N + nj];
               const double d2 = x2 - pd.node_xyz[2 * pd.N + nj];
               const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
-              const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
+              const double R2 = d0 * d0 + d1 * d1 + d2 * d2;
+              const double ri = 1.0 / sqrt(R2), ri2 = ri * ri, ri3 = ri2 * ri;
               const double dn = d0 * v0 + d1 * v1 + d2 * v2;
               const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
               const double f = pd.node_wt[nj] * kInv4Pi * out.dens[nj];
-              a0 -= f / R;
-              a1 -= f * (dn / R3);
-              a2 -= f * (-dnt / R3);
-              a3 -= f * ((v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2));
+              a0 -= f * ri;
+              a1 -= f * (dn * ri3);
+              a2 -= f * (-dnt * ri3);
+              a3 -= f * (((v0 * nt0 + v1 * nt1 + v2 * nt2) - 3.0 * dn * dnt * ri2) * ri3);
             }
           }
           a0 = wave_sum(a0);
@@ -1025,16 +1026,25 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
               if (K == 0) val *= sc;
               else if (K == 3) val /= sc;
               if ((out.flags & RRQ_F_CORRECTION) && j != sself[t]) {
+                // smooth-rule kernels from one reciprocal square root: 1/R, then powers
                 const double d0 = tg.xyz[g] - rx, d1 = tg.xyz[tg.T + g] - ry, d2 = tg.xyz[2 * tg.T + g] - rz;
-                const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
-                const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
-                const double dn = d0 * v0 + d1 * v1 + d2 * v2;
-                const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
+                const double R2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double ri = 1.0 / sqrt(R2), ri2 = ri * ri, ri3 = ri2 * ri;
                 double kv;
-                if (K == 0) kv = 1.0 / R;
-                else if (K == 1) kv = dn / R3;
-                else if (K == 2) kv = -dnt / R3;
-                else kv = (v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2);
+                if (K == 0) {
+                  kv = ri;
+                } else if (K == 1) {
+                  kv = (d0 * v0 + d1 * v1 + d2 * v2) * ri3;
+                } else {
+                  const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
+                  const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
+                  if (K == 2) {
+                    kv = -dnt * ri3;
+                  } else {
+                    const double dn = d0 * v0 + d1 * v1 + d2 * v2;
+                    kv = ((v0 * nt0 + v1 * nt1 + v2 * nt2) - 3.0 * dn * dnt * ri2) * ri3;
+                  }
+                }
                 val -= kv * wj;
               }
               out.w[K][out.pair_off[k] + j] = val;
@@ -1142,14 +1152,15 @@ __global__ void k_smooth_direct(PlanDev pd, TargetsDev tg, uint32_t kmask, const
       const double d0 = x0 - pd.node_xyz[j], d1 = x1 - pd.node_xyz[pd.N + j],
                    d2 = x2 - pd.node_xyz[2 * pd.N + j];
       const double v0 = pd.node_nrm[j], v1 = pd.node_nrm[pd.N + j], v2 = pd.node_nrm[2 * pd.N + j];
-      const double R2 = d0 * d0 + d1 * d1 + d2 * d2, R = sqrt(R2), R3 = R2 * R;
+      const double R2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double ri = 1.0 / sqrt(R2), ri2 = ri * ri, ri3 = ri2 * ri;
       const double dn = d0 * v0 + d1 * v1 + d2 * v2;
       const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
       const double f = pd.node_wt[j] * kInv4Pi * dens[j];
-      acc[0] += f / R;
-      acc[1] += f * (dn / R3);
-      acc[2] += f * (-dnt / R3);
-      acc[3] += f * ((v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2));
+      acc[0] += f * ri;
+      acc[1] += f * (dn * ri3);
+      acc[2] += f * (-dnt * ri3);
+      acc[3] += f * (((v0 * nt0 + v1 * nt1 + v2 * nt2) - 3.0 * dn * dnt * ri2) * ri3);
     }
     for (int K = 0; K < 4; ++K) {
       const double v = wave_sum(acc[K]);
