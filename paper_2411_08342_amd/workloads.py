@@ -455,6 +455,31 @@ def quadratic_patch(k=(0.35, -0.2, 0.25), scale=0.6, shift=(0.0, 0.0, 0.0)):
     return PatchMap(fn)
 
 
+def paraboloid_patches(cases, q, spacing=10.0):
+    """Quadrilateral pieces of the paraboloid z = H/2 (x^2 + y^2) over [-h/2, h/2]^2 (maximum
+    mean curvature H, at the origin), one patch per (H, h) in `cases`, moved apart along x
+    so that no target is near two of them."""
+    maps = [quadratic_patch(k=(H * h / 4.0, 0.0, H * h / 4.0), scale=h / 2.0,
+                            shift=(spacing * i, 0.0, 0.0)) for i, (H, h) in enumerate(cases)]
+    return discretize(maps, np.full(len(cases), q))
+
+
+def paraboloid_workload(cases, q=8, seed=SEED_BASE + 50):
+    """Paraboloid patches with their node targets and 8 off-surface targets per patch at
+    1e-3 .. 0.3 patch diameters.  Near radius 2.5 corner diameters: the corners of the most
+    curved piece sit high above its bottom, so one diameter from their mean would miss the
+    patch's own nodes."""
+    rng = np.random.default_rng(seed)
+    surf = paraboloid_patches(cases, q)
+    x, nn, sp, sn = node_targets(surf)
+    xo, no = offsurface_targets(surf, rng, count_per_patch=8, rel_dist=(1e-3, 0.3))
+    m = xo.shape[1]
+    tg = make_targets(surf, np.concatenate([x, xo], axis=1), np.concatenate([nn, no], axis=1),
+                      np.concatenate([sp, np.full(m, -1, np.int32)]),
+                      np.concatenate([sn, np.full(m, -1, np.int32)]), eta=2.5)
+    return surf, tg
+
+
 def patch_point(surface, P, u, v):
     """Point, unit normal of patch P at parameters (u, v)."""
     r, ru, rv = surface["maps"][P].derivs(np.atleast_1d(u), np.atleast_1d(v))

@@ -189,6 +189,30 @@ def test_mixed_orders_parity():
     _compare(surf, tg, gpu, off, pairs)
 
 
+@pytest.mark.parametrize("q", [8, 10])
+def test_paraboloid_curvature_and_size_parity(q):
+    """Fit under stress, after the conditioning study of Sec. 5: pieces of the paraboloid
+    z = H/2 (x^2 + y^2) over [-h/2, h/2]^2 with growing curvature (h = 1, H up to 10; the
+    weighted DLP system's condition number reaches 2.7e6 at q = 8 and 9.5e7 at q = 10) and
+    shrinking size (H = 10, h down to 1/1024, where the frame scaling brings it back to the
+    flat value).  Node targets and close off-surface targets, same gate as every parity test
+    (its SVD-versus-QR term absorbs the conditioning)."""
+    from oracle.assemble import fit_patch
+    cases = [(0.0, 1.0), (2.0, 1.0), (10.0, 1.0), (10.0, 1.0 / 16), (10.0, 1.0 / 1024)]
+    surf, tg = wl.paraboloid_workload(cases, q)
+    for P, (H, h) in enumerate(cases):
+        f = fit_patch(surf, P)
+        sw = np.sqrt(np.tile(f.lsw, 4))
+        print(f"q={q} H={H:g} h={h:g}: cond(A) {np.linalg.cond(sw[:, None] * f.A):.2e}")
+    gpu, off, stats, _ = _run_gpu(surf, tg)
+    assert stats["newton_fail"] == 0
+    rng = np.random.default_rng(20 + q)
+    owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
+    off_surface = np.nonzero(tg["self_patch"][owner] < 0)[0]
+    pairs = _sample(tg, 120, rng, must=off_surface)
+    _compare(surf, tg, gpu, off, pairs)
+
+
 def test_empty_rows_and_kernel_mask():
     """Targets with no near patch, and a kernel mask that skips S and D'."""
     from paper_2411_08342_amd import rrq
