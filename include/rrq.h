@@ -110,8 +110,8 @@ typedef struct {
   int64_t newton_max;     /* largest iteration count of one edge                           */
   double kernel_ms;       /* device time of the pair kernels of this call (the per-pair
                              kernel of the plain form or the tile kernels of the batched form;
-                             binning and the root pre-pass excluded), from HIP events on the
-                             call's stream                                                  */
+                             binning, the root pre-pass and the near-edge moment pre-pass
+                             excluded), from HIP events on the call's stream                */
 } rrq_stats;
 
 /* Create a plan for a surface: allocates the per-patch frames, coefficient maps and edge
@@ -124,6 +124,16 @@ rrq_status rrq_plan_create(const rrq_surface* surf, const rrq_options* opts, voi
 rrq_status rrq_plan_refit(rrq_plan* plan, const rrq_surface* surf, void* stream);
 
 rrq_status rrq_plan_destroy(rrq_plan* plan);
+
+/* Conditioning of each patch's weighted least-squares fits (Steps 1-2; the study of the
+ * system matrix in Sec. 5): cond[2P'] = max|R_ii| / min|R_ii| of the Householder QR of the
+ * DLP system (4q^2 x 4n_p, eq. dlpdensitylinearsystem2) of patch P', cond[2P'+1] the same for
+ * the SLP system (q^2 x n_p, eq. slpdensitylinearsystem).  Each is a lower bound of the
+ * 2-norm condition number of its weighted system.  The fits still produce maps whatever the
+ * value; a caller flags patches against its own threshold (near 1/eps the fitted density
+ * loses accuracy).  cond is a HOST array of 2P doubles, filled from the last plan_create or
+ * plan_refit; the call synchronises `stream`. */
+rrq_status rrq_plan_fit_condition(const rrq_plan* plan, double* cond, void* stream);
 
 /* Bytes of caller-provided device workspace that rrq_assemble needs for this near list. */
 rrq_status rrq_workspace_size(const rrq_plan* plan, const rrq_targets* tg, size_t* bytes);

@@ -50,6 +50,7 @@ struct rrq_plan {
   double* tabs_d = nullptr;
   int64_t* tab_off_d = nullptr;
   double* fit_ws_d = nullptr;
+  double* fitcond_d = nullptr;    // [P][2]
   int64_t fit_ws_per_block = 0;
   int fit_blocks = 0;
   // per order
@@ -86,6 +87,7 @@ struct rrq_plan {
     d.tabs = tabs_d;
     d.tab_off = tab_off_d;
     d.mlp = has_mlp ? mlp_d : nullptr;
+    d.fitcond = fitcond_d;
     return d;
   }
 };
@@ -95,7 +97,7 @@ static void plan_free(rrq_plan* p) {
   void* ptrs[] = {p->order_d, p->node_off_d, p->edge_off_d, p->node_xyz_d, p->node_nrm_d,
                   p->node_wt_d, p->frame_d, p->node_loc_d, p->edge_loc_d, p->edge_tan_d,
                   p->edge_coef_d, p->maps_d, p->map_off_d, p->tabs_d, p->tab_off_d,
-                  p->fit_ws_d, p->perm_d, p->mlp_d};
+                  p->fit_ws_d, p->perm_d, p->mlp_d, p->fitcond_d};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int q = 0; q <= kMaxQ; ++q)
@@ -290,6 +292,7 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
   p->fit_blocks = std::min(p->P, 512);
   p->fit_ws_per_block = maxws;
   ok &= dalloc(&p->fit_ws_d, (size_t)maxws * p->fit_blocks) == hipSuccess;
+  ok &= dalloc(&p->fitcond_d, 2 * (size_t)p->P) == hipSuccess;
   for (int q = 0; q <= kMaxQ && ok; ++q)
     if (!p->patches_h[q].empty()) {
       ok &= dalloc(&p->patches_d[q], p->patches_h[q].size()) == hipSuccess;
@@ -366,13 +369,14 @@ static TargetsDev tdev(const rrq_targets* tg) {
 // workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders][xcds] u64 |
 // sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
-// nearf[4 nnz] u8 | pairpot[nnz][4] f64 | pcoef[P][kCoefStride] f64
+// nearf[4 nnz] u8 | pairpot[nnz][4] f64 | pcoef[P][kCoefStride] f64 | nlist[4 nnz] i64 |
+// lamg[4 nnz][lam_stride] f64 (near-edge moments; lam_stride = 2 ptilde_max + 1)
 struct WsLayout {
   size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, root,
-      nearf, pairpot, pcoef, total;
+      nearf, pairpot, pcoef, nlist, lamg, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
-static WsLayout ws_layout(int64_t nnz, int P) {
+static WsLayout ws_layout(int64_t nnz, int P, int lam_stride) {
   const size_t n = (size_t)(nnz > 0 ? nnz : 1);
   WsLayout w;
   size_t o = 0;
@@ -391,16 +395,39 @@ static WsLayout ws_layout(int64_t nnz, int P) {
   w.nearf = o; o = al(o + 4 * n);
   w.pairpot = o; o = al(o + 4 * n * 8);
   w.pcoef = o; o = al(o + (size_t)P * kCoefStride * 8);
+  w.nlist = o; o = al(o + 4 * n * 8);
+  w.lamg = o; o = al(o + 4 * n * (size_t)lam_stride * 8);
   w.total = o;
   return w;
 }
-static size_t ws_bytes(int64_t nnz, int P) { return ws_layout(nnz, P).total; }
+// doubles per slot of the near-edge moments: lambda^(1), lambda^(3) at the largest order's
+// ptilde edge nodes, and the Omega_0 part
+static int lam_stride_of(const rrq_plan* p) {
+  int qmax = 1;
+  for (int q = 0; q <= kMaxQ; ++q)
+    if (!p->patches_h[q].empty()) qmax = q;
+  return 2 * (2 * qmax) + 1;
+}
+static WsLayout ws_layout(const rrq_plan* p, int64_t nnz) {
+  return ws_layout(nnz, p->P, lam_stride_of(p));
+}
+static size_t ws_bytes(const rrq_plan* p, int64_t nnz) { return ws_layout(p, nnz).total; }
+
+rrq_status rrq_plan_fit_condition(const rrq_plan* p, double* cond, void* stream) {
+  if (!p || !cond) return RRQ_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(cond, p->fitcond_d, 2 * (size_t)p->P * sizeof(double), hipMemcpyDeviceToHost,
+                     st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return RRQ_ERR_DEVICE;
+  return RRQ_OK;
+}
 
 rrq_status rrq_workspace_size(const rrq_plan* p, const rrq_targets* tg, size_t* bytes) {
   if (!bytes) return RRQ_ERR_ARG;
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
-  *bytes = ws_bytes(tg->nnz, p->P);
+  *bytes = ws_bytes(p, tg->nnz);
   return RRQ_OK;
 }
 
@@ -410,9 +437,9 @@ rrq_status rrq_pair_offsets(const rrq_plan* p, const rrq_targets* tg, int64_t* p
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
   if (!pair_off || !workspace) return RRQ_ERR_ARG;
-  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
+  if (workspace_bytes < ws_bytes(p, tg->nnz)) return RRQ_ERR_BUFFER;
   hipStream_t st = (hipStream_t)stream;
-  int64_t* part = (int64_t*)((char*)workspace + ws_layout(tg->nnz, p->P).part);
+  int64_t* part = (int64_t*)((char*)workspace + ws_layout(p, tg->nnz).part);
   if (launch_pair_offsets(p->dev(), tdev(tg), pair_off, part, st) != hipSuccess)
     return RRQ_ERR_DEVICE;
   if (nweights) {
@@ -429,7 +456,7 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
                             const double* density, double* const* pots, void* workspace,
                             hipStream_t st, rrq_stats* stats) {
   const bool pot = pots != nullptr;
-  const WsLayout wl = ws_layout(tg->nnz, p->P);
+  const WsLayout wl = ws_layout(p, tg->nnz);
   char* wb = (char*)workspace;
   int64_t* owner = (int64_t*)(wb + wl.owner);
   unsigned long long* counters = (unsigned long long*)(wb + wl.counters);
@@ -444,6 +471,8 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
   ao.counters = counters;
   ao.root = nullptr;
   ao.nearf = nullptr;
+  ao.lamg = nullptr;
+  ao.lam_stride = 0;
   ao.dens = density;
   ao.pcoef = pot ? (const double*)(wb + wl.pcoef) : nullptr;
   ao.pairpot = pot ? (double*)(wb + wl.pairpot) : nullptr;
@@ -489,11 +518,23 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       ro.newton_maxit = p->opt.newton_maxit;
       double2* root = (double2*)(wb + wl.root);
       uint8_t* nearf = (uint8_t*)(wb + wl.nearf);
-      if (launch_root(pd, td, owner, ro, (flags & RRQ_F_LEARNED) != 0, root, nearf, counters,
-                      st) != hipSuccess)
+      int64_t* nlist = (int64_t*)(wb + wl.nlist);
+      double* lamg = (double*)(wb + wl.lamg);
+      const int lam_stride = lam_stride_of(p);
+      if (launch_root(pd, td, owner, ro, (flags & RRQ_F_LEARNED) != 0, root, nearf, nlist,
+                      counters, st) != hipSuccess)
         return RRQ_ERR_DEVICE;
+      for (int qi = 0; qi < kNumOrders; ++qi) {
+        const int q = kOrders[qi];
+        if (p->patches_h[q].empty()) continue;
+        if (launch_lambda(q, pd, p->od[q], td, owner, root, nlist, counters, lamg, lam_stride,
+                          p->rho_far[q], st) != hipSuccess)
+          return RRQ_ERR_DEVICE;
+      }
       ao.root = root;
       ao.nearf = nearf;
+      ao.lamg = lamg;
+      ao.lam_stride = lam_stride;
     }
     if (pot && launch_patch_coef(pd, density, (double*)(wb + wl.pcoef), st) != hipSuccess)
       return RRQ_ERR_DEVICE;
@@ -537,7 +578,7 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
   if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
-  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
+  if (workspace_bytes < ws_bytes(p, tg->nnz)) return RRQ_ERR_BUFFER;
   double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
   for (int K = 0; K < 4; ++K)
     if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
@@ -556,7 +597,7 @@ rrq_status rrq_potentials(const rrq_plan* p, const rrq_targets* tg, uint32_t kma
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
   if (!density || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
-  if (workspace_bytes < ws_bytes(tg->nnz, p->P)) return RRQ_ERR_BUFFER;
+  if (workspace_bytes < ws_bytes(p, tg->nnz)) return RRQ_ERR_BUFFER;
   double* pots[4] = {pot_S, pot_D, pot_Sp, pot_Dp};
   for (int K = 0; K < 4; ++K)
     if ((kmask & (1u << K)) && !pots[K]) return RRQ_ERR_ARG;

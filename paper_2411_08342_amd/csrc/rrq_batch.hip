@@ -241,11 +241,13 @@ constexpr int kLearnedMaxit = 8;
 template <bool LEARNED>
 __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const int64_t* owner,
                                               RootOpts ro, double2* root, uint8_t* nearf,
-                                              unsigned long long* counters) {
+                                              int64_t* nlist, unsigned long long* counters) {
   constexpr int kQ = 1024;               // slots per chunk of a workgroup
   __shared__ float w[LEARNED ? kMlpParams : 1];
   __shared__ int64_t qslot[kQ];          // chunk slots whose chord root needs Newton
-  __shared__ int qn;
+  __shared__ int64_t nslot_l[kQ];        // chunk slots of the singularity-swap class
+  __shared__ int qn, nn;
+  __shared__ long long nbase;
   __shared__ unsigned long long cs[5];
   const int tid = threadIdx.x;
   if (tid < 5) cs[tid] = 0;
@@ -255,7 +257,10 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
   const int64_t nslot = 4 * tg.nnz;
   for (int64_t base = (int64_t)blockIdx.x * kQ; base < nslot; base += (int64_t)gridDim.x * kQ) {
     __syncthreads();
-    if (tid == 0) qn = 0;
+    if (tid == 0) {
+      qn = 0;
+      nn = 0;
+    }
     __syncthreads();
     // classify the chunk; slots with the chord root outside the ellipse are done here
     for (int i = tid; i < kQ; i += blockDim.x) {
@@ -351,7 +356,13 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
       c_near += near;
       root[slot] = make_double2(t0.re, t0.im);
       nearf[slot] = (uint8_t)near;
+      if (near) nslot_l[atomicAdd(&nn, 1)] = slot;
     }
+    // the chunk's near slots go to the global list with one reservation per chunk
+    __syncthreads();
+    if (tid == 0) nbase = nn > 0 ? (long long)atomicAdd(&counters[5], (unsigned long long)nn) : 0;
+    __syncthreads();
+    for (int i = tid; i < nn; i += blockDim.x) nlist[nbase + i] = nslot_l[i];
   }
   if (c_near) atomicAdd(&cs[0], c_near);
   if (c_iters) atomicAdd(&cs[1], c_iters);
@@ -367,20 +378,213 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
 
 hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
                        const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
-                       unsigned long long* counters, hipStream_t st) {
+                       int64_t* nlist, unsigned long long* counters, hipStream_t st) {
   int64_t g = (4 * tg.nnz + 1023) / 1024;
   if (g < 1) g = 1;
   const dim3 grid((unsigned)(g < 4096 ? g : 4096));
   if (learned)
-    hipLaunchKernelGGL(k_root<true>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, counters);
+    hipLaunchKernelGGL(k_root<true>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
+                       counters);
   else
-    hipLaunchKernelGGL(k_root<false>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, counters);
+    hipLaunchKernelGGL(k_root<false>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
+                       counters);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
 // LDS layout of one tile (doubles, then ints)
 // ---------------------------------------------------------------------------------------
+// One wave: local coordinates xl and normal nl of a target in the frame fr of a patch whose
+// nodes start at n0, and the vector u of the solid-angle integrand: the target normal for a
+// self target, else the normal of the nearest node (lowest index on ties, wave argmin)
+// oriented toward the target.  Every lane returns the same values.
+template <int Q>
+__device__ __forceinline__ void wave_target_local(const PlanDev& pd, const double* fr, int64_t n0,
+                                                  int self, const double* xg, const double* nv,
+                                                  double* xl, double* nl, double* u) {
+  constexpr int Q2 = Q * Q;
+  const int lane = threadIdx.x & 63;
+  frame_point(fr, xg, xl);
+  for (int a = 0; a < 3; ++a) {
+    const double* ax = fr + 3 + 3 * a;
+    nl[a] = nv[0] * ax[0] + nv[1] * ax[1] + nv[2] * ax[2];
+  }
+  if (self >= 0) {
+    for (int c = 0; c < 3; ++c) u[c] = nl[c];
+    return;
+  }
+  double bd = 1e300;
+  int bi = 0x7fffffff;
+  for (int i = lane; i < Q2; i += 64) {
+    double d2 = 0;
+    for (int c = 0; c < 3; ++c) {
+      const double dd = xl[c] - pd.node_loc[c * pd.N + n0 + i];
+      d2 += dd * dd;
+    }
+    if (d2 < bd) { bd = d2; bi = i; }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(bd, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ob < bd || (ob == bd && oi < bi)) { bd = ob; bi = oi; }
+  }
+  double dd = 0, nn[3];
+  for (int c = 0; c < 3; ++c) {
+    nn[c] = pd.node_loc[(3 + c) * pd.N + n0 + bi];
+    dd += (xl[c] - pd.node_loc[c * pd.N + n0 + bi]) * nn[c];
+  }
+  const double sg = dd >= 0.0 ? 1.0 : -1.0;
+  for (int c = 0; c < 3; ++c) u[c] = sg * nn[c];
+}
+
+// Step 5 on a near edge (the singularity-swap class): the Lagrange-basis moments of the two
+// kernels |tau - t0|^m / |r(tau) - x|^m, m = 1, 3, on panels graded toward t0, and the edge's
+// part of the solid angle Omega_0.  One wave per near (pair, edge), lanes over the panel
+// points; a workgroup of kLamWaves waves takes items i = w, w + stride, ... from the list of
+// near slots the root pre-pass wrote, skipping items of other orders.  Output per slot:
+// lamg[slot * stride] = lambda^(1)[PT], lambda^(3)[PT], Omega_0 part.
+constexpr int kLamWaves = 4;
+
+template <int Q>
+__global__ __launch_bounds__(64 * kLamWaves) __attribute__((amdgpu_waves_per_eu(3)))
+void k_lambda(PlanDev pd, OrderDev od,
+                                                           TargetsDev tg, const int64_t* owner,
+                                                           const double2* root,
+                                                           const int64_t* nlist,
+                                                           unsigned long long* counters,
+                                                           double* lamg, int lam_stride,
+                                                           double rho_far) {
+  constexpr int PT = 2 * Q;
+  constexpr int NB8 = (PT + 7) / 8;
+  constexpr int NPAN = wave_panel_cap(Q);
+  __shared__ double cgl_t[PT], cgl_w[PT], cbary[PT];
+  __shared__ double sfr[kLamWaves][kFrame];
+  __shared__ double scoef[kLamWaves][PT * 3];
+  __shared__ double span[kLamWaves][NPAN * 2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid < PT) {
+    cgl_t[tid] = od.gl_t[tid];
+    cgl_w[tid] = od.gl_w[tid];
+    cbary[tid] = od.bary[tid];
+  }
+  __syncthreads();
+  const int64_t nitems = (int64_t)counters[5];
+  unsigned long long c_fail = 0;
+  double* fr = sfr[wv];
+  double* ecoef = scoef[wv];
+  double* wpan = span[wv];
+  for (int64_t it = (int64_t)blockIdx.x * kLamWaves + wv; it < nitems;
+       it += (int64_t)gridDim.x * kLamWaves) {
+    const int64_t slot = nlist[it];
+    const int64_t k = slot >> 2;
+    const int e = (int)(slot & 3);
+    const int P = tg.near_patch[k];
+    if (pd.order[P] != Q) continue;
+    const int64_t g = owner[k];
+    const int64_t n0 = pd.node_off[P];
+    const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
+    if (lane < kFrame) fr[lane] = pd.frame[(int64_t)P * kFrame + lane];
+    for (int i = lane; i < PT * 3; i += 64)
+      ecoef[i] = pd.edge_coef[(i % 3) * pd.E + e0 + i / 3];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int self = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
+    double xg[3], nv[3], xl[3], nl[3], u[3];
+    for (int c = 0; c < 3; ++c) {
+      xg[c] = tg.xyz[c * tg.T + g];
+      nv[c] = tg.nrm[c * tg.T + g];
+    }
+    wave_target_local<Q>(pd, fr, n0, self, xg, nv, xl, nl, u);
+    const double2 r0 = root[slot];
+    const double a = r0.x, b = r0.y;
+    bool over;
+    const int npan = wave_graded_panels(a, b, rho_far, wpan, NPAN, &over);
+    if (over && lane == 0) ++c_fail;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int npts = npan * PT;
+    double lacc[NB8];
+#pragma unroll
+    for (int bI = 0; bI < NB8; ++bI) lacc[bI] = 0.0;
+    double om = 0.0;
+    for (int base = 0; base < npts; base += 64) {
+      const int idx = base + lane;
+      double w1p = 0.0, w3p = 0.0, tau = 3.0;
+      asm volatile("" ::: "memory");   // keep the node tables out of registers
+      if (idx < npts) {
+        const int pn = idx / PT, gg = idx % PT;
+        const double lo = wpan[pn * 2], hi = wpan[pn * 2 + 1];
+        const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+        tau = c + h * cgl_t[gg];
+        const double K2 = (tau - a) * (tau - a) + b * b;
+        const double K1 = 1.0 / sqrt(K2);
+        const double hw = h * cgl_w[gg];
+        w1p = hw * K1;
+        w3p = w1p / K2;
+        double r[3], dr[3];
+        leg3r(ecoef, PT, tau, r, dr);
+        om += hw * omega0_at(xl, u, r, dr);
+      }
+      // Lagrange basis at tau, barycentric form; 1/(tau - t_j) by the hardware reciprocal
+      // and one Newton step (relative error a few ulp, against a correctly rounded divide)
+      double den = 0.0;
+      int hit = -1;
+#pragma unroll
+      for (int j = 0; j < PT; ++j) {
+        const double dtj = tau - cgl_t[j];
+        if (dtj == 0.0) hit = j;
+        else den += cbary[j] * rcp_nr(dtj);
+      }
+      const double rden = 1.0 / den;
+#pragma unroll
+      for (int bI = 0; bI < NB8; ++bI) {
+        double x[16];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int i = bI * 8 + v;
+          double l = 0.0;
+          if (i < PT) {
+            if (hit >= 0) l = hit == i ? 1.0 : 0.0;
+            else l = cbary[i] * rcp_nr(tau - cgl_t[i]) * rden;
+          }
+          x[v] = w1p * l;
+          x[8 + v] = w3p * l;
+        }
+        lacc[bI] += reduce_scatter16(x);
+      }
+    }
+    om = wave_sum(om);
+    double* outp = lamg + slot * lam_stride;
+    if ((lane & 3) == 0) {
+      const int v = lane >> 2;
+#pragma unroll
+      for (int bI = 0; bI < NB8; ++bI) {
+        const int i = bI * 8 + (v & 7);
+        if (i < PT) outp[(v >> 3) * PT + i] = lacc[bI];
+      }
+    }
+    if (lane == 0) outp[2 * PT] = om;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (c_fail) atomicAdd(&counters[2], c_fail);
+}
+
+hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
+                         const int64_t* owner, const double2* root, const int64_t* nlist,
+                         unsigned long long* counters, double* lamg, int lam_stride,
+                         double rho_far, hipStream_t st) {
+  if (tg.nnz <= 0) return hipSuccess;
+  const int grid = 2048;
+  switch (q) {
+#define X(Q) case Q: hipLaunchKernelGGL(k_lambda<Q>, dim3(grid), dim3(64 * kLamWaves), 0, st, pd, od, tg, owner, root, nlist, counters, lamg, lam_stride, rho_far); break;
+    X(4) X(5) X(6) X(8) X(10)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int Q, int T>
 struct TileLds {
   static constexpr int PT = 2 * Q, NP = np_of(Q), NJK = njk_of(Q), NR = tri(Q, Q) + 1;
@@ -406,9 +610,7 @@ struct TileLds {
   static constexpr int o_vq = o_td + n_scrA;               // [T][NJK][18]
   static constexpr int o_rt = o_vq + T * NJK * 18;         // [T][NR] cplx
   static constexpr int o_gs = o_rt + 2 * T * NR;           // [T][NR] cplx
-  static constexpr int NPAN = wave_panel_cap(Q);
-  static constexpr int o_pan = o_gs + 2 * T * NR;          // [4 waves][NPAN][2]
-  static constexpr int o_red = o_pan + 4 * NPAN * 2;
+  static constexpr int o_red = o_gs + 2 * T * NR;
   static constexpr int o_cst = o_red + 8;                  // gl_t, gl_w, bary [PT] each
   static constexpr int n_dbl = o_cst + 3 * PT;
   // ints
@@ -453,7 +655,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   double* vq = smem + L::o_vq;
   cplx* Rt = (cplx*)(smem + L::o_rt);
   cplx* gS = (cplx*)(smem + L::o_gs);
-  double* pan = smem + L::o_pan;
   double* cgl_t = smem + L::o_cst;
   double* cgl_w = cgl_t + PT;
   double* cbary = cgl_w + PT;
@@ -463,7 +664,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t tlo = qtile[0], thi = qtile[1];
-  unsigned long long c_fail = 0;
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
     cgl_w[tid] = od.gl_w[tid];
@@ -516,50 +716,18 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         const int64_t k = sorted[tile.y + sub + t];
         const int64_t g = out.owner[k];
         const int self = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
-        double xg[3], nv[3], xl[3], nl[3];
+        double xg[3], nv[3], xl[3], nl[3], u[3];
         for (int c = 0; c < 3; ++c) {
           xg[c] = tg.xyz[c * tg.T + g];
           nv[c] = tg.nrm[c * tg.T + g];
         }
-        frame_point(fr, xg, xl);
-        for (int a = 0; a < 3; ++a) {
-          const double* ax = fr + 3 + 3 * a;
-          nl[a] = nv[0] * ax[0] + nv[1] * ax[1] + nv[2] * ax[2];
-        }
-        double bd = 1e300;
-        int bi = 0x7fffffff;
-        if (self < 0) {
-          for (int i = lane; i < Q2; i += 64) {
-            double d2 = 0;
-            for (int c = 0; c < 3; ++c) {
-              const double dd = xl[c] - pd.node_loc[c * pd.N + n0 + i];
-              d2 += dd * dd;
-            }
-            if (d2 < bd) { bd = d2; bi = i; }
-          }
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(bd, o, 64);
-            const int oi = __shfl_xor(bi, o, 64);
-            if (ob < bd || (ob == bd && oi < bi)) { bd = ob; bi = oi; }
-          }
-        }
+        wave_target_local<Q>(pd, fr, n0, self, xg, nv, xl, nl, u);
         if (lane == 0) {
           sself[t] = self;
           for (int a = 0; a < 3; ++a) {
             sx[t * 3 + a] = xl[a];
             snu[t * 3 + a] = nl[a];
-          }
-          if (self >= 0) {
-            for (int c = 0; c < 3; ++c) su[t * 3 + c] = nl[c];
-          } else {
-            double dd = 0, nn[3];
-            for (int c = 0; c < 3; ++c) {
-              nn[c] = pd.node_loc[(3 + c) * pd.N + n0 + bi];
-              dd += (xl[c] - pd.node_loc[c * pd.N + n0 + bi]) * nn[c];
-            }
-            const double sg = dd >= 0.0 ? 1.0 : -1.0;
-            for (int c = 0; c < 3; ++c) su[t * 3 + c] = sg * nn[c];
+            su[t * 3 + a] = u[a];
           }
         }
       }
@@ -578,85 +746,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         solid_table<Q>(sx[t * 3 + 1], sx[t * 3 + 2], sx[t * 3 + 0], Rt + t * NR);
       }
       __syncthreads();
-      // ---- Lagrange-basis moments of near edges on graded panels: one wave per near item
-      // near items ranked by a ballot; wave w takes ranks w, w + 4, ... (near edges of one
-      // edge index cluster, so assigning by item index would load one wave)
-      const unsigned long long nmask = __ballot(lane < 4 * nt && snear[lane < 4 * nt ? lane : 0]);
-      const int nnear = __popcll(nmask);
-      for (int rk = wv; rk < nnear; rk += BNT / 64) {
-        unsigned long long mm = nmask;
-        for (int j = 0; j < rk; ++j) mm &= mm - 1;
-        const int item = __builtin_ctzll(mm);
-        const int t = item >> 2, e = item & 3;
-        const double a = st0[item * 2], b = st0[item * 2 + 1];
-        double* wpan = pan + wv * L::NPAN * 2;
-        bool over;
-        const int npan = wave_graded_panels(a, b, so.rho_far, wpan, L::NPAN, &over);
-        if (over && lane == 0) ++c_fail;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int npts = npan * PT;
-        double lacc[NB8];
-#pragma unroll
-        for (int bI = 0; bI < NB8; ++bI) lacc[bI] = 0.0;
-        double om = 0.0;
-        for (int base = 0; base < npts; base += 64) {
-          const int idx = base + lane;
-          double w1p = 0.0, w3p = 0.0, tau = 3.0;
-          asm volatile("" ::: "memory");   // keep the node tables out of registers
-          if (idx < npts) {
-            const int pn = idx / PT, g = idx % PT;
-            const double lo = wpan[pn * 2], hi = wpan[pn * 2 + 1];
-            const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
-            tau = c + h * cgl_t[g];
-            const double K2 = (tau - a) * (tau - a) + b * b;
-            const double K1 = 1.0 / sqrt(K2);
-            const double hw = h * cgl_w[g];
-            w1p = hw * K1;
-            w3p = w1p / K2;
-            double r[3], dr[3];
-            leg3r(ecoef + e * PT * 3, PT, tau, r, dr);
-            om += hw * omega0_at(sx + t * 3, su + t * 3, r, dr);
-          }
-          // Lagrange basis at tau, barycentric form; 1/(tau - t_j) by the hardware reciprocal
-          // and one Newton step (relative error a few ulp, against a correctly rounded divide)
-          double den = 0.0;
-          int hit = -1;
-#pragma unroll
-          for (int j = 0; j < PT; ++j) {
-            const double dtj = tau - cgl_t[j];
-            if (dtj == 0.0) hit = j;
-            else den += cbary[j] * rcp_nr(dtj);
-          }
-          const double rden = 1.0 / den;
-#pragma unroll
-          for (int bI = 0; bI < NB8; ++bI) {
-            double x[16];
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-              const int i = bI * 8 + v;
-              double l = 0.0;
-              if (i < PT) {
-                if (hit >= 0) l = hit == i ? 1.0 : 0.0;
-                else l = cbary[i] * rcp_nr(tau - cgl_t[i]) * rden;
-              }
-              x[v] = w1p * l;
-              x[8 + v] = w3p * l;
-            }
-            lacc[bI] += reduce_scatter16(x);
-          }
-        }
-        om = wave_sum(om);
-        if ((lane & 3) == 0) {
-          const int v = lane >> 2;
-#pragma unroll
-          for (int bI = 0; bI < NB8; ++bI) {
-            const int i = bI * 8 + (v & 7);
-            if (i < PT) lam[((t * 4 + e) * PT + i) * 2 + (v >> 3)] = lacc[bI];
-          }
-        }
-        if (lane == 0) som0e[item] = om;
-        __builtin_amdgcn_wave_barrier();
+      // ---- Lagrange-basis moments of the near edges, from the near-edge pre-pass
+      for (int idx = tid; idx < 4 * nt * (2 * PT + 1); idx += BNT) {
+        const int item = idx / (2 * PT + 1), i = idx % (2 * PT + 1);
+        if (!snear[item]) continue;
+        const int64_t slot = 4 * sorted[tile.y + sub + (item >> 2)] + (item & 3);
+        const double v = out.lamg[slot * out.lam_stride + i];
+        if (i < 2 * PT) lam[(item * PT + i % PT) * 2 + i / PT] = v;
+        else som0e[item] = v;
       }
       __syncthreads();
       // ---- effective weights per (target, edge, node), PTP lanes per (target, edge), and
@@ -1054,7 +1151,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       }
     }
   }
-  if (c_fail) atomicAdd(&out.counters[2], c_fail);
 }
 
 #define RRQ_TILE_CASES(X) X(4, 4) X(4, 8) X(5, 4) X(5, 8) X(6, 4) X(6, 8) X(8, 4) X(8, 8) X(10, 4)

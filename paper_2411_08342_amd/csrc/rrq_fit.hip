@@ -462,6 +462,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __syncthreads();
     hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sT, sG, sbeta, salpha, sX);
     hh_lsq(B, Q2, NP, LDB, LDB, sV, sT, sG, sbeta, salpha, sX);
+    // condition estimate of each fit: max|R_ii| / min|R_ii| (a lower bound of the 2-norm
+    // condition number of the weighted system), on wave 0 by lane reductions
+    if (tid < 64) {
+      double amax = 0.0, amin = 1e308, bmax = 0.0, bmin = 1e308;
+      for (int i = tid; i < 4 * NP; i += 64) {
+        const double r = fabs(A[(int64_t)i * LDA + i]);
+        amax = fmax(amax, r);
+        amin = fmin(amin, r);
+      }
+      for (int i = tid; i < NP; i += 64) {
+        const double r = fabs(B[(int64_t)i * LDB + i]);
+        bmax = fmax(bmax, r);
+        bmin = fmin(bmin, r);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        amax = fmax(amax, __shfl_xor(amax, o, 64));
+        amin = fmin(amin, __shfl_xor(amin, o, 64));
+        bmax = fmax(bmax, __shfl_xor(bmax, o, 64));
+        bmin = fmin(bmin, __shfl_xor(bmin, o, 64));
+      }
+      if (tid == 0) {
+        pd.fitcond[2 * (int64_t)P] = amax / amin;
+        pd.fitcond[2 * (int64_t)P + 1] = bmax / bmin;
+      }
+    }
     double* maps = pd.maps + pd.map_off[P];
     double* MD = maps;
     double* MSp = maps + 4 * NP * Q2;

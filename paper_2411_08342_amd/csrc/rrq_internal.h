@@ -54,6 +54,7 @@ struct PlanDev {
   double* tabs;             // per patch: [4][pt][njk][12]: c (3 cplx), h (3 cplx)
   const int64_t* tab_off;
   const float* mlp;         // learned-guess network, inference layout (or null)
+  double* fitcond;          // [P][2]: max|R_ii| / min|R_ii| of the DLP and SLP fits
 };
 
 struct TargetsDev {
@@ -74,6 +75,8 @@ struct AssembleOut {
   unsigned long long* counters;   // [8] stats
   const double2* root;      // [4 nnz] singularity-swap roots t0 (root pre-pass)
   const uint8_t* nearf;     // [4 nnz] 1: singularity-swap class, 0: plain rule
+  const double* lamg;       // [4 nnz][lam_stride] near-edge moments (near slots only)
+  int lam_stride;
   // potentials mode
   const double* dens;       // [N] nodal density
   const double* pcoef;      // [P][kCoefStride] c_D, c_S', c_S of every patch
@@ -143,7 +146,13 @@ struct RootOpts {
 };
 hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
                        const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
-                       unsigned long long* counters, hipStream_t st);
+                       int64_t* nlist, unsigned long long* counters, hipStream_t st);
+// near-edge moments of every singularity-swap slot listed by the root pre-pass (counters[5]
+// of them), for the patches of order q
+hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
+                         const int64_t* owner, const double2* root, const int64_t* nlist,
+                         unsigned long long* counters, double* lamg, int lam_stride,
+                         double rho_far, hipStream_t st);
 
 // learned initial guess: sample collection and training
 struct CollectOpts {

@@ -21,7 +21,7 @@ EXPORTED = ("rrq_plan_create", "rrq_plan_refit", "rrq_plan_destroy", "rrq_worksp
             "rrq_pair_offsets", "rrq_assemble", "rrq_apply", "rrq_autotune", "rrq_graph_create",
             "rrq_graph_launch", "rrq_graph_destroy", "rrq_collect_roots", "rrq_mlp_train",
             "rrq_mlp_loss_grad", "rrq_mlp_predict", "rrq_plan_set_mlp", "rrq_potentials",
-            "rrq_smooth_potentials", "rrq_status_string")
+            "rrq_smooth_potentials", "rrq_plan_fit_condition", "rrq_status_string")
 MLP_PARAMS = 4866
 
 
@@ -87,6 +87,7 @@ def lib():
                                       ctypes.POINTER(vp)]
         L.rrq_plan_refit.argtypes = [vp, ctypes.POINTER(Surface), vp]
         L.rrq_plan_destroy.argtypes = [vp]
+        L.rrq_plan_fit_condition.argtypes = [vp, vp, vp]
         L.rrq_workspace_size.argtypes = [vp, ctypes.POINTER(Targets), ctypes.POINTER(ctypes.c_size_t)]
         L.rrq_pair_offsets.argtypes = [vp, ctypes.POINTER(Targets), vp, vp, ctypes.c_size_t,
                                        ctypes.POINTER(i64), vp]
@@ -194,6 +195,12 @@ class Plan:
         """Install a trained network (float32 CUDA tensor of MLP_PARAMS) or remove it (None)."""
         _check(lib().rrq_plan_set_mlp(self.handle, params.data_ptr() if params is not None else None,
                                       _stream()))
+
+    def fit_condition(self):
+        """(P, 2) host array: max|R_ii| / min|R_ii| of the DLP and SLP fits of every patch."""
+        out = np.zeros((self.dsurf.npatch, 2))
+        _check(lib().rrq_plan_fit_condition(self.handle, out.ctypes.data, _stream()))
+        return out
 
     def refit(self, dsurf=None):
         if dsurf is not None:
