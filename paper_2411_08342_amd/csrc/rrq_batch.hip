@@ -589,23 +589,17 @@ template <int Q, int T>
 struct TileLds {
   static constexpr int PT = 2 * Q, NP = np_of(Q), NJK = njk_of(Q), NR = tri(Q, Q) + 1;
   static constexpr int o_fr = 0;
-  static constexpr int o_eloc = o_fr + kFrame;
-  static constexpr int o_etan = o_eloc + 4 * PT * 3;
-  static constexpr int o_ecoef = o_etan + 4 * PT * 3;
-  static constexpr int o_x = o_ecoef + 4 * PT * 3;        // [T][3]
+  static constexpr int o_x = o_fr + kFrame;                // [T][3]
   static constexpr int o_nu = o_x + 3 * T;
   static constexpr int o_u = o_nu + 3 * T;
   static constexpr int o_t0 = o_u + 3 * T;                 // [T][4][2]
   static constexpr int o_om = o_t0 + 8 * T;                // [T][4]: Omega_0, Omega_vec
   static constexpr int o_dom = o_om + 4 * T;               // [T][4]
-  static constexpr int o_om0e = o_dom + 4 * T;             // [T][4]: Omega_0 per edge
-  static constexpr int o_part = o_om0e + 4 * T;            // [T][4][8]: edge partial sums
+  static constexpr int o_part = o_dom + 4 * T;             // [T][4][8]: edge partial sums
   static constexpr int o_td = o_part + 32 * T;             // [T][4][PT][8] (aliased by rows)
   static constexpr int n_td = T * 4 * PT * 8;
-  static constexpr int o_lam = o_td + n_td;                // [T][4][PT][2]
-  static constexpr int n_lam = T * 4 * PT * 2;
   static constexpr int n_rows = T * 17 * NP;
-  static constexpr int n_scrA = (n_td + n_lam) > n_rows ? (n_td + n_lam) : n_rows;
+  static constexpr int n_scrA = n_td > n_rows ? n_td : n_rows;
   static constexpr int o_rows = o_td;                      // rD [T][4NP], rSp, rS [T][5NP], rDp
   static constexpr int o_vq = o_td + n_scrA;               // [T][NJK][18]
   static constexpr int o_rt = o_vq + T * NJK * 18;         // [T][NR] cplx
@@ -623,9 +617,11 @@ struct TileLds {
 // Persistent workgroups take tiles of this order from a queue, so that the workgroups in
 // flight work on a narrow window of consecutive tiles (tiles of one patch are consecutive)
 // and the patch's maps and edge tables are served from L2.
+// Register target = the workgroups per CU that the LDS allows (160 KiB per CU): three at
+// order 8 with 4 targets, which outweighs the spills that 168 VGPRs cost.
 template <int Q, int T, bool POT>
 __global__ __launch_bounds__(BNT)
-__attribute__((amdgpu_waves_per_eu(TileLds<Q, T>::bytes <= 80 * 1024 ? 2 : 1)))
+__attribute__((amdgpu_waves_per_eu(TileLds<Q, T>::bytes <= 54 * 1024 ? 3 : (TileLds<Q, T>::bytes <= 80 * 1024 ? 2 : 1))))
 void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
                                                    AssembleOut out, SolveOpts so,
                                                    const int4* tiles, const int64_t* qtile,
@@ -638,19 +634,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   extern __shared__ double smem[];
   __shared__ long long s_ti;
   double* fr = smem + L::o_fr;
-  double* eloc = smem + L::o_eloc;
-  double* etan = smem + L::o_etan;
-  double* ecoef = smem + L::o_ecoef;
   double* sx = smem + L::o_x;
   double* snu = smem + L::o_nu;
   double* su = smem + L::o_u;
   double* st0 = smem + L::o_t0;
   double* som = smem + L::o_om;
   double* sdom = smem + L::o_dom;
-  double* som0e = smem + L::o_om0e;
   double* part = smem + L::o_part;
   double* td = smem + L::o_td;
-  double* lam = smem + L::o_lam;
   double* rows = smem + L::o_rows;
   double* vq = smem + L::o_vq;
   cplx* Rt = (cplx*)(smem + L::o_rt);
@@ -703,12 +694,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       __syncthreads();
       // ---- patch data
       if (tid < kFrame) fr[tid] = pd.frame[(int64_t)P * kFrame + tid];
-      for (int i = tid; i < 4 * PT * 3; i += BNT) {
-        const int c = i % 3, ei = i / 3;
-        eloc[i] = pd.edge_loc[c * pd.E + e0 + ei];
-        etan[i] = pd.edge_tan[c * pd.E + e0 + ei];
-        ecoef[i] = pd.edge_coef[c * pd.E + e0 + ei];
-      }
       __syncthreads();
       // ---- targets (one wave each): local coordinates; u from the nearest node, lowest
       // index on ties (wave argmin)
@@ -740,20 +725,9 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         snear[t * 4 + e] = out.nearf[slot];
         st0[(t * 4 + e) * 2] = r.x;
         st0[(t * 4 + e) * 2 + 1] = r.y;
-        som0e[t * 4 + e] = 0.0;
       } else if (tid >= 64 && tid < 64 + nt) {
         const int t = tid - 64;
         solid_table<Q>(sx[t * 3 + 1], sx[t * 3 + 2], sx[t * 3 + 0], Rt + t * NR);
-      }
-      __syncthreads();
-      // ---- Lagrange-basis moments of the near edges, from the near-edge pre-pass
-      for (int idx = tid; idx < 4 * nt * (2 * PT + 1); idx += BNT) {
-        const int item = idx / (2 * PT + 1), i = idx % (2 * PT + 1);
-        if (!snear[item]) continue;
-        const int64_t slot = 4 * sorted[tile.y + sub + (item >> 2)] + (item & 3);
-        const double v = out.lamg[slot * out.lam_stride + i];
-        if (i < 2 * PT) lam[(item * PT + i % PT) * 2 + i / PT] = v;
-        else som0e[item] = v;
       }
       __syncthreads();
       // ---- effective weights per (target, edge, node), PTP lanes per (target, edge), and
@@ -764,25 +738,32 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         double om0 = 0.0, ov[3] = {0, 0, 0}, dv[3] = {0, 0, 0}, dom0 = 0.0;
         const bool act = t < nt && i < PT;
         const int near = t < nt ? snear[te] : 0;
+        // near edges: lambda^(1), lambda^(3) and the Omega_0 part from the near-edge pre-pass
+        const double* lg = nullptr;
+        if (near) lg = out.lamg + (4 * sorted[tile.y + sub + t] + e) * out.lam_stride;
         if (act) {
           const double* xl = sx + t * 3;
           const double* nl = snu + t * 3;
           const double a = st0[te * 2], b = st0[te * 2 + 1];
-          const int ei = e * PT + i;
-          double d[3];
-          for (int c = 0; c < 3; ++c) d[c] = xl[c] - eloc[ei * 3 + c];
+          const int64_t ei = e0 + e * PT + i;
+          double d[3], rr[3], rp[3];
+          for (int c = 0; c < 3; ++c) {
+            rr[c] = pd.edge_loc[c * pd.E + ei];
+            rp[c] = pd.edge_tan[c * pd.E + ei];
+            d[c] = xl[c] - rr[c];
+          }
           const double R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
           const double R = sqrt(R2);
           double w1, w3;
           if (near) {
             const double ta = cgl_t[i] - a;
             const double q1 = sqrt(ta * ta + b * b) / R;
-            w1 = lam[(te * PT + i) * 2] * q1;
-            w3 = lam[(te * PT + i) * 2 + 1] * q1 * q1 * q1;
+            w1 = lg[i] * q1;
+            w3 = lg[PT + i] * q1 * q1 * q1;
           } else {
             w1 = cgl_w[i] / R;
             w3 = cgl_w[i] / (R2 * R);
-            om0 = cgl_w[i] * omega0_at(xl, su + t * 3, eloc + ei * 3, etan + ei * 3);
+            om0 = cgl_w[i] * omega0_at(xl, su + t * 3, rr, rp);
           }
           const double dn = d[0] * nl[0] + d[1] * nl[1] + d[2] * nl[2];
           double* o = td + (te * PT + i) * 8;
@@ -791,7 +772,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             o[1 + c] = d[c];
             o[4 + c] = w1 * nl[c] - w3 * dn * d[c];
           }
-          const double* rp = etan + ei * 3;
           for (int c = 0; c < 3; ++c) {
             ov[c] = -w1 * rp[c];
             dv[c] = w3 * dn * rp[c];
@@ -813,7 +793,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
         if (i == 0 && t < nt) {
           double* pp = part + te * 8;
-          pp[0] = near ? som0e[te] : om0;
+          pp[0] = near ? lg[2 * PT] : om0;
           pp[1] = ov[0]; pp[2] = ov[1]; pp[3] = ov[2];
           pp[4] = dv[0]; pp[5] = dv[1]; pp[6] = dv[2]; pp[7] = dom0;
         }
