@@ -23,8 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": "ed097b3cf16e3f0a75d2bbaff831e2e1ebf792d85591753b3237824559b1241b",
-           "fetch_bytes": 1700000675, "write_bytes": 3599357056}
+TRAFFIC = {"src_sha256": "de21eeb17dc9f1d7c4a1a5fc2a5c2a9c0c855ad01d65d6bd8986e23e404ad83d",
+           "fetch_bytes": 1940298198, "write_bytes": 4180977664}
 
 
 def flops_per_pair(q):

@@ -131,7 +131,7 @@ __device__ __forceinline__ void leg3r(const double* coef, int n, double t, doubl
     dr[c] = 0.0;
   }
   for (int k = 0; k < n - 1; ++k) {
-    const double p2 = ((2.0 * k + 1.0) * t * p1 - (double)k * p0) / (k + 1);
+    const double p2 = ((2.0 * k + 1.0) * t * p1 - (double)k * p0) * (1.0 / (k + 1));
     const double d2 = d0 + (2.0 * k + 1.0) * p1;
     p0 = p1; p1 = p2; d0 = d1; d1 = d2;
     for (int c = 0; c < 3; ++c) {
@@ -394,6 +394,15 @@ hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* o
 // ---------------------------------------------------------------------------------------
 // LDS layout of one tile (doubles, then ints)
 // ---------------------------------------------------------------------------------------
+// An opaque copy of a value: the compiler must assume it changed, so the per-lane
+// addresses derived from it are recomputed in each phase of the tile kernel instead of being
+// kept live (and spilled) from the start of the tile.
+template <typename V>
+__device__ __forceinline__ V fresh(V v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // One wave: local coordinates xl and normal nl of a target in the frame fr of a patch whose
 // nodes start at n0, and the vector u of the solid-angle integrand: the target normal for a
 // self target, else the normal of the nearest node (lowest index on ties, wave argmin)
@@ -595,7 +604,9 @@ struct TileLds {
   static constexpr int o_t0 = o_u + 3 * T;                 // [T][4][2]
   static constexpr int o_om = o_t0 + 8 * T;                // [T][4]: Omega_0, Omega_vec
   static constexpr int o_dom = o_om + 4 * T;               // [T][4]
-  static constexpr int o_part = o_dom + 4 * T;             // [T][4][8]: edge partial sums
+  static constexpr int o_ids = o_dom + 4 * T;              // [T][3] i64: pair, target, offset
+  static constexpr int o_xg = o_ids + 3 * T;               // [T][6]: global point, normal
+  static constexpr int o_part = o_xg + 6 * T;              // [T][4][8]: edge partial sums
   static constexpr int o_td = o_part + 32 * T;             // [T][4][PT][8] (aliased by rows)
   static constexpr int n_td = T * 4 * PT * 8;
   static constexpr int n_rows = T * 17 * NP;
@@ -640,6 +651,8 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   double* st0 = smem + L::o_t0;
   double* som = smem + L::o_om;
   double* sdom = smem + L::o_dom;
+  int64_t* sids = (int64_t*)(smem + L::o_ids);   // per target: pair k, target g, pair_off[k]
+  double* sxg = smem + L::o_xg;                   // per target: global point and normal
   double* part = smem + L::o_part;
   double* td = smem + L::o_td;
   double* rows = smem + L::o_rows;
@@ -706,9 +719,16 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
           xg[c] = tg.xyz[c * tg.T + g];
           nv[c] = tg.nrm[c * tg.T + g];
         }
-        wave_target_local<Q>(pd, fr, n0, self, xg, nv, xl, nl, u);
+        wave_target_local<Q>(pd, fr, fresh(n0), self, xg, nv, xl, nl, u);
         if (lane == 0) {
           sself[t] = self;
+          sids[t * 3] = k;
+          sids[t * 3 + 1] = g;
+          sids[t * 3 + 2] = POT ? 0 : out.pair_off[k];
+          for (int c = 0; c < 3; ++c) {
+            sxg[t * 6 + c] = xg[c];
+            sxg[t * 6 + 3 + c] = nv[c];
+          }
           for (int a = 0; a < 3; ++a) {
             sx[t * 3 + a] = xl[a];
             snu[t * 3 + a] = nl[a];
@@ -720,7 +740,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       // ---- Step 5 results (root pre-pass) per (target, edge); Step 4: target harmonics
       if (tid < 4 * nt) {
         const int t = tid >> 2, e = tid & 3;
-        const int64_t slot = 4 * sorted[tile.y + sub + t] + e;
+        const int64_t slot = 4 * sids[t * 3] + e;
         const double2 r = out.root[slot];
         snear[t * 4 + e] = out.nearf[slot];
         st0[(t * 4 + e) * 2] = r.x;
@@ -740,12 +760,12 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         const int near = t < nt ? snear[te] : 0;
         // near edges: lambda^(1), lambda^(3) and the Omega_0 part from the near-edge pre-pass
         const double* lg = nullptr;
-        if (near) lg = out.lamg + (4 * sorted[tile.y + sub + t] + e) * out.lam_stride;
+        if (near) lg = out.lamg + (4 * sids[t * 3] + e) * out.lam_stride;
         if (act) {
           const double* xl = sx + t * 3;
           const double* nl = snu + t * 3;
           const double a = st0[te * 2], b = st0[te * 2 + 1];
-          const int64_t ei = e0 + e * PT + i;
+          const int64_t ei = fresh(e0) + e * PT + i;
           double d[3], rr[3], rp[3];
           for (int c = 0; c < 3; ++c) {
             rr[c] = pd.edge_loc[c * pd.E + ei];
@@ -987,8 +1007,8 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         const bool corr = (out.flags & RRQ_F_CORRECTION) != 0;
         const double sc = fr[12];
         for (int t = wv; t < nt; t += BNT / 64) {
-          const int64_t k = sorted[tile.y + sub + t];
-          const int64_t g = out.owner[k];
+          const int64_t k = sids[t * 3];
+          const double* xt = sxg + t * 6;
           const double* rD = rows + t * 4 * NP;
           const double* rSp = rows + T * 4 * NP + t * 4 * NP;
           const double* rS = rows + T * 8 * NP + t * 5 * NP;
@@ -1004,11 +1024,11 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
           a0 *= sc;
           a3 /= sc;
           if (corr) {
-            const double x0 = tg.xyz[g], x1 = tg.xyz[tg.T + g], x2 = tg.xyz[2 * tg.T + g];
-            const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
+            const double x0 = xt[0], x1 = xt[1], x2 = xt[2];
+            const double nt0 = xt[3], nt1 = xt[4], nt2 = xt[5];
             for (int j = lane; j < Q2; j += 64) {
               if (j == sself[t]) continue;
-              const int64_t nj = n0 + j;
+              const int64_t nj = fresh(n0) + j;
               const double d0 = x0 - pd.node_xyz[nj];
               const double d1 = x1 - pd.node_xyz[pd.N + nj];
               const double d2 = x2 - pd.node_xyz[2 * pd.N + nj];
@@ -1087,7 +1107,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             }
             if (!bval) continue;
             const int j = bcol;
-            const int64_t nj = n0 + j;
+            const int64_t nj = fresh(n0) + j;
             const double rx = pd.node_xyz[nj], ry = pd.node_xyz[pd.N + nj], rz = pd.node_xyz[2 * pd.N + nj];
             const double v0 = pd.node_nrm[nj], v1 = pd.node_nrm[pd.N + nj], v2 = pd.node_nrm[2 * pd.N + nj];
             const double wj = pd.node_wt[nj] * kInv4Pi;
@@ -1097,14 +1117,13 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
               const int t = (a % TQ) * 4 + kr;
               const int K = grp == 0 ? (a < TQ ? 1 : 3) : (grp == 1 ? 2 : 0);
               if (t >= nt || !(out.kmask & (1u << K)) || out.w[K] == nullptr) continue;
-              const int64_t k = sorted[tile.y + sub + t];
-              const int64_t g = out.owner[k];
+              const double* xt = sxg + t * 6;
               double val = acc[a];
               if (K == 0) val *= sc;
               else if (K == 3) val /= sc;
               if ((out.flags & RRQ_F_CORRECTION) && j != sself[t]) {
                 // smooth-rule kernels from one reciprocal square root: 1/R, then powers
-                const double d0 = tg.xyz[g] - rx, d1 = tg.xyz[tg.T + g] - ry, d2 = tg.xyz[2 * tg.T + g] - rz;
+                const double d0 = xt[0] - rx, d1 = xt[1] - ry, d2 = xt[2] - rz;
                 const double R2 = d0 * d0 + d1 * d1 + d2 * d2;
                 const double ri = 1.0 / sqrt(R2), ri2 = ri * ri, ri3 = ri2 * ri;
                 double kv;
@@ -1113,7 +1132,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
                 } else if (K == 1) {
                   kv = (d0 * v0 + d1 * v1 + d2 * v2) * ri3;
                 } else {
-                  const double nt0 = tg.nrm[g], nt1 = tg.nrm[tg.T + g], nt2 = tg.nrm[2 * tg.T + g];
+                  const double nt0 = xt[3], nt1 = xt[4], nt2 = xt[5];
                   const double dnt = d0 * nt0 + d1 * nt1 + d2 * nt2;
                   if (K == 2) {
                     kv = -dnt * ri3;
@@ -1124,7 +1143,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
                 }
                 val -= kv * wj;
               }
-              out.w[K][out.pair_off[k] + j] = val;
+              out.w[K][sids[t * 3 + 2] + j] = val;
             }
           }
         }
