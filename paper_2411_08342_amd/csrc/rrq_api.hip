@@ -179,7 +179,10 @@ __global__ void k_copy3(const double* a, const double* b, const double* c, doubl
   }
 }
 
-static rrq_status run_fit(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
+// Source-only data in two parts: the geometry (frames, local nodes, edge interpolants), which
+// the root and near-edge pre-passes need, and the maps and edge tables, which only the tile
+// kernels need (a captured step runs the second part beside the pre-passes).
+static rrq_status run_geometry(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
   // plan copies of the smooth-rule data used by the correction (a kernel, not a memcpy, so
   // that the step can be captured into a graph)
   {
@@ -199,6 +202,16 @@ static rrq_status run_fit(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
     if (!cnt) continue;
     if (launch_geometry(pd, sd, p->od[q], p->patches_d[q], cnt, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
+  }
+  return RRQ_OK;
+}
+
+static rrq_status run_maps(rrq_plan* p, hipStream_t st) {
+  PlanDev pd = p->dev();
+  for (int qi = 0; qi < kNumOrders; ++qi) {
+    const int q = kOrders[qi];
+    const int cnt = (int)p->patches_h[q].size();
+    if (!cnt) continue;
     if (launch_edge_tables(pd, p->od[q], p->patches_d[q], cnt, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
     if (launch_fit(pd, p->od[q], p->patches_d[q], cnt, p->fit_ws_d, p->fit_ws_per_block,
@@ -206,6 +219,11 @@ static rrq_status run_fit(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
       return RRQ_ERR_DEVICE;
   }
   return RRQ_OK;
+}
+
+static rrq_status run_fit(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
+  rrq_status r = run_geometry(p, s, st);
+  return r == RRQ_OK ? run_maps(p, st) : r;
 }
 
 extern "C" {
@@ -454,7 +472,7 @@ rrq_status rrq_pair_offsets(const rrq_plan* p, const rrq_targets* tg, int64_t* p
 static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
                             uint32_t flags, double* const* outs, const int64_t* pair_off,
                             const double* density, double* const* pots, void* workspace,
-                            hipStream_t st, rrq_stats* stats) {
+                            hipStream_t st, rrq_stats* stats, hipEvent_t maps_ready = nullptr) {
   const bool pot = pots != nullptr;
   const WsLayout wl = ws_layout(p, tg->nnz);
   char* wb = (char*)workspace;
@@ -490,6 +508,7 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
     }
   } evg{ev};
   if (flags & RRQ_F_PLAIN) {
+    if (maps_ready && hipStreamWaitEvent(st, maps_ready, 0) != hipSuccess) return RRQ_ERR_DEVICE;
     if (stats && hipEventRecord(ev[0], st) != hipSuccess) return RRQ_ERR_DEVICE;
     for (int qi = 0; qi < kNumOrders; ++qi) {
       const int q = kOrders[qi];
@@ -536,6 +555,8 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       ao.lamg = lamg;
       ao.lam_stride = lam_stride;
     }
+    // the maps and edge tables may still be in flight on another stream (captured step)
+    if (maps_ready && hipStreamWaitEvent(st, maps_ready, 0) != hipSuccess) return RRQ_ERR_DEVICE;
     if (pot && launch_patch_coef(pd, density, (double*)(wb + wl.pcoef), st) != hipSuccess)
       return RRQ_ERR_DEVICE;
     if (stats && hipEventRecord(ev[0], st) != hipSuccess) return RRQ_ERR_DEVICE;
@@ -872,12 +893,29 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
     (void)hipStreamDestroy(cs);
     return RRQ_ERR_DEVICE;
   }
-  r = rrq_plan_refit(p, s, cs);
+  // captured step: geometry, then the maps and edge tables on a second stream beside the pair
+  // offsets, binning and pre-passes; the tile kernels wait for them
+  hipStream_t ms = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  bool ok = hipStreamCreateWithFlags(&ms, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+  r = ok ? run_geometry(p, s, cs) : RRQ_ERR_DEVICE;
+  if (r == RRQ_OK && (hipEventRecord(fork, cs) != hipSuccess ||
+                      hipStreamWaitEvent(ms, fork, 0) != hipSuccess))
+    r = RRQ_ERR_DEVICE;
+  if (r == RRQ_OK) r = run_maps(p, ms);
+  if (r == RRQ_OK && hipEventRecord(join, ms) != hipSuccess) r = RRQ_ERR_DEVICE;
   if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, workspace, workspace_bytes, nullptr, cs);
-  if (r == RRQ_OK)
-    r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
-                     workspace_bytes, cs, nullptr);
+  if (r == RRQ_OK) {
+    double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
+    r = run_pairs(p, tg, kmask, flags, outs, pair_off, nullptr, nullptr, workspace, cs, nullptr,
+                  join);
+  }
   hipError_t ec = hipStreamEndCapture(cs, &g->graph);
+  if (join) (void)hipEventDestroy(join);
+  if (fork) (void)hipEventDestroy(fork);
+  if (ms) (void)hipStreamDestroy(ms);
   if (r == RRQ_OK && ec == hipSuccess &&
       hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess) {
     (void)hipStreamDestroy(cs);

@@ -335,6 +335,24 @@ def test_graph_replays_match_eager():
             assert np.array_equal(asm.out[k].cpu().numpy(), eager[k]), (rep, k)
         asm.assemble(flags=rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV | rrq.RRQ_F_PLAIN)
         torch.cuda.synchronize()
+    # the step refits: move surface and targets in place (a scale and a shift), and a replay
+    # must equal an eager refit and assembly of the moved surface (the maps, computed beside
+    # the pre-passes in the graph, are ready before the tile kernels read them)
+    ds = plan.dsurf
+    with torch.no_grad():
+        for t in (ds.node_xyz, ds.edge_xyz, asm.dtg.xyz):
+            t.mul_(1.5).add_(0.25)
+        ds.node_wt.mul_(2.25)
+    torch.cuda.synchronize()
+    g.launch()
+    torch.cuda.synchronize()
+    replay = {k: asm.out[k].cpu().numpy().copy() for k in KERNELS}
+    plan.refit()
+    asm.assemble()
+    torch.cuda.synchronize()
+    for k in KERNELS:
+        assert np.array_equal(replay[k], asm.out[k].cpu().numpy()), k
+        assert not np.array_equal(replay[k], eager[k]), k
     g.close()
 
 
