@@ -206,10 +206,13 @@ rrq_status rrq_autotune(rrq_plan* plan, const rrq_targets* tg, uint32_t kmask, u
                         const char* cache_path, void* stream, rrq_tune_result* result);
 
 /* One whole assembly step (rrq_plan_refit, rrq_pair_offsets, rrq_assemble with the given
- * arguments) captured into a HIP graph; rrq_graph_launch replays it on `stream`.  The graph
- * holds the pointers it was created with: the buffers must stay allocated and the sizes
- * unchanged until rrq_graph_destroy.  Nothing in the captured step allocates memory or
- * issues memset/memcpy nodes. */
+ * arguments) captured into a HIP graph; rrq_graph_launch replays it on `stream`.  In the
+ * graph the maps and edge tables (needed only by the tile kernels) run on a branch of their
+ * own beside the pair offsets, binning and pre-passes, joined before the tile kernels.  The
+ * graph holds the pointers it was created with: the buffers must stay allocated and the
+ * sizes unchanged until rrq_graph_destroy; their contents (surface, targets) may change
+ * between replays.  Nothing in the captured step allocates memory or issues memset/memcpy
+ * nodes. */
 typedef struct rrq_graph rrq_graph;
 rrq_status rrq_graph_create(rrq_plan* plan, const rrq_surface* surf, const rrq_targets* tg,
                             uint32_t kmask, uint32_t flags, double* out_S, double* out_D,
