@@ -23,8 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": "de21eeb17dc9f1d7c4a1a5fc2a5c2a9c0c855ad01d65d6bd8986e23e404ad83d",
-           "fetch_bytes": 1940298198, "write_bytes": 4180977664}
+TRAFFIC = {"src_sha256": "5d382d5f8760bfee5ca702ff4cf6c43bedd4dd76788fa3a891d3abd788c7f42b",
+           "fetch_bytes": 1932676789, "write_bytes": 4180637312}
 
 
 def flops_per_pair(q):
@@ -173,6 +173,44 @@ def cpu_baseline(surf, tg, seconds=20.0, seed=0):
                        f"({len(fits)} patch fits included), {dt:.1f} s"), results
 
 
+def parity_gate(surf, tg, res, gpu_blocks, owner, max_pairs=150, tol=1e-11, ulp_factor=30.0):
+    """Fraction of the sampled pair blocks (the first max_pairs) that pass the weights gate of
+    the parity tests: ||W_gpu - W_or|| <= tol ||W_raw|| + ulp_factor ||dW_ulp||, dW_ulp the
+    largest change of the oracle block under rounding-level perturbations (target moved by
+    one relative ulp, edge samples by one ulp, fits solved by SVD instead of QR)."""
+    from oracle.assemble import pair_block
+    KERNELS = ("S", "D", "Sp", "Dp")
+    fits, fits_svd = {}, {}
+    ok = {k: 0 for k in KERNELS}
+    pairs = sorted(res)[:max_pairs]
+    for i in pairs:
+        t, P = int(owner[i]), int(tg["near_patch"][i])
+        W = res[i]
+        raw, _ = pair_block(surf, tg, fits, t, P, False)
+        need = [k for k in KERNELS
+                if np.max(np.abs(gpu_blocks[i][k] - W[k])) > tol * np.max(np.abs(raw[k]))]
+        for k in KERNELS:
+            ok[k] += k not in need
+        if not need:
+            continue
+        tg2 = dict(tg)
+        x = np.array(tg["xyz"], copy=True)
+        x[:, t] *= 1.0 + 2.0 ** -52
+        tg2["xyz"] = x
+        s2 = dict(surf)
+        e = np.array(surf["edge_xyz"], copy=True)
+        sg = np.random.default_rng(i).choice([-1.0, 1.0], size=e.shape)
+        s2["edge_xyz"] = e * (1.0 + 2.0 ** -52 * sg)
+        pert = (pair_block(surf, tg2, fits, t, P)[0], pair_block(surf, tg, fits_svd, t, P, True,
+                                                                 True, "svd")[0],
+                pair_block(s2, tg, {}, t, P)[0])
+        for k in need:
+            dw = max(np.max(np.abs(pp[k] - W[k])) for pp in pert)
+            ok[k] += np.max(np.abs(gpu_blocks[i][k] - W[k])) <= (tol * np.max(np.abs(raw[k]))
+                                                                + ulp_factor * dw)
+    return {k: ok[k] / len(pairs) for k in KERNELS}
+
+
 def copy_probe(nbytes=1 << 30, reps=3):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -307,12 +345,15 @@ def main():
                 for k in rrq.KERNELS:
                     sm[k][int(tg["self_node"][t])] = 0.0
             raw[i] = {k: W[k] + sm[k] for k in rrq.KERNELS}
+        gpu_blocks = {i: {k: asm.out[k][off[i]:off[i + 1]].cpu().numpy() for k in rrq.KERNELS}
+                      for i in res}
+        gate = parity_gate(surf, tg, res, gpu_blocks, owner, max_pairs=150)
         acc = {}
         for k in rrq.KERNELS:
             wrel = pot = 0.0
             within = 0
             for i, W in res.items():
-                g = asm.out[k][off[i]:off[i + 1]].cpu().numpy()
+                g = gpu_blocks[i][k]
                 P = int(tg["near_patch"][i])
                 f = dens[surf["node_off"][P]:surf["node_off"][P + 1]]
                 d = np.max(np.abs(g - W[k]))
@@ -322,7 +363,8 @@ def main():
                 pot = max(pot, abs((g - W[k]) @ f) / np.sum(np.abs(raw[i][k] * f)))
             acc[k] = {"weights_max_rel_to_raw_block": wrel,
                       "pairs_within_1e-11_of_raw_block": within / len(res),
-                      "potential_max_rel_to_raw_block": pot}
+                      "potential_max_rel_to_raw_block": pot,
+                      "pairs_within_parity_gate": gate[k]}
         cb["gpu_vs_oracle_on_sample"] = acc
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

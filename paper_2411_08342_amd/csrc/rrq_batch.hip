@@ -615,9 +615,8 @@ struct TileLds {
   static constexpr int o_vq = o_td + n_scrA;               // [T][NJK][18]
   static constexpr int o_rt = o_vq + T * NJK * 18;         // [T][NR] cplx
   static constexpr int o_gs = o_rt + 2 * T * NR;           // [T][NR] cplx
-  static constexpr int o_red = o_gs + 2 * T * NR;
-  static constexpr int o_cst = o_red + 8;                  // gl_t, gl_w, bary [PT] each
-  static constexpr int n_dbl = o_cst + 3 * PT;
+  static constexpr int o_cst = o_gs + 2 * T * NR;          // gl_t, gl_w [PT] each
+  static constexpr int n_dbl = o_cst + 2 * PT;
   // ints
   static constexpr int i_near = 0;                         // [T][4]
   static constexpr int i_self = i_near + 4 * T;
@@ -661,7 +660,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   cplx* gS = (cplx*)(smem + L::o_gs);
   double* cgl_t = smem + L::o_cst;
   double* cgl_w = cgl_t + PT;
-  double* cbary = cgl_w + PT;
   int* ints = (int*)(smem + L::n_dbl);
   int* snear = ints + L::i_near;
   int* sself = ints + L::i_self;
@@ -671,7 +669,6 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
     cgl_w[tid] = od.gl_w[tid];
-    cbary[tid] = od.bary[tid];
   }
   // chunk c of the order's tiles is [tlo + len c / kXcds, tlo + len (c+1) / kXcds); the
   // workgroup starts with its own die's chunk and moves on to the next one when it is empty
