@@ -95,7 +95,7 @@ typedef struct {
                            <= 0 selects 10^(8/ptilde)                                       */
   double newton_tol;    /* Newton step tolerance (relative); <= 0 selects 1e-14             */
   int32_t newton_maxit; /* <= 0 selects 60                                                  */
-  int32_t tile_targets; /* batched form: targets per workgroup tile (4 or 8); <= 0 = 8
+  int32_t tile_targets; /* batched form: targets per workgroup tile (4 or 8); <= 0 = 4
                            until rrq_autotune picks one                                     */
   int32_t grid;         /* batched form: persistent workgroups per launch; <= 0 = 2048
                            until rrq_autotune picks one                                     */

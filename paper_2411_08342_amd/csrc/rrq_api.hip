@@ -255,7 +255,7 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
     delete p;
     return RRQ_ERR_UNSUPPORTED;
   }
-  p->tile = p->opt.tile_targets > 0 ? p->opt.tile_targets : 8;
+  p->tile = p->opt.tile_targets > 0 ? p->opt.tile_targets : 4;
   if (p->opt.grid < 0 || p->opt.grid > (1 << 20)) {
     delete p;
     return RRQ_ERR_ARG;

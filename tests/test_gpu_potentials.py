@@ -175,7 +175,7 @@ def _rounding_scale(surf, tg, targets, f, correction, onsurf_pv):
     return out
 
 
-@pytest.mark.parametrize("case", ["sphere", "star", "mixed"])
+@pytest.mark.parametrize("case", ["sphere", "star", "mixed", "star-tile8"])
 def test_potentials_match_assemble_apply(case):
     """rrq_potentials = rrq_apply(rrq_assemble) per target.  Both add up the same products,
     the first as rows . (maps . f), the second as (rows . maps) . f, so they differ by
@@ -187,12 +187,12 @@ def test_potentials_match_assemble_apply(case):
     from paper_2411_08342_amd import rrq
     if case == "sphere":
         surf, tg, _ = wl.config1()
-    elif case == "star":
+    elif case.startswith("star"):
         surf, tg, _ = wl.config2(n=4)
     else:
         surf, tg, _ = wl.config3(n_ell=2, nmin=2, nmax=3, mean_targets=40)
     f = _density(surf)
-    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    plan = rrq.Plan(rrq.DeviceSurface(surf), tile_targets=8 if case.endswith("tile8") else 0)
     dtg = rrq.DeviceTargets(tg)
     asm = rrq.Assembler(plan, dtg)
     ev = rrq.Evaluator(plan, dtg)
