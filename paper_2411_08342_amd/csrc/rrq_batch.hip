@@ -1069,11 +1069,12 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             const int NA = grp == 0 ? 2 * TQ : TQ;          // accumulators: (kind, target quad)
             const int bcol = ct * 16 + (lane & 15);
             const bool bval = bcol < Q2;
-            double acc[2 * TQ];
+            double acc[2 * TQ], acc2[2 * TQ];
 #pragma unroll
-            for (int a = 0; a < 2 * TQ; ++a) acc[a] = 0.0;
+            for (int a = 0; a < 2 * TQ; ++a) acc[a] = acc2[a] = 0.0;
             // 8 k-steps per batch: map operands loaded first (8 loads in flight), then the
-            // row operands and MFMAs of every accumulator
+            // row operands and MFMAs of every accumulator, alternating between two partial
+            // sums so that consecutive MFMAs do not wait on each other
             for (int kb = 0; kb < KR; kb += 32) {
               double bv[8];
 #pragma unroll
@@ -1098,10 +1099,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
                   av[u] = (rowp != nullptr && k < KR) ? rowp[k] : 0.0;
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < 8; u += 2) {
                   acc[a] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[u], bv[u], acc[a], 0, 0, 0);
+                  acc2[a] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[u + 1], bv[u + 1], acc2[a], 0, 0, 0);
+                }
               }
             }
+#pragma unroll
+            for (int a = 0; a < 2 * TQ; ++a) acc[a] += acc2[a];
             if (!bval) continue;
             const int j = bcol;
             const int64_t nj = fresh(n0) + j;
