@@ -401,3 +401,54 @@ def test_green_extinction_on_exterior_grid_sphere():
               f"{len(tg['near_patch'])} near pairs: E_inf {e:.2e}", flush=True)
         plan.close()
     assert res[(8, 6)] < 6e-9 and res[(8, 8)] < 3e-9 and res[(10, 6)] < 5e-10
+
+
+def test_closed_forms_unit_sphere():
+    """Closed forms on the unit sphere through the whole GPU path (smooth rule + correction):
+    Gauss's identity D[1] = -1 inside, -1/2 on the surface (principal value), 0 outside, and
+    the eigenrelations S[Y_l] = r^l Y_l / (2l+1) inside, Y_l / (2l+1) on the surface and
+    r^-(l+1) Y_l / (2l+1) outside, for the degree-3 harmonic Y_3^2 of the sphere workload.
+    Targets inside and outside at radii 0.5 .. 0.95 and 1.05 .. 1.6 along seeded directions,
+    and the nodes; q = 10 on 216 patches.  Gates: 1e-10 absolute for Gauss's identity and
+    for S off the surface (relative to max |Y|); measured 3e-14 and 4e-12.  On the surface the
+    discretisation of the density sets the error (measured 4e-9), gated at 1e-6."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    n, q = 6, 10
+    surf = wl.discretize(wl.cubed_sphere_patches(n), np.full(6 * n * n, q))
+    x, nn, sp, sn = wl.node_targets(surf)
+    rng = np.random.default_rng(77)
+    m = 400
+    d = rng.normal(size=(3, m))
+    d /= np.linalg.norm(d, axis=0)
+    rad = np.where(np.arange(m) < m // 2, rng.uniform(0.5, 0.95, m), rng.uniform(1.05, 1.6, m))
+    xo = d * rad
+    xyz = np.concatenate([x, xo], axis=1)
+    nrm = np.concatenate([nn, d], axis=1)
+    tg = wl.make_targets(surf, xyz, nrm, np.concatenate([sp, np.full(m, -1, np.int32)]),
+                         np.concatenate([sn, np.full(m, -1, np.int32)]), eta=1.5)
+    N = x.shape[1]
+    Y = lambda p: math.sqrt(7.0 / 120.0) * 15.0 * p[2] * (p[0] ** 2 - p[1] ** 2)
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    ev = rrq.Evaluator(plan, rrq.DeviceTargets(tg), kmask=rrq.RRQ_K_S | rrq.RRQ_K_D)
+    one = np.ones(N)
+    yl = Y(surf["node_xyz"])
+    flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    d1 = (ev.potentials(one, flags=flags)["D"] + ev.smooth(one)["D"]).cpu().numpy()
+    s3 = (ev.potentials(yl, flags=flags)["S"] + ev.smooth(yl)["S"]).cpu().numpy()
+    torch.cuda.synchronize()
+    plan.close()
+    inside = np.arange(m) < m // 2
+    gauss = np.concatenate([np.full(N, -0.5), np.where(inside, -1.0, 0.0)])
+    e_gauss = np.abs(d1 - gauss)
+    r = np.concatenate([np.ones(N), rad])
+    dirs = xyz / r
+    ys = Y(dirs)
+    expect = np.where(r < 1.0, r ** 3, np.where(r > 1.0, r ** -4.0, 1.0)) * ys / 7.0
+    e_s = np.abs(s3 - expect) / np.max(np.abs(yl))
+    print(f"Gauss D[1]: on-surface {e_gauss[:N].max():.2e}, inside {e_gauss[N:][inside].max():.2e}, "
+          f"outside {e_gauss[N:][~inside].max():.2e}; S[Y_3^2]: on-surface {e_s[:N].max():.2e}, "
+          f"off-surface {e_s[N:].max():.2e}")
+    assert e_gauss.max() <= 1e-10
+    assert e_s[N:].max() <= 1e-10
+    assert e_s[:N].max() <= 1e-6
