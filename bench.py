@@ -174,19 +174,29 @@ def cpu_baseline(surf, tg, seconds=20.0, seed=0):
 
 
 def parity_gate(surf, tg, res, gpu_blocks, owner, max_pairs=150, tol=1e-11, ulp_factor=30.0):
-    """Fraction of the sampled pair blocks (the first max_pairs) that pass the weights gate of
-    the parity tests: ||W_gpu - W_or|| <= tol ||W_raw|| + ulp_factor ||dW_ulp||, dW_ulp the
-    largest change of the oracle block under rounding-level perturbations (target moved by
-    one relative ulp, edge samples by one ulp, fits solved by SVD instead of QR)."""
+    """On the sampled pair blocks (the first max_pairs): the fraction that passes the weights
+    gate of the parity tests, ||W_gpu - W_or|| <= tol ||W_raw|| + ulp_factor ||dW_ulp||, dW_ulp
+    the largest change of the oracle block under rounding-level perturbations (target moved by
+    one relative ulp, edge samples by one ulp, fits solved by SVD instead of QR); and, over
+    the same blocks, the max-norm difference GPU - oracle and oracle(SVD) - oracle(QR), both
+    relative to the largest oracle weight."""
     from oracle.assemble import pair_block
     KERNELS = ("S", "D", "Sp", "Dp")
     fits, fits_svd = {}, {}
     ok = {k: 0 for k in KERNELS}
+    dg = {k: 0.0 for k in KERNELS}
+    ds = {k: 0.0 for k in KERNELS}
+    wm = {k: 0.0 for k in KERNELS}
     pairs = sorted(res)[:max_pairs]
     for i in pairs:
         t, P = int(owner[i]), int(tg["near_patch"][i])
         W = res[i]
         raw, _ = pair_block(surf, tg, fits, t, P, False)
+        svd = pair_block(surf, tg, fits_svd, t, P, True, True, "svd")[0]
+        for k in KERNELS:
+            dg[k] = max(dg[k], float(np.max(np.abs(gpu_blocks[i][k] - W[k]))))
+            ds[k] = max(ds[k], float(np.max(np.abs(svd[k] - W[k]))))
+            wm[k] = max(wm[k], float(np.max(np.abs(W[k]))))
         need = [k for k in KERNELS
                 if np.max(np.abs(gpu_blocks[i][k] - W[k])) > tol * np.max(np.abs(raw[k]))]
         for k in KERNELS:
@@ -201,14 +211,14 @@ def parity_gate(surf, tg, res, gpu_blocks, owner, max_pairs=150, tol=1e-11, ulp_
         e = np.array(surf["edge_xyz"], copy=True)
         sg = np.random.default_rng(i).choice([-1.0, 1.0], size=e.shape)
         s2["edge_xyz"] = e * (1.0 + 2.0 ** -52 * sg)
-        pert = (pair_block(surf, tg2, fits, t, P)[0], pair_block(surf, tg, fits_svd, t, P, True,
-                                                                 True, "svd")[0],
-                pair_block(s2, tg, {}, t, P)[0])
+        pert = (pair_block(surf, tg2, fits, t, P)[0], svd, pair_block(s2, tg, {}, t, P)[0])
         for k in need:
             dw = max(np.max(np.abs(pp[k] - W[k])) for pp in pert)
             ok[k] += np.max(np.abs(gpu_blocks[i][k] - W[k])) <= (tol * np.max(np.abs(raw[k]))
                                                                 + ulp_factor * dw)
-    return {k: ok[k] / len(pairs) for k in KERNELS}
+    return {k: {"pairs_within_parity_gate": ok[k] / len(pairs),
+                "global_maxnorm_rel_gpu_vs_oracle": dg[k] / wm[k],
+                "global_maxnorm_rel_oracle_svd_vs_qr": ds[k] / wm[k]} for k in KERNELS}
 
 
 def copy_probe(nbytes=1 << 30, reps=3):
@@ -363,8 +373,8 @@ def main():
                 pot = max(pot, abs((g - W[k]) @ f) / np.sum(np.abs(raw[i][k] * f)))
             acc[k] = {"weights_max_rel_to_raw_block": wrel,
                       "pairs_within_1e-11_of_raw_block": within / len(res),
-                      "potential_max_rel_to_raw_block": pot,
-                      "pairs_within_parity_gate": gate[k]}
+                      "potential_max_rel_to_raw_block": pot}
+            acc[k].update(gate[k])
         cb["gpu_vs_oracle_on_sample"] = acc
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
