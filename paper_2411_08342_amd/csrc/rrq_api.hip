@@ -133,6 +133,8 @@ static rrq_status upload_consts(rrq_plan* p, int q) {
   o.lag_m1 = (const double*)b;
   if (!up(T.bary.data(), T.bary.size() * 8, &b)) return RRQ_ERR_OOM;
   o.bary = (const double*)b;
+  if (!up(T.bary1.data(), T.bary1.size() * 8, &b)) return RRQ_ERR_OOM;
+  o.bary1 = (const double*)b;
   if (!up(T.dlp_ptr.data(), T.dlp_ptr.size() * 4, &b)) return RRQ_ERR_OOM;
   o.dlp_ptr = (const int32_t*)b;
   if (!up(T.dlp.data(), T.dlp.size() * sizeof(Term), &b)) return RRQ_ERR_OOM;

@@ -475,7 +475,7 @@ void k_lambda(PlanDev pd, OrderDev od,
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
     cgl_w[tid] = od.gl_w[tid];
-    cbary[tid] = od.bary[tid];
+    cbary[tid] = od.bary1[tid];
   }
   __syncthreads();
   const int64_t nitems = (int64_t)counters[5];
@@ -535,17 +535,18 @@ void k_lambda(PlanDev pd, OrderDev od,
         leg3r(ecoef, PT, tau, r, dr);
         om += hw * omega0_at(xl, u, r, dr);
       }
-      // Lagrange basis at tau, barycentric form; 1/(tau - t_j) by the hardware reciprocal
-      // and one Newton step (relative error a few ulp, against a correctly rounded divide)
-      double den = 0.0;
+      // Lagrange basis at tau, first barycentric form l_i = ell(tau) b_i / (tau - t_i) with
+      // ell(tau) = prod_j (tau - t_j) (backward stable, and no reciprocal for the
+      // denominator); 1/(tau - t_i) by the hardware reciprocal and one Newton step (relative
+      // error a few ulp, against a correctly rounded divide)
+      double ell = 1.0;
       int hit = -1;
 #pragma unroll
       for (int j = 0; j < PT; ++j) {
         const double dtj = tau - cgl_t[j];
         if (dtj == 0.0) hit = j;
-        else den += cbary[j] * rcp_nr(dtj);
+        ell *= dtj;
       }
-      const double rden = 1.0 / den;
 #pragma unroll
       for (int bI = 0; bI < NB8; ++bI) {
         double x[16];
@@ -555,7 +556,7 @@ void k_lambda(PlanDev pd, OrderDev od,
           double l = 0.0;
           if (i < PT) {
             if (hit >= 0) l = hit == i ? 1.0 : 0.0;
-            else l = cbary[i] * rcp_nr(tau - cgl_t[i]) * rden;
+            else l = cbary[i] * rcp_nr(tau - cgl_t[i]) * ell;
           }
           x[v] = w1p * l;
           x[8 + v] = w3p * l;
@@ -900,11 +901,12 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         const cplx* R = Rt + tt * NR;
         const cplx* G = gS + tt * NR;
         const double* VQ = vq + tt * NJK * 18;
-        cplx Ia[4] = {mk(0, 0), mk(0, 0), mk(0, 0), mk(0, 0)};
-        cplx dIa[4] = {mk(0, 0), mk(0, 0), mk(0, 0), mk(0, 0)};
-        cplx sl = mk(0, 0);
+        // imaginary parts of I[alpha] (quaternion), of its normal derivative and of the
+        // single-layer sum
+        double Ia[4] = {0, 0, 0, 0}, dIa[4] = {0, 0, 0, 0}, sl = 0.0;
         // one pass over the (j, k) terms of this (l, m): single-layer sum (weights D_{j,l})
-        // and double-layer sums (weights C_{j,l}, zero for j = 1)
+        // and double-layer sums (weights C_{j,l}, zero for j = 1); the signs of conjugation
+        // (k < 0) and of S^{(a,b)} for b < 0 are folded into the weights
         int it0 = od.mrg_ptr[lm], it1 = od.mrg_ptr[lm + 1];
         const int mid = (it0 + it1) >> 1;
         if (kind == 1) it1 = mid;
@@ -913,19 +915,19 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
 #pragma unroll 2
         for (int it = it0; it < it1; ++it) {
           const Term2 tm = od.mrg[it];
-          const cplx s_ = rget(R, tm.a, tm.b);
-          const cplx cs = tm.cD * s_;
-          const cplx cg = tm.cD * rget(G, tm.a, tm.b);
+          const cplx s_ = R[tm.r];
+          const cplx g_ = G[tm.r];
+          const double csi = tm.cDi * s_.im, csr = tm.cDr * s_.re;
+          const double cgi = tm.cDi * g_.im, cgr = tm.cDr * g_.re;
           const double* q = VQ + tm.n * 18;
-          cplx V = mk(q[0], q[1]);
-          if (tm.neg) V = conjg(V);
-          cfma(sl, tm.cS * V, s_);
+          sl = fma(tm.cSi * q[0], s_.im, fma(tm.cSr * q[1], s_.re, sl));
+#pragma unroll
           for (int c = 0; c < 4; ++c) {
-            cplx X = mk(q[2 + 2 * c], q[3 + 2 * c]), dX = mk(q[10 + 2 * c], q[11 + 2 * c]);
-            if (tm.neg) { X = conjg(X); dX = conjg(dX); }
-            cfma(Ia[c], X, cs);
-            cfma(dIa[c], dX, cs);
-            cfma(dIa[c], X, cg);
+            const double xr = q[2 + 2 * c], xi = q[3 + 2 * c];
+            const double dxr = q[10 + 2 * c], dxi = q[11 + 2 * c];
+            Ia[c] = fma(xr, csi, fma(xi, csr, Ia[c]));
+            dIa[c] = fma(dxr, csi, fma(dxi, csr, dIa[c]));
+            dIa[c] = fma(xr, cgi, fma(xi, cgr, dIa[c]));
           }
         }
         // first half += second half (the partner lane is idx ^ 1)
@@ -933,10 +935,9 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
           double o;
 #define RRQ_ADD_HALF(v) o = __shfl_xor(v, 1, 64); if (kind == 1) v += o;
           for (int c = 0; c < 4; ++c) {
-            RRQ_ADD_HALF(Ia[c].re) RRQ_ADD_HALF(Ia[c].im)
-            RRQ_ADD_HALF(dIa[c].re) RRQ_ADD_HALF(dIa[c].im)
+            RRQ_ADD_HALF(Ia[c]) RRQ_ADD_HALF(dIa[c])
           }
-          RRQ_ADD_HALF(sl.re) RRQ_ADD_HALF(sl.im)
+          RRQ_ADD_HALF(sl)
 #undef RRQ_ADD_HALF
         }
         if (!act || kind == 2) continue;
@@ -961,10 +962,10 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         dIg[3] = p0 * g[2] + (p1 * g[1] - p2 * g[0]) + o0 * hn[2] + (o1 * hn[1] - o2 * hn[0]);
         double Dq[4], dDq[4];
         for (int c = 0; c < 4; ++c) {
-          Dq[c] = -kSqrt2 * kInv4Pi * (Ia[c].im + Ig[c].im);
-          dDq[c] = -kSqrt2 * kInv4Pi * (dIa[c].im + dIg[c].im);
+          Dq[c] = -kSqrt2 * kInv4Pi * (Ia[c] + Ig[c].im);
+          dDq[c] = -kSqrt2 * kInv4Pi * (dIa[c] + dIg[c].im);
         }
-        const double Psi = kSqrt2 * kInv4Pi * (sl.im - R[tri(l, m)].im * som[t * 4]);
+        const double Psi = kSqrt2 * kInv4Pi * (sl - R[tri(l, m)].im * som[t * 4]);
         const double n0_ = nu[0], n1_ = nu[1], n2_ = nu[2];
         double Eq[4];
         Eq[0] = -(n0_ * Dq[1] + n1_ * Dq[2] + n2_ * Dq[3]);
@@ -1074,30 +1075,31 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             for (int a = 0; a < 2 * TQ; ++a) acc[a] = acc2[a] = 0.0;
             // 8 k-steps per batch: map operands loaded first (8 loads in flight), then the
             // row operands and MFMAs of every accumulator, alternating between two partial
-            // sums so that consecutive MFMAs do not wait on each other
+            // sums so that consecutive MFMAs do not wait on each other.  Loads are
+            // unconditional, at clamped indices: the map operand is then zeroed past row KR
+            // (so the clamped row entries there add exact zeros), and rows of targets past
+            // nt read target 0's row (row m of the product depends on row m of A only, and
+            // those rows are not stored).
             for (int kb = 0; kb < KR; kb += 32) {
               double bv[8];
 #pragma unroll
               for (int u = 0; u < 8; ++u) {
                 const int k = kb + 4 * u + kr;
-                bv[u] = (bval && k < KR) ? M[k * Q2 + bcol] : 0.0;
+                const double b = M[min(k, KR - 1) * Q2 + min(bcol, Q2 - 1)];
+                bv[u] = (bval && k < KR) ? b : 0.0;
               }
 #pragma unroll
               for (int a = 0; a < 2 * TQ; ++a) {
                 if (a >= NA) break;
-                const int t = (a % TQ) * 4 + am;
-                const double* rowp = nullptr;
-                if (t < nt) {
-                  if (grp == 0) rowp = a < TQ ? rows + t * 4 * NP : rows + T * 13 * NP + t * 4 * NP;
-                  else if (grp == 1) rowp = rows + T * 4 * NP + t * 4 * NP;
-                  else rowp = rows + T * 8 * NP + t * 5 * NP;
-                }
+                int t = (a % TQ) * 4 + am;
+                if (t >= nt) t = 0;
+                const double* rowp;
+                if (grp == 0) rowp = a < TQ ? rows + t * 4 * NP : rows + T * 13 * NP + t * 4 * NP;
+                else if (grp == 1) rowp = rows + T * 4 * NP + t * 4 * NP;
+                else rowp = rows + T * 8 * NP + t * 5 * NP;
                 double av[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                  const int k = kb + 4 * u + kr;
-                  av[u] = (rowp != nullptr && k < KR) ? rowp[k] : 0.0;
-                }
+                for (int u = 0; u < 8; ++u) av[u] = rowp[min(kb + 4 * u + kr, KR - 1)];
 #pragma unroll
                 for (int u = 0; u < 8; u += 2) {
                   acc[a] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[u], bv[u], acc[a], 0, 0, 0);

@@ -121,6 +121,14 @@ OrderTables build_order_tables(int q, int pt) {
     long double ti = T.gl_t[i];
     T.bary[i] = (double)((i & 1 ? -1.0L : 1.0L) * sqrtl((1 - ti * ti) * (long double)T.gl_w[i]));
   }
+  // first barycentric form: l_i(t) = ell(t) bary1_i / (t - t_i), ell(t) = prod_j (t - t_j)
+  T.bary1.assign(pt, 0.0);
+  for (int i = 0; i < pt; ++i) {
+    long double pr = 1.0L;
+    for (int j = 0; j < pt; ++j)
+      if (j != i) pr *= (long double)T.gl_t[i] - (long double)T.gl_t[j];
+    T.bary1[i] = (double)(1.0L / pr);
+  }
 
   // translation terms, grouped by basis function (l, m), 1 <= m <= l <= q
   T.dlp_ptr.assign(1, 0);
@@ -158,19 +166,23 @@ OrderTables build_order_tables(int q, int pt) {
     int d = T.dlp_ptr[lm];
     for (int s = T.slp_ptr[lm]; s < T.slp_ptr[lm + 1]; ++s) {
       const Term& ts = T.slp[s];
-      Term2 t2;
-      t2.n = ts.n;
-      t2.a = ts.a;
-      t2.b = ts.b;
-      t2.neg = ts.neg;
-      t2.pad = 0;
-      t2.cS = ts.coef;
-      t2.cD = 0.0;
+      double cD = 0.0;
       if (d < T.dlp_ptr[lm + 1] && T.dlp[d].n == ts.n && T.dlp[d].a == ts.a &&
           T.dlp[d].b == ts.b && T.dlp[d].neg == ts.neg) {
-        t2.cD = T.dlp[d].coef;
+        cD = T.dlp[d].coef;
         ++d;
       }
+      const int ab = std::abs((int)ts.b);
+      const double sr = (ts.b < 0 && (ab & 1)) ? -1.0 : 1.0;
+      const double si = (ts.b < 0 && !(ab & 1)) ? -1.0 : 1.0;
+      const double nu = ts.neg ? -1.0 : 1.0;
+      Term2 t2;
+      t2.n = ts.n;
+      t2.r = ts.a * (ts.a + 1) / 2 + ab;
+      t2.cDr = cD * sr * nu;
+      t2.cDi = cD * si;
+      t2.cSr = ts.coef * sr * nu;
+      t2.cSi = ts.coef * si;
       T.mrg.push_back(t2);
     }
     T.mrg_ptr.push_back((int32_t)T.mrg.size());

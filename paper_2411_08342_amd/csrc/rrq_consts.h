@@ -24,14 +24,18 @@ struct Term {
 };
 
 // one term of the merged translation sum over the (j, k) index set of the single-layer sum;
-// the double-layer weight cD is zero for j = 1
+// the double-layer weight (cDr, cDi) is zero for j = 1.  Only imaginary parts of the sums
+// are used (eq. wlmdef takes Im), so a term contributes Im(X' c S') with X' = X^{(j,|k|)},
+// conjugated for k < 0, and S' = S^{(a,b)} = +-S^{(a,|b|)} or its conjugate for b < 0
+// (rget).  Both sign patterns are folded into the weights: with s = S^{(a,|b|)},
+//   Im(X' c S') = X.re (c_i s.im) + X.im (c_r s.re),  c_i = c sigma_i, c_r = c sigma_r nu,
+// nu = -1 for k < 0, (sigma_r, sigma_i) = (1, 1) for b >= 0, (-1, 1) for odd b < 0,
+// (1, -1) for even b < 0.  Every sign is exact, so the sums round as the unfolded form.
 struct Term2 {
-  int32_t n;
-  int16_t a, b;
-  int32_t neg;
-  int32_t pad;
-  double cD;      // C_{j,l} T_{jk,lm} (sign for k < 0 included)
-  double cS;      // D_{j,l} T_{jk,lm} (sign for k < 0 included)
+  int32_t n;      // index of (j, |k|) in the jk table
+  int32_t r;      // index tri(a, |b|) of S^{(a,|b|)} in the target tables
+  double cDr, cDi;  // C_{j,l} T_{jk,lm} (sign for k < 0 included), folded as above
+  double cSr, cSi;  // D_{j,l} T_{jk,lm} (sign for k < 0 included), folded as above
 };
 
 struct OrderTables {
@@ -43,6 +47,7 @@ struct OrderTables {
   std::vector<double> DP;             // [pt][pt]: DP[i*pt + k] = P_k'(t_i)
   std::vector<double> lag_m1;         // l_i(-1)
   std::vector<double> bary;           // barycentric weights (-1)^i sqrt((1 - t_i^2) w_i)
+  std::vector<double> bary1;          // first-form weights 1 / prod_{j != i} (t_i - t_j)
   std::vector<int32_t> dlp_ptr, slp_ptr;   // [np+1]
   std::vector<Term> dlp, slp;
   std::vector<int32_t> mrg_ptr;        // [np+1]

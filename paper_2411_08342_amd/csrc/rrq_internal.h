@@ -20,6 +20,7 @@ struct OrderDev {
   const double* DP;         // Legendre derivatives at the GL nodes
   const double* lag_m1;
   const double* bary;       // barycentric weights of the ptilde GL nodes
+  const double* bary1;      // first-form weights 1 / prod_{j != i} (t_i - t_j)
   const int32_t* dlp_ptr;
   const Term* dlp;
   const int32_t* slp_ptr;
