@@ -142,17 +142,31 @@ __device__ __forceinline__ void leg3r(const double* coef, int n, double t, doubl
   }
 }
 
+// An opaque copy of a value: the compiler must assume it changed.  The tile kernel uses it
+// so that per-lane addresses are recomputed in each phase instead of being kept live (and
+// spilled) from the start of the tile.
+template <typename V>
+__device__ __forceinline__ V fresh(V v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Sum over the 64 lanes of x[v], v = 0..15, returned in lane l for v = (l >> 2) & 15
 // (a reduce-scatter: 17 exchanges instead of 16 full reductions).  x is overwritten.
 __device__ __forceinline__ double reduce_scatter16(double* x) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int w = 8, o = 32; w >= 1; w >>= 1, o >>= 1) {
+  for (int s = 0; s < 4; ++s) {
+    const int w = 8 >> s, o = 32 >> s;
     const bool hi = lane & o;
 #pragma unroll
     for (int j = 0; j < w; ++j) {
-      const double send = hi ? x[j] : x[w + j];
-      const double keep = hi ? x[w + j] : x[j];
+      // selects between two values: the opaque copies keep the compiler from turning
+      // them into one load at a lane-dependent index of x[] (a select chain over the
+      // whole array)
+      const double lo_v = fresh(x[j]), hi_v = fresh(x[w + j]);
+      const double send = hi ? lo_v : hi_v;
+      const double keep = hi ? hi_v : lo_v;
       x[j] = keep + __shfl_xor(send, o, 64);
     }
   }
@@ -394,15 +408,6 @@ hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* o
 // ---------------------------------------------------------------------------------------
 // LDS layout of one tile (doubles, then ints)
 // ---------------------------------------------------------------------------------------
-// An opaque copy of a value: the compiler must assume it changed, so the per-lane
-// addresses derived from it are recomputed in each phase of the tile kernel instead of being
-// kept live (and spilled) from the start of the tile.
-template <typename V>
-__device__ __forceinline__ V fresh(V v) {
-  asm volatile("" : "+v"(v));
-  return v;
-}
-
 // One wave: local coordinates xl and normal nl of a target in the frame fr of a patch whose
 // nodes start at n0, and the vector u of the solid-angle integrand: the target normal for a
 // self target, else the normal of the nearest node (lowest index on ties, wave argmin)
@@ -912,7 +917,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         if (kind == 1) it1 = mid;
         else if (kind == 2) it0 = mid;
         if (!act) it1 = it0;
-#pragma unroll 2
+#pragma unroll 1
         for (int it = it0; it < it1; ++it) {
           const Term2 tm = od.mrg[it];
           const cplx s_ = R[tm.r];
