@@ -207,8 +207,9 @@ rrq_status rrq_autotune(rrq_plan* plan, const rrq_targets* tg, uint32_t kmask, u
 
 /* One whole assembly step (rrq_plan_refit, rrq_pair_offsets, rrq_assemble with the given
  * arguments) captured into a HIP graph; rrq_graph_launch replays it on `stream`.  In the
- * graph the maps and edge tables (needed only by the tile kernels) run on a branch of their
- * own beside the pair offsets, binning and pre-passes, joined before the tile kernels.  The
+ * graph the fits (the maps, needed only by the tile kernels) run on a branch of their own
+ * beside the edge tables, pair offsets, binning and pre-passes, joined before the tile
+ * kernels.  The
  * graph holds the pointers it was created with: the buffers must stay allocated and the
  * sizes unchanged until rrq_graph_destroy; their contents (surface, targets) may change
  * between replays.  Nothing in the captured step allocates memory or issues memset/memcpy

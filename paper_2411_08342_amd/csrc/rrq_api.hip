@@ -183,7 +183,7 @@ __global__ void k_copy3(const double* a, const double* b, const double* c, doubl
 
 // Source-only data in two parts: the geometry (frames, local nodes, edge interpolants), which
 // the root and near-edge pre-passes need, and the maps and edge tables, which only the tile
-// kernels need (a captured step runs the second part beside the pre-passes).
+// kernels need (a captured step runs the fits beside the edge tables and the pre-passes).
 static rrq_status run_geometry(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
   // plan copies of the smooth-rule data used by the correction (a kernel, not a memcpy, so
   // that the step can be captured into a graph)
@@ -208,19 +208,32 @@ static rrq_status run_geometry(rrq_plan* p, const rrq_surface* s, hipStream_t st
   return RRQ_OK;
 }
 
-static rrq_status run_maps(rrq_plan* p, hipStream_t st) {
+static rrq_status run_edge_tables(rrq_plan* p, hipStream_t st) {
   PlanDev pd = p->dev();
   for (int qi = 0; qi < kNumOrders; ++qi) {
     const int q = kOrders[qi];
     const int cnt = (int)p->patches_h[q].size();
-    if (!cnt) continue;
-    if (launch_edge_tables(pd, p->od[q], p->patches_d[q], cnt, st) != hipSuccess)
-      return RRQ_ERR_DEVICE;
-    if (launch_fit(pd, p->od[q], p->patches_d[q], cnt, p->fit_ws_d, p->fit_ws_per_block,
-                   p->fit_blocks, st) != hipSuccess)
+    if (cnt && launch_edge_tables(pd, p->od[q], p->patches_d[q], cnt, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
   }
   return RRQ_OK;
+}
+
+static rrq_status run_fits(rrq_plan* p, hipStream_t st) {
+  PlanDev pd = p->dev();
+  for (int qi = 0; qi < kNumOrders; ++qi) {
+    const int q = kOrders[qi];
+    const int cnt = (int)p->patches_h[q].size();
+    if (cnt && launch_fit(pd, p->od[q], p->patches_d[q], cnt, p->fit_ws_d, p->fit_ws_per_block,
+                          p->fit_blocks, st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+  }
+  return RRQ_OK;
+}
+
+static rrq_status run_maps(rrq_plan* p, hipStream_t st) {
+  const rrq_status r = run_edge_tables(p, st);
+  return r == RRQ_OK ? run_fits(p, st) : r;
 }
 
 static rrq_status run_fit(rrq_plan* p, const rrq_surface* s, hipStream_t st) {
@@ -557,7 +570,7 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       ao.lamg = lamg;
       ao.lam_stride = lam_stride;
     }
-    // the maps and edge tables may still be in flight on another stream (captured step)
+    // the maps may still be in flight on another stream (captured step)
     if (maps_ready && hipStreamWaitEvent(st, maps_ready, 0) != hipSuccess) return RRQ_ERR_DEVICE;
     if (pot && launch_patch_coef(pd, density, (double*)(wb + wl.pcoef), st) != hipSuccess)
       return RRQ_ERR_DEVICE;
@@ -895,8 +908,8 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
     (void)hipStreamDestroy(cs);
     return RRQ_ERR_DEVICE;
   }
-  // captured step: geometry, then the maps and edge tables on a second stream beside the pair
-  // offsets, binning and pre-passes; the tile kernels wait for them
+  // captured step: geometry, then the fits (maps) on a second stream beside the edge tables,
+  // pair offsets, binning and pre-passes; the tile kernels wait for them
   hipStream_t ms = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   bool ok = hipStreamCreateWithFlags(&ms, hipStreamNonBlocking) == hipSuccess &&
@@ -906,8 +919,9 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   if (r == RRQ_OK && (hipEventRecord(fork, cs) != hipSuccess ||
                       hipStreamWaitEvent(ms, fork, 0) != hipSuccess))
     r = RRQ_ERR_DEVICE;
-  if (r == RRQ_OK) r = run_maps(p, ms);
+  if (r == RRQ_OK) r = run_fits(p, ms);
   if (r == RRQ_OK && hipEventRecord(join, ms) != hipSuccess) r = RRQ_ERR_DEVICE;
+  if (r == RRQ_OK) r = run_edge_tables(p, cs);
   if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, workspace, workspace_bytes, nullptr, cs);
   if (r == RRQ_OK) {
     double* outs[4] = {out_S, out_D, out_Sp, out_Dp};

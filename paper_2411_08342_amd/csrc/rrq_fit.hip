@@ -198,15 +198,18 @@ __global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
 //  - its reflectors H_1 ... H_nb = I - V T V^T are applied to every later column in one pass
 //    (C <- C - V T^T V^T C, one column per thread, loads issued 8 rows ahead);
 //  - the right-hand sides are then solved with R by column sweeps, kBackCols columns at a
-//    time held in LDS.
+//    time held in LDS, with the columns of R staged in LDS kRC at a time.
 // On exit the right-hand-side columns hold the solution in rows 0..n-1.
-// LDS: V [m][HNB], T [HNB][HNB], G [HNB][HNB], beta [HNB], alpha [HNB], X [n][kBackCols].
+// LDS: V [m][HNB], T [HNB][HNB], G [HNB][HNB], beta [HNB], alpha [HNB], X [n][kBackCols],
+// Rs [kRC][rs] (rs >= n).
 // ---------------------------------------------------------------------------------------
 constexpr int HNB = 8;
 constexpr int kBackCols = 32;
+constexpr int kRB = 8;   // rows per thread in the map products
+constexpr int kRC = 16;  // columns of R staged in LDS per chunk of the back substitution
 
 __device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, double* T,
-                       double* G, double* beta, double* alpha, double* X) {
+                       double* G, double* beta, double* alpha, double* X, double* Rs, int rs) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int k0 = 0; k0 < n; k0 += HNB) {
     const int nb = min(HNB, n - k0);
@@ -370,16 +373,30 @@ __device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int l
       const int r = idx / kBackCols, jj = idx % kBackCols;
       X[idx] = jj < cw ? A[(int64_t)r * ld + j0 + jj] : 0.0;
     }
-    __syncthreads();
-    for (int c = n - 1; c >= 0; --c) {
-      if (tid < kBackCols) X[c * kBackCols + tid] /= A[(int64_t)c * ld + c];
-      __syncthreads();
-      for (int idx = tid; idx < c * kBackCols; idx += NT) {
-        const int r = idx / kBackCols, jj = idx % kBackCols;
-        X[idx] -= A[(int64_t)r * ld + c] * X[c * kBackCols + jj];
+    // columns of R are staged in LDS kRC at a time (one barrier and one round of loads per
+    // chunk); per column every thread divides its right-hand side's entry itself (the same
+    // quotient in every thread of that column), updates its rows r < c, and after the
+    // column's barrier one thread per right-hand side stores the quotient in row c
+    const int jj = tid % kBackCols;
+    double xc = 0.0;
+    for (int cb = n; cb > 0; cb -= kRC) {
+      const int clo = max(0, cb - kRC), nc = cb - clo;
+      for (int idx = tid; idx < cb * nc; idx += NT) {
+        const int r = idx / nc, cc = idx % nc;
+        Rs[cc * rs + r] = A[(int64_t)r * ld + clo + cc];
       }
       __syncthreads();
+      if (cb < n && tid < kBackCols) X[cb * kBackCols + tid] = xc;
+      for (int c = cb - 1; c >= clo; --c) {
+        const double* Rc = Rs + (c - clo) * rs;
+        xc = X[c * kBackCols + jj] / Rc[c];
+        for (int idx = tid; idx < c * kBackCols; idx += NT) X[idx] -= Rc[idx / kBackCols] * xc;
+        __syncthreads();
+        if (c > clo && tid < kBackCols) X[c * kBackCols + tid] = xc;
+      }
     }
+    if (tid < kBackCols) X[tid] = xc;
+    __syncthreads();
     for (int idx = tid; idx < n * kBackCols; idx += NT) {
       const int r = idx / kBackCols, jj = idx % kBackCols;
       if (jj < cw) A[(int64_t)r * ld + j0 + jj] = X[idx];
@@ -415,6 +432,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   constexpr int LDB = NP + Q2;
   __shared__ double sV[M * HNB];
   __shared__ double sX[4 * NP * kBackCols];
+  __shared__ double sR[kRC * 4 * NP];
   __shared__ double sT[HNB * HNB], sG[HNB * HNB], sbeta[HNB], salpha[HNB];
   double* A = ws + (int64_t)blockIdx.x * ws_per_block;
   double* B = A + (int64_t)M * LDA;
@@ -460,8 +478,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       B[(int64_t)i * LDB + NP + i] = om;
     }
     __syncthreads();
-    hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sT, sG, sbeta, salpha, sX);
-    hh_lsq(B, Q2, NP, LDB, LDB, sV, sT, sG, sbeta, salpha, sX);
+    hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
+    hh_lsq(B, Q2, NP, LDB, LDB, sV, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
     // condition estimate of each fit: max|R_ii| / min|R_ii| (a lower bound of the 2-norm
     // condition number of the weighted system), on wave 0 by lane reductions
     if (tid < 64) {
@@ -499,20 +517,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const int r = idx / Q2, j = idx % Q2;
       MS[idx] = B[(int64_t)r * LDB + NP + j];
     }
-    // T1 = Hmat (Q2 x NP) * B^+ (NP x Q2)
-    for (int idx = tid; idx < Q2 * Q2; idx += NT) {
-      const int i = idx / Q2, j = idx % Q2;
-      double acc = 0.0;
-      for (int n = 0; n < NP; ++n) acc += Hm[i * NP + n] * B[(int64_t)n * LDB + NP + j];
-      T1[idx] = acc;
+    // T1 = Hmat (Q2 x NP) * B^+ (NP x Q2), kept in LDS (the back-substitution buffer, free
+    // now) where it fits.  Both products: one column j per lane and kRB rows per thread, so
+    // that every loaded operand feeds kRB (or, for the row operand, one per row) FMAs; each
+    // output is still one FMA chain in the order of the sum.
+    constexpr bool kT1Lds = Q2 * Q2 <= 4 * NP * kBackCols;
+    double* T1p = kT1Lds ? sX : T1;
+    for (int it = tid; it < ((Q2 + kRB - 1) / kRB) * Q2; it += NT) {
+      const int i0 = (it / Q2) * kRB, j = it % Q2;
+      double acc[kRB];
+#pragma unroll
+      for (int u = 0; u < kRB; ++u) acc[u] = 0.0;
+      for (int n = 0; n < NP; ++n) {
+        const double b = B[(int64_t)n * LDB + NP + j];
+#pragma unroll
+        for (int u = 0; u < kRB; ++u)
+          if (i0 + u < Q2) acc[u] = fma(Hm[(i0 + u) * NP + n], b, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kRB; ++u)
+        if (i0 + u < Q2) T1p[(i0 + u) * Q2 + j] = acc[u];
     }
     __syncthreads();
     // M_S lower block = M_D * T1 ; M_Sp column j = (M_D column j) (0, nu_j)
-    for (int idx = tid; idx < 4 * NP * Q2; idx += NT) {
-      const int r = idx / Q2, j = idx % Q2;
-      double acc = 0.0;
-      for (int i = 0; i < Q2; ++i) acc += A[(int64_t)r * LDA + 4 * NP + i] * T1[i * Q2 + j];
-      MS[NP * Q2 + idx] = acc;
+    for (int it = tid; it < ((4 * NP + kRB - 1) / kRB) * Q2; it += NT) {
+      const int r0 = (it / Q2) * kRB, j = it % Q2;
+      double acc[kRB];
+#pragma unroll
+      for (int u = 0; u < kRB; ++u) acc[u] = 0.0;
+      for (int i = 0; i < Q2; ++i) {
+        const double t = T1p[i * Q2 + j];
+#pragma unroll
+        for (int u = 0; u < kRB; ++u)
+          if (r0 + u < 4 * NP) acc[u] = fma(A[(int64_t)(r0 + u) * LDA + 4 * NP + i], t, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kRB; ++u)
+        if (r0 + u < 4 * NP) MS[NP * Q2 + (r0 + u) * Q2 + j] = acc[u];
     }
     for (int idx = tid; idx < NP * Q2; idx += NT) {
       const int lm = idx / Q2, j = idx % Q2;
