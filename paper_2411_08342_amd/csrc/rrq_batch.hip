@@ -853,16 +853,27 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         double V0 = 0, V1 = 0;
         double Qr[4] = {0, 0, 0, 0}, Qi[4] = {0, 0, 0, 0};
         double Dr[4] = {0, 0, 0, 0}, Di[4] = {0, 0, 0, 0};
-        for (int e = 0; e < 4; ++e)
-#pragma unroll 4
-          for (int i = 0; i < PT; ++i) {
-            const double* o = tb + (((int64_t)e * PT + i) * NJK + n) * 12;
-            const double* tdp = td + ((t * 4 + e) * PT + i) * 8;
+        // the 4 PT edge points in order (edge-major); the table entries of the next point are
+        // loaded before this point's products, so that their latency overlaps them
+        constexpr int NPTS = 4 * PT;
+        const double* ob = tb + (int64_t)n * 12;
+        const double* tdb = td + t * NPTS * 8;
+        double cur[12];
+#pragma unroll
+        for (int u = 0; u < 12; ++u) cur[u] = ob[u];
+#pragma unroll 2
+        for (int p = 0; p < NPTS; ++p) {
+          const double* onx = ob + (int64_t)min(p + 1, NPTS - 1) * NJK * 12;
+          double nx[12];
+#pragma unroll
+          for (int u = 0; u < 12; ++u) nx[u] = onx[u];
+          {
+            const double* tdp = tdb + p * 8;
             const double w1 = tdp[0];
             const double d0 = tdp[1], d1 = tdp[2], d2 = tdp[3];
             const double a0 = tdp[4], a1 = tdp[5], a2 = tdp[6];
-            const double c0r = o[0], c0i = o[1], c1r = o[2], c1i = o[3], c2r = o[4], c2i = o[5];
-            const double h0r = o[6], h0i = o[7], h1r = o[8], h1i = o[9], h2r = o[10], h2i = o[11];
+            const double c0r = cur[0], c0i = cur[1], c1r = cur[2], c1i = cur[3], c2r = cur[4], c2i = cur[5];
+            const double h0r = cur[6], h0i = cur[7], h1r = cur[8], h1i = cur[9], h2r = cur[10], h2i = cur[11];
             // every product is accumulated with its own FMA (no temporary sums)
             const double v0 = w1 * d0, v1 = w1 * d1, v2 = w1 * d2;
             V0 = fma(v0, c0r, fma(v1, c1r, fma(v2, c2r, V0)));
@@ -884,6 +895,9 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             Dr[3] = fma(a0, h1r, fma(-a1, h0r, Dr[3]));
             Di[3] = fma(a0, h1i, fma(-a1, h0i, Di[3]));
           }
+#pragma unroll
+          for (int u = 0; u < 12; ++u) cur[u] = nx[u];
+        }
         double* o = vq + (t * NJK + n) * 18;
         o[0] = V0; o[1] = V1;
         for (int c = 0; c < 4; ++c) {
