@@ -322,7 +322,9 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
     if (ok) ok &= hipMemcpy(p->perm_d, perm.data(), perm.size() * 4, hipMemcpyHostToDevice) ==
                   hipSuccess;
   }
-  p->fit_blocks = std::min(p->P, 512);
+  // persistent fit workgroups: fewer than two per CU, so that in a captured step the kernels
+  // of the other branch (edge tables, binning, pre-passes) find room beside them
+  p->fit_blocks = std::min(p->P, 384);
   p->fit_ws_per_block = maxws;
   ok &= dalloc(&p->fit_ws_d, (size_t)maxws * p->fit_blocks) == hipSuccess;
   ok &= dalloc(&p->fitcond_d, 2 * (size_t)p->P) == hipSuccess;
