@@ -28,11 +28,6 @@ __device__ __forceinline__ double rcp_nr(double d) {
   const double r = __builtin_amdgcn_rcp(d);
   return fma(r, fma(-d, r, 1.0), r);
 }
-// acc += a b with one FMA per real product
-__device__ __forceinline__ void cfma(cplx& acc, cplx a, cplx b) {
-  acc.re = fma(a.re, b.re, fma(-a.im, b.im, acc.re));
-  acc.im = fma(a.re, b.im, fma(a.im, b.re, acc.im));
-}
 __device__ __forceinline__ cplx conjg(cplx a) { return {a.re, -a.im}; }
 __device__ __forceinline__ double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
 __device__ __forceinline__ double cabsd(cplx a) { return sqrt(a.re * a.re + a.im * a.im); }
