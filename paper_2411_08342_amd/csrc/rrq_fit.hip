@@ -206,62 +206,72 @@ __global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
 constexpr int HNB = 8;
 constexpr int kBackCols = 32;
 constexpr int kRB = 8;   // rows per thread in the map products
-constexpr int kRC = 16;  // columns of R staged in LDS per chunk of the back substitution
+constexpr int kRC = 8;   // columns of R staged in LDS per chunk of the back substitution
 
-__device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V, double* T,
-                       double* G, double* beta, double* alpha, double* X, double* Rs, int rs) {
+// Householder reflectors of one panel held in LDS (mr rows, nb <= HNB columns, row stride HNB),
+// by wave 0: lane l owns the rows r = l mod 64; reductions by lane exchanges.  On exit the
+// panel holds R above the diagonal and the reflectors below it; beta and alpha per column.
+__device__ __forceinline__ void hh_panel(double* V, int mr, int nb, double* beta, double* alpha) {
+  const int lane = threadIdx.x & 63;
+    for (int c = 0; c < nb; ++c) {
+      double part = 0.0;
+      for (int r = lane; r < mr; r += 64)
+        if (r >= c) {
+          const double a = V[r * HNB + c];
+          part += a * a;
+        }
+      const double nrm2 = wave_sum(part);
+      const double akk = V[c * HNB + c];
+      const double nrm = sqrt(nrm2);
+      const double al = akk >= 0.0 ? -nrm : nrm;
+      const double vtv = 2.0 * nrm * (nrm + fabs(akk));
+      const double be = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      // w_j = v . V[:, j]; only c < j < nb are used (the others get 0: unchanged)
+      double w[HNB];
+#pragma unroll
+      for (int j = 0; j < HNB; ++j) w[j] = 0.0;
+      for (int r = lane; r < mr; r += 64)
+        if (r >= c) {
+          const double vr = r == c ? akk - al : V[r * HNB + c];
+#pragma unroll
+          for (int j = 0; j < HNB; ++j) w[j] += vr * V[r * HNB + j];
+        }
+#pragma unroll
+      for (int j = 0; j < HNB; ++j) w[j] = (j > c && j < nb) ? be * wave_sum(w[j]) : 0.0;
+      for (int r = lane; r < mr; r += 64)
+        if (r >= c) {
+          const double vr = r == c ? akk - al : V[r * HNB + c];
+#pragma unroll
+          for (int j = 0; j < HNB; ++j) V[r * HNB + j] -= w[j] * vr;
+          if (r == c) V[r * HNB + c] = vr;
+        }
+      if (lane == 0) {
+        beta[c] = be;
+        alpha[c] = al;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+__device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int ld, double* V0,
+                                       double* V1, double* T, double* G, double* beta,
+                                       double* alpha, double* X, double* Rs, int rs) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int k0 = 0; k0 < n; k0 += HNB) {
+  // the first panel; every later one is updated and factorised one step ahead (below)
+  for (int idx = tid; idx < m * HNB; idx += NT) {
+    const int r = idx / HNB, c = idx % HNB;
+    V0[idx] = c < min(HNB, n) ? A[(int64_t)r * ld + c] : 0.0;
+  }
+  __syncthreads();
+  if (wv == 0) hh_panel(V0, m, min(HNB, n), beta, alpha);
+  __syncthreads();
+  for (int k0 = 0, p = 0; k0 < n; k0 += HNB, ++p) {
+    double* V = (p & 1) ? V1 : V0;    // this panel, factorised
+    double* Vn = (p & 1) ? V0 : V1;   // the next one
     const int nb = min(HNB, n - k0);
     const int mr = m - k0;
-    for (int idx = tid; idx < mr * HNB; idx += NT) {
-      const int r = idx / HNB, c = idx % HNB;
-      V[idx] = c < nb ? A[(int64_t)(k0 + r) * ld + k0 + c] : 0.0;
-    }
-    __syncthreads();
-    if (wv == 0) {
-      for (int c = 0; c < nb; ++c) {
-        double part = 0.0;
-        for (int r = lane; r < mr; r += 64)
-          if (r >= c) {
-            const double a = V[r * HNB + c];
-            part += a * a;
-          }
-        const double nrm2 = wave_sum(part);
-        const double akk = V[c * HNB + c];
-        const double nrm = sqrt(nrm2);
-        const double al = akk >= 0.0 ? -nrm : nrm;
-        const double vtv = 2.0 * nrm * (nrm + fabs(akk));
-        const double be = vtv > 0.0 ? 2.0 / vtv : 0.0;
-        // w_j = v . V[:, j]; only c < j < nb are used (the others get 0: unchanged)
-        double w[HNB];
-#pragma unroll
-        for (int j = 0; j < HNB; ++j) w[j] = 0.0;
-        for (int r = lane; r < mr; r += 64)
-          if (r >= c) {
-            const double vr = r == c ? akk - al : V[r * HNB + c];
-#pragma unroll
-            for (int j = 0; j < HNB; ++j) w[j] += vr * V[r * HNB + j];
-          }
-#pragma unroll
-        for (int j = 0; j < HNB; ++j) w[j] = (j > c && j < nb) ? be * wave_sum(w[j]) : 0.0;
-        for (int r = lane; r < mr; r += 64)
-          if (r >= c) {
-            const double vr = r == c ? akk - al : V[r * HNB + c];
-#pragma unroll
-            for (int j = 0; j < HNB; ++j) V[r * HNB + j] -= w[j] * vr;
-            if (r == c) V[r * HNB + c] = vr;
-          }
-        if (lane == 0) {
-          beta[c] = be;
-          alpha[c] = al;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    }
-    __syncthreads();
     // R of the panel back to A (strict upper part from V, diagonal alpha); then V keeps only
     // the reflectors (zero above the diagonal)
     for (int idx = tid; idx < nb * nb; idx += NT) {
@@ -313,8 +323,61 @@ __device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int l
       for (int i = 0; i < HNB; ++i) T[j * HNB + i] = trow[i];
     }
     __syncthreads();
-    // trailing update of every later column: C <- C - V T^T V^T C, one column per thread
-    for (int j = k0 + nb + tid; j < ncols; j += NT) {
+    // Look-ahead: wave 0 applies this panel's reflectors to the next panel's columns and
+    // factorises that panel while waves 1-3 update the other later columns.  Every column is
+    // updated with the same operations in the same order either way.
+    const int k1 = k0 + nb;
+    const bool ahead = k1 < n;
+    if (ahead && wv == 0) {
+      const int nb1 = min(HNB, n - k1);
+      const int jj = lane >> 3, cc = lane & 7;   // next-panel column jj; reflector / row group cc
+      const int j = k1 + jj;
+      // w_cc of column j: one FMA chain over the rows in order
+      double w = 0.0;
+      if (jj < nb1) {
+        int r = 0;
+        for (; r + 8 <= mr; r += 8) {
+          double a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(k0 + r + u) * ld + j];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) w = fma(V[(r + u) * HNB + cc], a[u], w);
+        }
+        for (; r < mr; ++r) w = fma(V[r * HNB + cc], A[(int64_t)(k0 + r) * ld + j], w);
+      }
+      double wl[HNB];
+#pragma unroll
+      for (int l = 0; l < HNB; ++l) wl[l] = __shfl(w, (lane & ~7) | l, 64);
+      // T is upper triangular: the terms l > cc add exact zeros
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < HNB; ++l) acc = fma(T[l * HNB + cc], wl[l], acc);
+      double wt[HNB];
+#pragma unroll
+      for (int c = 0; c < HNB; ++c) wt[c] = __shfl(acc, (lane & ~7) | c, 64);
+      // rows r = cc mod 8 of column j: rows of this panel are R entries (back to A), the rest
+      // become the next panel (zero columns past nb1)
+      if (jj < nb1) {
+        for (int r = cc; r < mr; r += 8) {
+          double acc2 = 0.0;
+#pragma unroll
+          for (int c = 0; c < HNB; ++c) acc2 = fma(V[r * HNB + c], wt[c], acc2);
+          const double v = A[(int64_t)(k0 + r) * ld + j] - acc2;
+          if (r < nb) A[(int64_t)(k0 + r) * ld + j] = v;
+          else Vn[(r - nb) * HNB + jj] = v;
+        }
+      } else {
+        for (int r = nb + cc; r < mr; r += 8) Vn[(r - nb) * HNB + jj] = 0.0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      hh_panel(Vn, mr - nb, nb1, beta, alpha);
+    }
+    // trailing update of the other later columns: C <- C - V T^T V^T C, one column per thread
+    const int jbeg = ahead ? k1 + min(HNB, n - k1) : k1;
+    const int tj = ahead ? tid - 64 : tid, tstep = ahead ? NT - 64 : NT;
+    for (int j = jbeg + tj; tj >= 0 && j < ncols; j += tstep) {
       double w[HNB];
 #pragma unroll
       for (int c = 0; c < HNB; ++c) w[c] = 0.0;
@@ -430,7 +493,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   constexpr int M = 4 * Q2;
   constexpr int LDA = 4 * NP + Q2;
   constexpr int LDB = NP + Q2;
-  __shared__ double sV[M * HNB];
+  __shared__ double sV[2 * M * HNB];   // two panel buffers (look-ahead)
   __shared__ double sX[4 * NP * kBackCols];
   __shared__ double sR[kRC * 4 * NP];
   __shared__ double sT[HNB * HNB], sG[HNB * HNB], sbeta[HNB], salpha[HNB];
@@ -478,8 +541,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       B[(int64_t)i * LDB + NP + i] = om;
     }
     __syncthreads();
-    hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
-    hh_lsq(B, Q2, NP, LDB, LDB, sV, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
+    hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sV + M * HNB, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
+    hh_lsq(B, Q2, NP, LDB, LDB, sV, sV + M * HNB, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
     // condition estimate of each fit: max|R_ii| / min|R_ii| (a lower bound of the 2-norm
     // condition number of the weighted system), on wave 0 by lane reductions
     if (tid < 64) {
@@ -517,12 +580,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const int r = idx / Q2, j = idx % Q2;
       MS[idx] = B[(int64_t)r * LDB + NP + j];
     }
-    // T1 = Hmat (Q2 x NP) * B^+ (NP x Q2), kept in LDS (the back-substitution buffer, free
-    // now) where it fits.  Both products: one column j per lane and kRB rows per thread, so
+    // T1 = Hmat (Q2 x NP) * B^+ (NP x Q2), kept in LDS (the panel or back-substitution
+    // buffers, free now) where it fits.  Both products: one column j per lane and kRB rows per thread, so
     // that every loaded operand feeds kRB (or, for the row operand, one per row) FMAs; each
     // output is still one FMA chain in the order of the sum.
-    constexpr bool kT1Lds = Q2 * Q2 <= 4 * NP * kBackCols;
-    double* T1p = kT1Lds ? sX : T1;
+    constexpr bool kT1V = Q2 * Q2 <= 2 * M * HNB, kT1X = Q2 * Q2 <= 4 * NP * kBackCols;
+    double* T1p = kT1V ? sV : (kT1X ? sX : T1);
     for (int it = tid; it < ((Q2 + kRB - 1) / kRB) * Q2; it += NT) {
       const int i0 = (it / Q2) * kRB, j = it % Q2;
       double acc[kRB];
