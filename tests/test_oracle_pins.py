@@ -391,3 +391,46 @@ def test_rigid_motion_and_scaling_invariance():
         e = {"S": 1, "D": 0, "Sp": 0, "Dp": -1}[k]
         for sc, v in res[1:]:
             assert abs(v[k] - res[0][1][k] * sc ** e) < 1e-11 * max(1, abs(v[k])), k
+
+
+# ---------------------------------------------------------------- smooth rule
+
+def test_smooth_kernels_against_derivatives_of_green_function():
+    """The smooth rule K(x, r_j) w_j of the splitting D = D_smooth + D_RRQ (eq. dlpsplitting)
+    for the four kernels, from G(x, r) = 1/(4 pi |x - r|) and its directional derivatives:
+    K_S = G, K_D = nu . grad_r G, K_S' = nu' . grad_x G, K_D' = nu' . grad_x (nu . grad_r G).
+    The derivatives are taken by 30-digit numerical differentiation (mpmath.diff) of G along
+    the two normals, independently of the closed forms in the oracle; the weights w_j scale
+    each kernel."""
+    import mpmath
+    from oracle.rrq import smooth_kernels
+    rng = np.random.default_rng(17)
+    x = rng.normal(size=3)
+    nu_t = rng.normal(size=3)
+    nu_t /= np.linalg.norm(nu_t)
+    r = x[None, :] + rng.normal(size=(5, 3)) * np.array([[0.1], [0.5], [1.0], [2.0], [7.0]])
+    nu = rng.normal(size=(5, 3))
+    nu /= np.linalg.norm(nu, axis=1)[:, None]
+    w = rng.uniform(0.5, 2.0, size=5)
+    K = smooth_kernels(x, nu_t, r, nu, w)
+    with mpmath.workdps(30):
+        X = [mpmath.mpf(float(v)) for v in x]
+        A = [mpmath.mpf(float(v)) for v in nu_t]
+
+        def G(s, t, j):
+            # G(x + s nu', r_j + t nu_j)
+            d = [X[c] + s * A[c] - mpmath.mpf(float(r[j, c])) - t * mpmath.mpf(float(nu[j, c]))
+                 for c in range(3)]
+            return 1 / (4 * mpmath.pi * mpmath.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2))
+
+        for j in range(5):
+            ref = {"S": G(0, 0, j),
+                   "D": mpmath.diff(lambda t: G(0, t, j), 0),
+                   "Sp": mpmath.diff(lambda s: G(s, 0, j), 0),
+                   "Dp": mpmath.diff(lambda s, t: G(s, t, j), (0, 0), (1, 1))}
+            R = float(np.linalg.norm(x - r[j]))
+            for k in ("S", "D", "Sp", "Dp"):
+                exact = float(ref[k]) * w[j]
+                # D' is a difference of two terms, each at most w / (4 pi R^3) and 3 times that
+                scale = 4 * w[j] / (4 * math.pi * R ** 3) if k == "Dp" else abs(exact)
+                assert abs(K[k][j] - exact) <= 1e-14 * scale, (k, j, K[k][j], exact)
