@@ -1,6 +1,7 @@
 """GPU parity at the full sizes of the benchmark workloads, in the launch configuration the
 benchmark times (batched form, autotuned tile and grid, correction weights, principal value
-on the surface): sampled pair blocks against the oracle, with the gates of the parity tests.
+on the surface): sampled pair blocks against the oracle, with the gates of the parity tests
+(the flat 1e-11 potential gate on every pair of the star and ellipsoid workloads).
 Only the sampled blocks leave the device."""
 import numpy as np
 import pytest
@@ -62,7 +63,7 @@ def test_star_full_size():
     surf, tg, _ = wl.config2()
     gpu, off, stats, keep = _assemble_bench_config(surf, tg)
     pairs = _pairs(tg, np.random.default_rng(21), 70)
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="star full size")
     assert stats["newton_fail"] == 0
 
 
@@ -72,7 +73,7 @@ def test_uneven_ellipsoids_full_size():
     surf, tg, _ = wl.config3()
     gpu, off, stats, keep = _assemble_bench_config(surf, tg)
     pairs = _pairs(tg, np.random.default_rng(22), 40, surf, per_order=12)
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="ellipsoids full size")
     assert stats["newton_fail"] <= 1e-4 * stats["near_edges"]
 
 
@@ -83,5 +84,5 @@ def test_forty_spheres_full_size():
     surf, tg, _ = wl.config5()
     gpu, off, stats, keep = _assemble_bench_config(surf, tg)
     pairs = _pairs(tg, np.random.default_rng(23), 40)
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, label="forty spheres full size")
     assert stats["newton_fail"] <= 1e-4 * stats["near_edges"]

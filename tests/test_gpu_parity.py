@@ -1,28 +1,25 @@
 """GPU parity: the HIP library (through the C ABI) against the oracle, on seeded inputs.
 
-Gates, per kernel S, D, S', D' and per compared (target, patch) pair block:
-* weights:    ||W_gpu - W_or||_inf <= 1e-11 ||W_raw||_inf + 30 ||dW_ulp||_inf
-* potentials: |(W_gpu - W_or) . f| <= 1e-11 sum_j |W_raw,j f_j| + 30 |dW_ulp . f|
-  for a smooth nodal density f,
-where W_raw is the oracle block without the smooth-rule correction and dW_ulp is the larger of
-three changes of the oracle block under perturbations at rounding level: the target coordinates
-moved by one relative ulp (2^-52), the edge samples moved by one relative ulp with random signs
-(they fix the patch frame and the boundary curve), and the least-squares fits solved by SVD
-instead of Householder QR (both backward stable).  dW_ulp is only computed for blocks that miss the plain
-1e-11 bound: for pairs about a patch diameter away the
-weights are small differences of large moment x map products, and one ulp of input already
-moves them by 1e-10..1e-8 relative, so no FP64 implementation reproduces them to 1e-11.  Such
-blocks are counted and reported.  Pair offsets are compared bit-exactly.
+Gates (tests/_parity.py), per kernel S, D, S', D' and per compared (target, patch) pair block:
+* flat:     ||W_gpu - W_or||_inf <= 1e-11 ||W_raw||_inf and, for a smooth nodal density f,
+            |(W_gpu - W_or) . f| <= 1e-11 sum_j |W_raw,j f_j|
+            (W_raw: the oracle block without the smooth-rule subtraction);
+* ensemble: a block that misses a flat bound must lie within 3 times the spread of the oracle
+            itself over 16 evaluations with every input of the pair moved by one relative ulp
+            (random signs) and one with its fits solved by the SVD instead of QR.
+Where the workload's conditioning allows it (on-surface targets of fine meshes, moderate
+curvature) every pair's potential must also meet the flat bound with no allowance
+(flat_potential).  Pair offsets are compared bit-exactly.
 """
 import numpy as np
 import pytest
 
 from paper_2411_08342_amd import workloads as wl
+from _parity import compare_pairs, smooth_density  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
-ULP_FACTOR = 30.0
 KERNELS = ("S", "D", "Sp", "Dp")
 
 
@@ -41,65 +38,18 @@ def _run_gpu(surf, tg, flags=None, kmask=15):
     return out, asm.pair_off.cpu().numpy(), stats, (plan, asm)
 
 
-def smooth_density(surf):
-    x, y, z = surf["node_xyz"]
-    return 0.7 + x * x - 0.4 * y * z + 0.3 * z + 0.2 * x * y * z
-
-
-def _compare(surf, tg, gpu, pair_off, pairs, correction=True, onsurf_pv=True, tol=TOL):
-    from oracle.assemble import pair_block, pair_offsets
-    from oracle.rrq import smooth_kernels
+def _compare(surf, tg, gpu, pair_off, pairs, correction=True, onsurf_pv=True,
+             flat_potential=False, label=""):
+    """Pair offsets bit-exact, then the gates of tests/_parity.py on the blocks of `pairs`."""
+    from oracle.assemble import pair_offsets
     off = pair_offsets(surf, tg)
     assert np.array_equal(off, pair_off)
-    owner = np.repeat(np.arange(len(tg["near_ptr"]) - 1), np.diff(tg["near_ptr"]))
-    f = smooth_density(surf)
-    fits, fits_svd = {}, {}
-    stat = {k: dict(max_rel=0.0, max_abs=0.0, wmax=0.0, pot=0.0, ulp_limited=0)
-            for k in KERNELS if gpu[k] is not None}
-    for i in pairs:
-        t, P = int(owner[i]), int(tg["near_patch"][i])
-        ref, _ = pair_block(surf, tg, fits, t, P, correction, onsurf_pv)
-        raw, _ = pair_block(surf, tg, fits, t, P, False, onsurf_pv)
-        n0 = surf["node_off"][P]
-        a, b = off[i], off[i + 1]
-        fi = f[n0:n0 + (b - a)]
-        pert = None
-        for k in stat:
-            g, r = gpu[k][a:b], ref[k]
-            assert np.all(np.isfinite(g)), (k, i)
-            ew = np.max(np.abs(g - r))
-            ep = abs((g - r) @ fi)
-            sw = np.max(np.abs(raw[k]))
-            sp = np.sum(np.abs(raw[k] * fi))
-            st = stat[k]
-            st["max_rel"] = max(st["max_rel"], ew / sw)
-            st["max_abs"] = max(st["max_abs"], ew)
-            st["wmax"] = max(st["wmax"], np.max(np.abs(r)))
-            st["pot"] = max(st["pot"], ep / sp)
-            if ew <= tol * sw and ep <= tol * sp:
-                continue
-            if pert is None:
-                tg2 = dict(tg)
-                x = np.array(tg["xyz"], copy=True)
-                x[:, t] *= 1.0 + 2.0 ** -52
-                tg2["xyz"] = x
-                s2 = dict(surf)
-                e = np.array(surf["edge_xyz"], copy=True)
-                sg = np.random.default_rng(i).choice([-1.0, 1.0], size=e.shape)
-                s2["edge_xyz"] = e * (1.0 + 2.0 ** -52 * sg)
-                pert = (pair_block(surf, tg2, fits, t, P, correction, onsurf_pv)[0],
-                        pair_block(surf, tg, fits_svd, t, P, correction, onsurf_pv, "svd")[0],
-                        pair_block(s2, tg, {}, t, P, correction, onsurf_pv)[0])
-            ds = [pp[k] - r for pp in pert]
-            dw = max(ds, key=lambda d: np.max(np.abs(d)))
-            dpot = max(abs(d @ fi) for d in ds)
-            st["ulp_limited"] += 1
-            assert ew <= tol * sw + ULP_FACTOR * np.max(np.abs(dw)), (k, i, ew, sw, np.max(np.abs(dw)))
-            assert ep <= tol * sp + ULP_FACTOR * dpot, (k, i, ep, sp, dpot)
-    print("parity over", len(pairs), "pairs:",
-          {k: dict(max_rel_to_raw=f"{s['max_rel']:.2e}", global_maxnorm=f"{s['max_abs'] / s['wmax']:.2e}",
-                   potential=f"{s['pot']:.2e}", ulp_limited=s["ulp_limited"]) for k, s in stat.items()})
-    return stat
+
+    def block(i):
+        return {k: (gpu[k][off[i]:off[i + 1]] if gpu[k] is not None else None) for k in KERNELS}
+
+    return compare_pairs(surf, tg, pairs, gpu_block=block, correction=correction,
+                         onsurf_pv=onsurf_pv, flat_potential=flat_potential, label=label)
 
 
 def _sample(tg, n, rng, must=()):
@@ -125,7 +75,7 @@ def test_config1_parity_sampled(cfg1):
     off_surface = [k for t in (216, 260, 330, 400)
                    for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])]
     pairs = _sample(tg, 120, rng, must=self_pairs + off_surface)
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="config1")
 
 
 def test_config1_offsurface_targets_all_pairs(cfg1):
@@ -133,7 +83,7 @@ def test_config1_offsurface_targets_all_pairs(cfg1):
     surf, tg, dens, gpu, off, stats, _ = cfg1
     ts = list(range(216, 236)) + list(range(316, 336))
     pairs = [k for t in ts for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])]
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="config1 off-surface")
 
 
 def test_config1_raw_and_exterior_limit():
@@ -146,7 +96,8 @@ def test_config1_raw_and_exterior_limit():
                   for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])
                   if tg["near_patch"][k] == tg["self_patch"][t]]
     pairs = _sample(tg, 40, rng, must=self_pairs)
-    _compare(surf, tg, gpu, off, pairs, correction=False, onsurf_pv=False)
+    _compare(surf, tg, gpu, off, pairs, correction=False, onsurf_pv=False, flat_potential=True,
+             label="config1 raw exterior")
 
 
 def _small_star(n=3, q=8):
@@ -169,7 +120,7 @@ def test_star_q8_parity_nodes_and_close_targets():
     T0 = surf["node_xyz"].shape[1]
     close = [k for t in range(T0, T0 + 300, 7) for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])]
     pairs = _sample(tg, 120, rng, must=close)
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, label="star 54 patches")
     assert stats["newton_fail"] <= 1e-3 * stats["near_edges"]
 
 
@@ -186,7 +137,7 @@ def test_mixed_orders_parity():
     tg = wl.make_targets(surf, xyz, nrm, np.full(T, -1), np.full(T, -1), eta=1.0)
     gpu, off, stats, _ = _run_gpu(surf, tg)
     pairs = _sample(tg, 150, rng)
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="mixed orders")
 
 
 @pytest.mark.parametrize("q", [8, 10])
@@ -196,7 +147,7 @@ def test_paraboloid_curvature_and_size_parity(q):
     weighted DLP system's condition number reaches 2.7e6 at q = 8 and 9.5e7 at q = 10) and
     shrinking size (H = 10, h down to 1/1024, where the frame scaling brings it back to the
     flat value).  Node targets and close off-surface targets, same gate as every parity test
-    (its SVD-versus-QR term absorbs the conditioning)."""
+    (its SVD-solved member absorbs the conditioning of the fit)."""
     from oracle.assemble import fit_patch
     cases = [(0.0, 1.0), (2.0, 1.0), (10.0, 1.0), (10.0, 1.0 / 16), (10.0, 1.0 / 1024)]
     surf, tg = wl.paraboloid_workload(cases, q)
@@ -225,7 +176,7 @@ def test_paraboloid_curvature_and_size_parity(q):
     owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
     off_surface = np.nonzero(tg["self_patch"][owner] < 0)[0]
     pairs = _sample(tg, 120, rng, must=off_surface)
-    _compare(surf, tg, gpu, off, pairs)
+    _compare(surf, tg, gpu, off, pairs, label=f"paraboloid q={q}")
 
 
 def test_empty_rows_and_kernel_mask():
@@ -239,7 +190,8 @@ def test_empty_rows_and_kernel_mask():
     assert tg2["near_ptr"][2] == 0
     gpu, off, stats, _ = _run_gpu(surf, tg2, kmask=rrq.RRQ_K_D | rrq.RRQ_K_SP)
     assert gpu["S"] is None and gpu["Dp"] is None
-    _compare(surf, tg2, gpu, off, list(range(len(tg2["near_patch"]))))
+    _compare(surf, tg2, gpu, off, list(range(len(tg2["near_patch"]))), flat_potential=True,
+             label="kernel mask")
 
 
 def test_plain_form_parity():
@@ -252,7 +204,8 @@ def test_plain_form_parity():
     self_pairs = [k for t in range(0, 216, 31)
                   for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])
                   if tg["near_patch"][k] == tg["self_patch"][t]]
-    _compare(surf, tg, gpu, off, _sample(tg, 60, rng, must=self_pairs))
+    _compare(surf, tg, gpu, off, _sample(tg, 60, rng, must=self_pairs), flat_potential=True,
+             label="plain form")
 
 
 @pytest.mark.parametrize("tile", [4, 8])

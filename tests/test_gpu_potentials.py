@@ -1,9 +1,9 @@
 """GPU tests of the potentials mode (the correction applied to a density without storing the
 weights) and of the whole method end to end:
 
-* pair potentials against the oracle, with the weights parity gate carried to the potential
-  level: |p_gpu - W_or . f| <= 1e-11 sum_j |W_raw,j f_j| + 30 |dW_ulp . f| (dW_ulp as in the
-  weights parity tests: the larger change of the oracle under rounding-level perturbations);
+* pair potentials against the oracle with the potential gates of tests/_parity.py:
+  |p_gpu - W_or . f| <= 1e-11 sum_j |W_raw,j f_j|, or within 3 times the spread of the oracle
+  over its ulp-perturbation ensemble (flat with no allowance on the sphere);
 * per-target potentials against rrq_assemble followed by rrq_apply (same numbers, another
   rounding order);
 * the direct smooth rule against a host sum;
@@ -22,7 +22,6 @@ pytestmark = pytest.mark.gpu
 
 KERNELS = ("S", "D", "Sp", "Dp")
 TOL = 1e-11
-ULP_FACTOR = 30.0
 
 
 def _density(surf):
@@ -60,47 +59,17 @@ def _evaluate(surf, tg, dens, flags=None, smooth=False):
     return out, sm
 
 
-def _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=True):
-    from oracle.assemble import pair_block
+def _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=True, flat_potential=False,
+                               label=""):
     from paper_2411_08342_amd import rrq
+    from _parity import compare_pairs
     f = _density(surf)
     one = _one_pair_targets(tg, pairs)
     flags = rrq.RRQ_F_CORRECTION | (rrq.RRQ_F_ONSURF_PV if onsurf_pv else 0)
     gpu, _ = _evaluate(surf, one, f, flags)
-    fits, fits_svd = {}, {}
-    worst = {k: 0.0 for k in KERNELS}
-    limited = 0
-    for i in range(len(pairs)):
-        P = int(one["near_patch"][i])
-        n0, n1 = surf["node_off"][P], surf["node_off"][P + 1]
-        fi = f[n0:n1]
-        ref, _ = pair_block(surf, one, fits, i, P, True, onsurf_pv)
-        raw, _ = pair_block(surf, one, fits, i, P, False, onsurf_pv)
-        pert = None
-        for k in KERNELS:
-            assert np.isfinite(gpu[k][i]), (k, i)
-            ep = abs(gpu[k][i] - ref[k] @ fi)
-            sp = np.sum(np.abs(raw[k] * fi))
-            worst[k] = max(worst[k], ep / sp)
-            if ep <= TOL * sp:
-                continue
-            if pert is None:
-                one2 = dict(one)
-                x = np.array(one["xyz"], copy=True)
-                x[:, i] *= 1.0 + 2.0 ** -52
-                one2["xyz"] = x
-                s2 = dict(surf)
-                e = np.array(surf["edge_xyz"], copy=True)
-                sg = np.random.default_rng(i).choice([-1.0, 1.0], size=e.shape)
-                s2["edge_xyz"] = e * (1.0 + 2.0 ** -52 * sg)
-                pert = (pair_block(surf, one2, fits, i, P, True, onsurf_pv)[0],
-                        pair_block(surf, one, fits_svd, i, P, True, onsurf_pv, "svd")[0],
-                        pair_block(s2, one, {}, i, P, True, onsurf_pv)[0])
-                limited += 1
-            dpot = max(abs((pp[k] - ref[k]) @ fi) for pp in pert)
-            assert ep <= TOL * sp + ULP_FACTOR * dpot, (k, i, ep, sp, dpot)
-    print(f"pair potentials over {len(pairs)} pairs: worst |dp| / sum|W_raw f| "
-          + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()) + f"; ulp-limited pairs {limited}")
+    compare_pairs(surf, one, list(range(len(pairs))),
+                  gpu_pot=lambda i: {k: gpu[k][i] for k in KERNELS}, correction=True,
+                  onsurf_pv=onsurf_pv, flat_potential=flat_potential, label=label)
 
 
 def test_pair_potentials_match_oracle_sphere():
@@ -108,14 +77,14 @@ def test_pair_potentials_match_oracle_sphere():
     rng = np.random.default_rng(11)
     nnz = len(tg["near_patch"])
     pairs = np.sort(rng.choice(nnz, size=min(240, nnz), replace=False))
-    _pair_potentials_vs_oracle(surf, tg, pairs)
+    _pair_potentials_vs_oracle(surf, tg, pairs, flat_potential=True, label="sphere")
 
 
 def test_pair_potentials_match_oracle_star_exterior_limit():
     surf, tg, _ = wl.config2(n=3)
     rng = np.random.default_rng(12)
     pairs = np.sort(rng.choice(len(tg["near_patch"]), size=160, replace=False))
-    _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=False)
+    _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=False, label="star exterior limit")
 
 
 def _weight_scale(surf, tg, w_raw, f):
