@@ -155,6 +155,20 @@ rrq_status rrq_assemble(const rrq_plan* plan, const rrq_targets* tg, uint32_t km
                         double* out_Dp, const int64_t* pair_off, void* workspace,
                         size_t workspace_bytes, void* stream, rrq_stats* stats);
 
+/* Allocation-free variant of rrq_assemble, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and the same output, with the workspace taken from a device array inside
+ * the library, RRQ_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, held from the first call on that
+ * GPU until the process ends.  Near lists whose rrq_workspace_size exceeds that return
+ * RRQ_ERR_BUFFER before any launch (about 50,000 pairs when the largest order is 8).  The call
+ * issues no hipMalloc, hipFree or memset, takes no statistics, and needs pair_off from
+ * rrq_pair_offsets.  All calls on one GPU share that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other threads) race and must be serialised by the caller. */
+#define RRQ_NOALLOC_SCRATCH_BYTES (64ll << 20)
+rrq_status rrq_assemble_noalloc(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
+                                uint32_t flags, double* out_S, double* out_D, double* out_Sp,
+                                double* out_Dp, const int64_t* pair_off, void* stream);
+
 /* pot[t] = sum over the near pairs of target t of W[block] . density[nodes of P]
  * (the sparse correction applied to nodal densities).  pot_* are [T]. */
 rrq_status rrq_apply(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,

@@ -628,6 +628,64 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
                    (hipStream_t)stream, stats);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// allocation-free assembly: the workspace of rrq_assemble taken from a file-scope device
+// array instead of a caller buffer
+// ---------------------------------------------------------------------------------------
+#include <mutex>
+
+static __device__ __align__(256) unsigned char scratch[RRQ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.  In host
+// code the array's name is only a host-side stand-in; kernels must get this address.
+rrq_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return RRQ_ERR_DEVICE;
+  if (dev >= kMaxDevices) return RRQ_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return RRQ_ERR_DEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RRQ_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rrq_status rrq_assemble_noalloc(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
+                                uint32_t flags, double* out_S, double* out_D, double* out_Sp,
+                                double* out_Dp, const int64_t* pair_off, void* stream) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!pair_off || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
+  if (ws_bytes(p, tg->nnz) > (size_t)RRQ_NOALLOC_SCRATCH_BYTES) return RRQ_ERR_BUFFER;
+  double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
+  for (int K = 0; K < 4; ++K)
+    if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
+  if (flags & RRQ_F_LEARNED) {
+    if (flags & RRQ_F_PLAIN) return RRQ_ERR_UNSUPPORTED;
+    if (!p->has_mlp) return RRQ_ERR_ARG;
+  }
+  void* ws = nullptr;
+  c = scratch_for_current_device(&ws);
+  if (c != RRQ_OK) return c;
+  // every part of the workspace that must start at zero (counters, bins, queues) is cleared
+  // by the kernels of the assembly itself, so the previous call's contents do not matter
+  return run_pairs(p, tg, kmask, flags, outs, pair_off, nullptr, nullptr, ws,
+                   (hipStream_t)stream, nullptr);
+}
+
 rrq_status rrq_potentials(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
                           uint32_t flags, const double* density, double* pot_S, double* pot_D,
                           double* pot_Sp, double* pot_Dp, void* workspace,

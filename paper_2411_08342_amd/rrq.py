@@ -21,7 +21,8 @@ EXPORTED = ("rrq_plan_create", "rrq_plan_refit", "rrq_plan_destroy", "rrq_worksp
             "rrq_pair_offsets", "rrq_assemble", "rrq_apply", "rrq_autotune", "rrq_graph_create",
             "rrq_graph_launch", "rrq_graph_destroy", "rrq_collect_roots", "rrq_mlp_train",
             "rrq_mlp_loss_grad", "rrq_mlp_predict", "rrq_plan_set_mlp", "rrq_potentials",
-            "rrq_smooth_potentials", "rrq_plan_fit_condition", "rrq_status_string")
+            "rrq_smooth_potentials", "rrq_plan_fit_condition", "rrq_assemble_noalloc",
+            "rrq_status_string")
 MLP_PARAMS = 4866
 
 
@@ -93,6 +94,8 @@ def lib():
                                        ctypes.POINTER(i64), vp]
         L.rrq_assemble.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp, vp,
                                    ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
+        L.rrq_assemble_noalloc.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp,
+                                           vp, vp, vp]
         L.rrq_apply.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp]
         L.rrq_potentials.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp,
@@ -252,6 +255,14 @@ class Assembler:
                                   self.workspace.data_ptr(), self.workspace.numel(), _stream(),
                                   ctypes.byref(st) if st is not None else None))
         return st.as_dict() if st is not None else None
+
+    def assemble_noalloc(self, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV):
+        """rrq_assemble_noalloc: the same assembly with the library's own device scratch
+        instead of this object's workspace (no statistics)."""
+        ptr = [self.out[k].data_ptr() if self.out[k] is not None else None for k in KERNELS]
+        _check(lib().rrq_assemble_noalloc(self.plan.handle, ctypes.byref(self._t), self.kmask,
+                                          flags, ptr[0], ptr[1], ptr[2], ptr[3],
+                                          self.pair_off.data_ptr(), _stream()))
 
     def apply(self, density):
         import torch

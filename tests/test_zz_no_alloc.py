@@ -1,0 +1,77 @@
+"""rrq_assemble_noalloc (the allocation-free variant of rrq_assemble, for callers that cannot
+allocate device memory) against rrq_assemble on the same inputs: two calls in a row, the
+second with a smaller near list, each bitwise equal to the workspace form (the same kernels
+and the same per-tile arithmetic); and the size limit rejected before any launch."""
+import numpy as np
+import pytest
+
+from paper_2411_08342_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ("S", "D", "Sp", "Dp")
+
+
+def _star_targets(surf, ntarget, seed):
+    x, n, sp, sn = wl.node_targets(surf)
+    rng = np.random.default_rng(seed)
+    xo, no = wl.offsurface_targets(surf, rng, total=100, rel_dist=(1e-5, 0.5))
+    keep = np.arange(0, x.shape[1], max(1, x.shape[1] // ntarget))[:ntarget]
+    xyz = np.concatenate([x[:, keep], xo], axis=1)
+    nrm = np.concatenate([n[:, keep], no], axis=1)
+    sp = np.concatenate([sp[keep], np.full(100, -1, np.int32)])
+    sn = np.concatenate([sn[keep], np.full(100, -1, np.int32)])
+    return wl.make_targets(surf, xyz, nrm, sp, sn, eta=1.5)
+
+
+def test_noalloc_matches_workspace_form_twice():
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf = wl.discretize(wl.cubed_sphere_patches(2, radial=wl.star_radius), np.full(24, 8))
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    sizes = []
+    for ntarget, seed in ((1536, 1), (300, 2)):
+        tg = _star_targets(surf, ntarget, seed)
+        asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
+        asm.assemble(flags=flags)
+        torch.cuda.synchronize()
+        ref = {k: asm.out[k].cpu().numpy().copy() for k in KERNELS}
+        for k in KERNELS:
+            asm.out[k].fill_(float("nan"))
+        asm.assemble_noalloc(flags=flags)
+        torch.cuda.synchronize()
+        for k in KERNELS:
+            got = asm.out[k].cpu().numpy()
+            assert np.all(np.isfinite(got)), k
+            assert np.array_equal(got, ref[k]), (ntarget, k, np.max(np.abs(got - ref[k])))
+        sizes.append(len(tg["near_patch"]))
+        print(f"noalloc: {sizes[-1]} pairs bitwise equal to rrq_assemble")
+    assert sizes[1] < sizes[0]
+
+
+def test_noalloc_rejects_near_lists_beyond_the_scratch():
+    import ctypes
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    reps = 20000
+    xyz = np.repeat(tg["xyz"][:, 216:217], reps, axis=1)
+    nrm = np.repeat(tg["nrm"][:, 216:217], reps, axis=1)
+    big = wl.make_targets(surf, xyz, nrm, np.full(reps, -1), np.full(reps, -1), eta=1.0)
+    dt = rrq.DeviceTargets(big)
+    t = dt.cstruct()
+    sz = ctypes.c_size_t()
+    assert rrq.lib().rrq_workspace_size(plan.handle, ctypes.byref(t), ctypes.byref(sz)) == 0
+    assert sz.value > (64 << 20)
+    rc = rrq.lib().rrq_assemble_noalloc(plan.handle, ctypes.byref(t), rrq.RRQ_K_ALL,
+                                        rrq.RRQ_F_CORRECTION, None, None, None, None, None,
+                                        rrq._stream())
+    assert rc == -1      # null outputs are an argument error, checked first
+    import torch
+    off = torch.zeros(dt.nnz + 1, dtype=torch.int64, device="cuda")
+    outs = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in range(4)]
+    rc = rrq.lib().rrq_assemble_noalloc(plan.handle, ctypes.byref(t), rrq.RRQ_K_ALL,
+                                        rrq.RRQ_F_CORRECTION, *[o.data_ptr() for o in outs],
+                                        off.data_ptr(), rrq._stream())
+    assert rc == -6      # RRQ_ERR_BUFFER: beyond the scratch, nothing launched
