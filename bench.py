@@ -28,14 +28,15 @@ TRAFFIC = {"src_sha256": "8f8d22ce8d25613e2c644f860e889d97d3a18b2611ea5fd8a5808e
 
 
 def flops_per_pair(q):
-    """Algorithmic FP64 flops of one (target, patch) pair at order q (ptilde = 2q), counting
-    only data-independent work (Newton iterations and panel points excluded):
-      edge contractions  4 ptilde (16 J1 + 76 J2)      V: 16, Q and dQ: 38 each per (j,k,node)
-      edge weights/Omega 4 ptilde * 60
-      translations       100 tD + 10 tS                  terms of the DLP/SLP sums
-      target harmonics   60 (q+1)^2
-      weight contraction 2 q^2 17 n_p                    rows x maps
-    """
+    """Algorithmic FP64 flops of one (target, patch) pair at order q (p = q, ptilde = 2q, an FMA
+    counted as 2), data-independent work only (Newton iterations and the extra panel points of
+    near edges excluded):
+      edge weights and contractions   4 [12 J1 pt + 72 J2 pt + 4 pt^2 + 90 pt]
+      translations, target harmonics  32 tD + 8 tS + 64 tD + 50 (p+1)^2 + 200 n_p
+      rows x maps                     2 q^2 17 n_p
+    with J1 = p(p+3)/2 (j >= 1, k >= 0), J2 = J1 - 2 (j >= 2) and tD, tS the (l, m, j, k) term
+    counts of the double- and single-layer translation sums (489 and 574 at p = 8): 378,306
+    flops per pair at q = 8."""
     p, pt = q, 2 * q
     n_p = p * (p + 1) // 2
     J1 = p * (p + 3) // 2
@@ -49,8 +50,9 @@ def flops_per_pair(q):
                         tS += 1
                         if j >= 2:
                             tD += 1
-    return (4 * pt * (16 * J1 + 76 * J2) + 4 * pt * 60 + 100 * tD + 10 * tS
-            + 60 * (p + 1) ** 2 + 2 * q * q * 17 * n_p)
+    edges = 4 * (12 * J1 * pt + 72 * J2 * pt + 4 * pt * pt + 90 * pt)
+    trans = 32 * tD + 8 * tS + 64 * tD + 50 * (p + 1) ** 2 + 200 * n_p
+    return edges + trans + 2 * q * q * 17 * n_p
 
 
 def kernel_src_sha():
@@ -137,88 +139,193 @@ def build_workload(name):
     elif name == "star-small":
         surf, tg, dens = wl.config2(n=4)
         desc = "star, 96 quads q=8, node targets, near 1.5 patch diameters"
+    elif name == "sphere":
+        surf, tg, dens = wl.config1()
+        desc = ("unit sphere, 6 quads q=6, 216 node targets and 200 off-surface targets "
+                "1e-4..1e-1 away, near 1 patch diameter")
     else:
         raise SystemExit(f"unknown workload {name}")
     return surf, tg, desc
 
 
-def cpu_baseline(surf, tg, seconds=20.0, seed=0):
-    """The oracle, as it stands, on all near pairs of seeded targets (fits of the touched
-    patches included), one thread, until about `seconds` of work."""
+# ---------------------------------------------------------------------------------------
+# CPU baseline: the oracle, as it stands, timed on the host cores.  The worker processes are
+# started before this process initialises the GPU, each limited to one BLAS thread.
+# ---------------------------------------------------------------------------------------
+_W = {}
+
+
+def _worker_init():
     from threadpoolctl import threadpool_limits
+    _W["limits"] = threadpool_limits(limits=1)
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+
+
+def _worker_workload(name):
+    if name not in _W:
+        surf, tg, _ = build_workload(name)
+        owner = np.repeat(np.arange(len(tg["near_ptr"]) - 1), np.diff(tg["near_ptr"]))
+        _W[name] = (surf, tg, owner)
+    return _W[name]
+
+
+def _w_ready(name):
+    _worker_workload(name)
+    return os.getpid()
+
+
+def _w_time(name, targets, seconds, keep):
+    """The oracle on all near pairs of `targets` in order, until `seconds` have passed (at least
+    one target).  Returns (elapsed s, weights, pairs, targets done, fits, blocks of the pairs
+    listed in `keep` or of all pairs if keep is True)."""
     from oracle.assemble import pair_block
+    surf, tg, _ = _worker_workload(name)
+    fits, blocks = {}, {}
+    nw = npairs = ntg = 0
+    t0 = time.perf_counter()
+    for t in targets:
+        for i in range(tg["near_ptr"][t], tg["near_ptr"][t + 1]):
+            W, _ = pair_block(surf, tg, fits, int(t), int(tg["near_patch"][i]))
+            nw += 4 * len(W["S"])
+            npairs += 1
+            if keep is True or i in keep:
+                blocks[int(i)] = (W, fits[int(tg["near_patch"][i])].frame.s)
+        ntg += 1
+        if seconds and time.perf_counter() - t0 > seconds:
+            break
+    return time.perf_counter() - t0, nw, npairs, ntg, len(fits), blocks
+
+
+def _w_gate(name, pairs, gpu):
+    """The parity gates of the tests (tests/_parity.py) on GPU blocks of `pairs`, counting
+    instead of asserting."""
+    from _parity import compare_pairs
+    surf, tg, _ = _worker_workload(name)
+    return compare_pairs(surf, tg, pairs, gpu_block=lambda i: gpu[i], strict=False)
+
+
+def _merge_gate(parts):
+    out = {}
+    for part in parts:
+        for k, v in part.items():
+            if k not in out:
+                out[k] = dict(v)
+                continue
+            o, n0, n1 = out[k], out[k]["pairs"], v["pairs"]
+            for f in ("max_rel", "global_maxnorm", "potential", "ratio_max", "pot_ratio_max"):
+                o[f] = max(o[f], v[f])
+            for f in ("potential_flat_rate", "gate_pass_rate", "ratio_p50"):
+                o[f] = (o[f] * n0 + v[f] * n1) / (n0 + n1)
+            o["pairs"] = n0 + n1
+            o["ensemble_pairs"] += v["ensemble_pairs"]
+    return out
+
+
+def start_cpu_pool(name, workers):
+    """Worker processes for the oracle, started and warmed (workload built) before the GPU is
+    touched."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    pool = cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"),
+                                  initializer=_worker_init)
+    pids = list(pool.map(_w_ready, [name] * workers))
+    list(pool.map(_w_ready, ["sphere"] * workers))
+    return pool, len(set(pids))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pool, workers, name, surf, tg, gpu_block, seconds=10.0, seed=0, gate_pairs=150):
+    """The oracle timed (i) on one core over all near pairs of a run of consecutive targets from
+    a seeded start, (ii) on `workers` cores (one process each, a run from its own start), (iii)
+    on `workers` cores over every pair of the unit-sphere workload (6 patches, q = 6: all of
+    it); then the parity gates of the tests applied to the GPU blocks of the first
+    `gate_pairs` sampled pairs and the flat potential gate to all of them."""
     rng = np.random.default_rng(seed)
     T = len(tg["near_ptr"]) - 1
-    order = rng.permutation(T)
-    fits = {}
-    nw = 0
-    npairs = 0
-    ntg = 0
-    results = {}
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for t in order:
-            for i in range(tg["near_ptr"][t], tg["near_ptr"][t + 1]):
-                P = int(tg["near_patch"][i])
-                W, _ = pair_block(surf, tg, fits, int(t), P)
-                results[int(i)] = W
-                nw += 4 * len(W["S"])
-                npairs += 1
-            ntg += 1
-            if time.perf_counter() - t0 > seconds:
-                break
-        dt = time.perf_counter() - t0
-    return dict(value=nw / dt, unit="weights/s", cores=1, kind="oracle",
-                sample=f"all {npairs} near pairs of {ntg} seeded targets "
-                       f"({len(fits)} patch fits included), {dt:.1f} s"), results
-
-
-def parity_gate(surf, tg, res, gpu_blocks, owner, max_pairs=150, tol=1e-11, ulp_factor=30.0):
-    """On the sampled pair blocks (the first max_pairs): the fraction that passes the weights
-    gate of the parity tests, ||W_gpu - W_or|| <= tol ||W_raw|| + ulp_factor ||dW_ulp||, dW_ulp
-    the largest change of the oracle block under rounding-level perturbations (target moved by
-    one relative ulp, edge samples by one ulp, fits solved by SVD instead of QR); and, over
-    the same blocks, the max-norm difference GPU - oracle and oracle(SVD) - oracle(QR), both
-    relative to the largest oracle weight."""
-    from oracle.assemble import pair_block
-    KERNELS = ("S", "D", "Sp", "Dp")
-    fits, fits_svd = {}, {}
-    ok = {k: 0 for k in KERNELS}
-    dg = {k: 0.0 for k in KERNELS}
-    ds = {k: 0.0 for k in KERNELS}
-    wm = {k: 0.0 for k in KERNELS}
-    pairs = sorted(res)[:max_pairs]
+    # consecutive targets (neighbouring nodes) share their near patches, so the patch fits are
+    # amortised over the pairs as in a whole assembly; each leg starts at a seeded target
+    starts = rng.integers(0, T, size=workers + 1)
+    run = lambda a: [int((a + j) % T) for j in range(T)]
+    # (i) one core
+    dt, nw, npairs, ntg, nfit, blocks = pool.submit(_w_time, name, run(starts[0]), seconds,
+                                                    True).result()
+    single = dict(value=nw / dt, unit="weights/s", cores=1,
+                  sample=f"all {npairs} near pairs of {ntg} consecutive targets from a seeded "
+                         f"start ({nfit} patch fits included), {dt:.1f} s")
+    # (ii) all workers, each from its own seeded start
+    chunks = [run(a) for a in starts[1:]]
+    t0 = time.perf_counter()
+    res = list(pool.map(_w_time, [name] * workers, chunks, [seconds] * workers,
+                        [set()] * workers))
+    wall = time.perf_counter() - t0
+    nw_all = sum(r[1] for r in res)
+    allc = dict(value=nw_all / wall, unit="weights/s", cores=workers, kind="oracle",
+                sample=f"all near pairs of {sum(r[3] for r in res)} targets, runs of consecutive "
+                       f"targets from {workers} seeded starts ({sum(r[2] for r in res)} pairs, "
+                       f"{sum(r[4] for r in res)} patch fits), one process per core, "
+                       f"{wall:.1f} s wall")
+    # (iii) the unit-sphere workload in full, static split by target
+    s1, t1, _ = build_workload("sphere")
+    T1 = len(t1["near_ptr"]) - 1
+    chunks = [list(range(w * T1 // workers, (w + 1) * T1 // workers)) for w in range(workers)]
+    t0 = time.perf_counter()
+    res = list(pool.map(_w_time, ["sphere"] * workers, chunks, [0] * workers,
+                        [set()] * workers))
+    wall1 = time.perf_counter() - t0
+    cfg1 = dict(value=sum(r[1] for r in res) / wall1, unit="weights/s", cores=workers,
+                sample=f"unit sphere, 6 patches q=6: all {sum(r[2] for r in res)} pairs, "
+                       f"{wall1:.1f} s wall")
+    # parity gates on the sampled blocks (pair-wise, spread over the workers)
+    pairs = sorted(blocks)
+    gpu = {i: gpu_block(i) for i in pairs}
+    gsel = pairs[:gate_pairs]
+    parts = list(pool.map(_w_gate, [name] * workers, [gsel[w::workers] for w in range(workers)],
+                          [{i: gpu[i] for i in gsel[w::workers]} for w in range(workers)]))
+    gate = _merge_gate([p for p in parts if p])
+    # flat potential gate (no allowance) over every sampled pair; the raw block is the
+    # corrected one plus the smooth rule it subtracts
+    if os.path.join(ROOT, "tests") not in sys.path:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _parity import block_scales, smooth_density, TOL
+    from oracle.assemble import patch_arrays
+    from oracle.rrq import smooth_kernels
+    owner = np.repeat(np.arange(T), np.diff(tg["near_ptr"]))
+    dens = smooth_density(surf)
+    flat = {k: 0 for k in ("S", "D", "Sp", "Dp")}
+    worst = {k: 0.0 for k in flat}
     for i in pairs:
         t, P = int(owner[i]), int(tg["near_patch"][i])
-        W = res[i]
-        raw, _ = pair_block(surf, tg, fits, t, P, False)
-        svd = pair_block(surf, tg, fits_svd, t, P, True, True, "svd")[0]
-        for k in KERNELS:
-            dg[k] = max(dg[k], float(np.max(np.abs(gpu_blocks[i][k] - W[k]))))
-            ds[k] = max(ds[k], float(np.max(np.abs(svd[k] - W[k]))))
-            wm[k] = max(wm[k], float(np.max(np.abs(W[k]))))
-        need = [k for k in KERNELS
-                if np.max(np.abs(gpu_blocks[i][k] - W[k])) > tol * np.max(np.abs(raw[k]))]
-        for k in KERNELS:
-            ok[k] += k not in need
-        if not need:
-            continue
-        tg2 = dict(tg)
-        x = np.array(tg["xyz"], copy=True)
-        x[:, t] *= 1.0 + 2.0 ** -52
-        tg2["xyz"] = x
-        s2 = dict(surf)
-        e = np.array(surf["edge_xyz"], copy=True)
-        sg = np.random.default_rng(i).choice([-1.0, 1.0], size=e.shape)
-        s2["edge_xyz"] = e * (1.0 + 2.0 ** -52 * sg)
-        pert = (pair_block(surf, tg2, fits, t, P)[0], svd, pair_block(s2, tg, {}, t, P)[0])
-        for k in need:
-            dw = max(np.max(np.abs(pp[k] - W[k])) for pp in pert)
-            ok[k] += np.max(np.abs(gpu_blocks[i][k] - W[k])) <= (tol * np.max(np.abs(raw[k]))
-                                                                + ulp_factor * dw)
-    return {k: {"pairs_within_parity_gate": ok[k] / len(pairs),
-                "global_maxnorm_rel_gpu_vs_oracle": dg[k] / wm[k],
-                "global_maxnorm_rel_oracle_svd_vs_qr": ds[k] / wm[k]} for k in KERNELS}
+        W, scale = blocks[i]
+        xyz, nrm, wt, _ = patch_arrays(surf, P)
+        keep = np.ones(len(wt), dtype=bool)
+        if int(tg["self_patch"][t]) == P:
+            keep[int(tg["self_node"][t])] = False
+        sm = smooth_kernels(tg["xyz"][:, t], tg["nrm"][:, t], xyz[keep], nrm[keep], wt[keep])
+        raw = {}
+        for k in flat:
+            raw[k] = W[k].copy()
+            raw[k][keep] += sm[k]
+        f = dens[surf["node_off"][P]:surf["node_off"][P + 1]]
+        _, sp = block_scales(raw, f, scale)
+        for k in flat:
+            e = abs((gpu[i][k] - W[k]) @ f) / sp[k]
+            worst[k] = max(worst[k], e)
+            flat[k] += e <= TOL
+    acc = {k: dict(gate[k], potential_flat_all_sampled=flat[k] / len(pairs),
+                   potential_max_all_sampled=worst[k]) for k in gate}
+    allc.update(single_core=single, sphere_full=cfg1, nproc=os.cpu_count(), cpu_model=cpu_model(),
+                gpu_vs_oracle_on_sample=acc)
+    return allc
 
 
 def copy_probe(nbytes=1 << 30, reps=3):
@@ -241,7 +348,10 @@ def main():
     ap.add_argument("--workload", default="star")
     ap.add_argument("--form", default="batched", choices=["plain", "batched"])
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="seconds of oracle work per core in the CPU baseline legs")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle worker processes (0: min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-form and learned-guess measurements")
@@ -255,6 +365,13 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+
+    pool = None
+    workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+    if not args.no_cpu_baseline:
+        # before anything initialises the GPU: the workers are plain CPU processes
+        pool, workers = start_cpu_pool(args.workload, workers)
+        print(f"[bench] {workers} oracle workers ready", flush=True)
 
     import torch
     from paper_2411_08342_amd import rrq
@@ -336,47 +453,15 @@ def main():
                                 else f"k_pair_tile<{q},{tune['tile_targets'] if tune else 'T'}>"),
                      "flops_per_pair": flops_per_pair(q)},
     }
-    if not args.no_cpu_baseline:
-        cb, res = cpu_baseline(surf, tg, args.cpu_seconds)
+    if pool is not None:
         off = asm.pair_off.cpu().numpy()
-        x, y, z = surf["node_xyz"]
-        dens = 0.7 + x * x - 0.4 * y * z + 0.3 * z + 0.2 * x * y * z   # smooth nodal density
-        # scale of each block: the oracle block without the smooth-rule subtraction (the
-        # corrected weights of far pairs are small differences of large numbers)
-        from oracle.assemble import patch_arrays
-        from oracle.rrq import smooth_kernels
-        owner = np.repeat(np.arange(len(tg["near_ptr"]) - 1), np.diff(tg["near_ptr"]))
-        raw = {}
-        for i, W in res.items():
-            t, P = int(owner[i]), int(tg["near_patch"][i])
-            xyz, nrm, wt, _ = patch_arrays(surf, P)
-            sm = smooth_kernels(tg["xyz"][:, t], tg["nrm"][:, t], xyz, nrm, wt)
-            if int(tg["self_patch"][t]) == P:
-                for k in rrq.KERNELS:
-                    sm[k][int(tg["self_node"][t])] = 0.0
-            raw[i] = {k: W[k] + sm[k] for k in rrq.KERNELS}
-        gpu_blocks = {i: {k: asm.out[k][off[i]:off[i + 1]].cpu().numpy() for k in rrq.KERNELS}
-                      for i in res}
-        gate = parity_gate(surf, tg, res, gpu_blocks, owner, max_pairs=150)
-        acc = {}
-        for k in rrq.KERNELS:
-            wrel = pot = 0.0
-            within = 0
-            for i, W in res.items():
-                g = gpu_blocks[i][k]
-                P = int(tg["near_patch"][i])
-                f = dens[surf["node_off"][P]:surf["node_off"][P + 1]]
-                d = np.max(np.abs(g - W[k]))
-                sc = np.max(np.abs(raw[i][k]))
-                wrel = max(wrel, d / sc)
-                within += d <= 1e-11 * sc
-                pot = max(pot, abs((g - W[k]) @ f) / np.sum(np.abs(raw[i][k] * f)))
-            acc[k] = {"weights_max_rel_to_raw_block": wrel,
-                      "pairs_within_1e-11_of_raw_block": within / len(res),
-                      "potential_max_rel_to_raw_block": pot}
-            acc[k].update(gate[k])
-        cb["gpu_vs_oracle_on_sample"] = acc
-        out["cpu_baseline"] = cb
+
+        def gpu_block(i):
+            return {k: asm.out[k][off[i]:off[i + 1]].cpu().numpy() for k in rrq.KERNELS}
+
+        out["cpu_baseline"] = cpu_baseline(pool, workers, args.workload, surf, tg, gpu_block,
+                                           args.cpu_seconds)
+        pool.shutdown()
     print(json.dumps(out), flush=True)
 
 
