@@ -45,11 +45,16 @@ extern "C" {
 
 typedef enum {
   RRQ_OK = 0,
-  RRQ_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, bad option)       */
+  RRQ_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, bad option, a near
+                               list / self index / target outside its range)               */
   RRQ_ERR_DEVICE = -2,      /* a HIP call or kernel launch failed                           */
   RRQ_ERR_OOM = -3,         /* device allocation failed                                     */
-  RRQ_ERR_UNSUPPORTED = -5, /* order or option outside what this build supports             */
-  RRQ_ERR_BUFFER = -6       /* a caller buffer is too small                                 */
+  RRQ_ERR_ILLCONDITIONED = -4, /* rrq_plan_patch_flags: some patch fit is flagged (the plan
+                               still produces weights for it)                               */
+  RRQ_ERR_UNSUPPORTED = -5, /* order, size or option outside what this build supports       */
+  RRQ_ERR_BUFFER = -6,      /* a caller buffer is too small                                 */
+  RRQ_ERR_NONFINITE = -7    /* the call wrote NaN or Inf outputs (counted in rrq_stats and
+                               marked in the per-pair flags)                                */
 } rrq_status;
 
 /* kernel mask bits */
@@ -92,13 +97,22 @@ typedef struct {
 
 typedef struct {
   double rho_far;       /* Bernstein radius above which an edge uses the plain GL rule;
-                           <= 0 selects 10^(8/ptilde)                                       */
+                           <= 0 selects 10^(8/ptilde).  Values above that default for an
+                           order present in the surface return RRQ_ERR_UNSUPPORTED (the
+                           graded-panel capacity of the near-edge kernels is sized for it)  */
   double newton_tol;    /* Newton step tolerance (relative); <= 0 selects 1e-14             */
   int32_t newton_maxit; /* <= 0 selects 60                                                  */
   int32_t tile_targets; /* batched form: targets per workgroup tile (4 or 8); <= 0 = 4
                            until rrq_autotune picks one                                     */
   int32_t grid;         /* batched form: persistent workgroups per launch; <= 0 = 2048
                            until rrq_autotune picks one                                     */
+  int32_t ls_unweighted; /* 0: least-squares rows weighted by sqrt(w_a w_b), the tensor GL
+                           parameter weights (default); 1: unit row weights                 */
+  int32_t ptilde_factor; /* edge samples per edge = ptilde_factor * q; 0 or 2 (the only
+                           supported value; the paper's "2p"), else RRQ_ERR_UNSUPPORTED     */
+  int32_t u_rule;       /* Dirac-string direction u of a pair: 0 = the target normal for a
+                           self target, else +-normal of the nearest node pointing to the
+                           target (the only supported rule), else RRQ_ERR_UNSUPPORTED       */
 } rrq_options;
 
 typedef struct {
@@ -112,6 +126,20 @@ typedef struct {
                              kernel of the plain form or the tile kernels of the batched form;
                              binning, the root pre-pass and the near-edge moment pre-pass
                              excluded), from HIP events on the call's stream                */
+  int64_t newton_wave_iters; /* batched form: sum over wavefronts of the root pre-pass of
+                             the largest iteration count among the wavefront's lanes (the
+                             SIMD cost of the Newton solves)                               */
+  int64_t panel_overflow; /* near edges whose graded panels exceeded the kernel's capacity
+                             (the deepest panels, nearest the root, were dropped)           */
+  int64_t nonfinite;      /* NaN or Inf outputs written (weights or pair potentials)        */
+  int64_t flagged_pairs;  /* pairs with a non-zero flag word (see rrq_assemble)             */
+  uint32_t invalid;       /* device check of the inputs: 1 near list, 2 self indices,
+                             4 pair offsets or output length, 8 non-finite target; 0 = ok   */
+  double order_kernel_ms[5]; /* batched form: device time of the tile kernel of each order
+                             (4, 5, 6, 8, 10; 0 for absent orders), from HIP events        */
+  int64_t newton_slots;   /* batched form: (pair, edge) slots whose Newton solve ran         */
+  int64_t newton_over[5]; /* of those, the ones that took more than 2, 4, 6, 8 and 12
+                             iterations (the tail of the iteration distribution)           */
 } rrq_stats;
 
 /* Create a plan for a surface: allocates the per-patch frames, coefficient maps and edge
@@ -135,25 +163,56 @@ rrq_status rrq_plan_destroy(rrq_plan* plan);
  * plan_refit; the call synchronises `stream`. */
 rrq_status rrq_plan_fit_condition(const rrq_plan* plan, double* cond, void* stream);
 
+/* Flags of the source-only data of every patch (Steps 1-2), into host_flags[P] (HOST): bit 1
+ * = the DLP fit's condition estimate (rrq_plan_fit_condition) exceeds max_cond, bit 2 = the
+ * SLP fit's does, bit 4 = the patch's frame, local geometry, maps or edge tables hold a NaN
+ * or Inf.  max_cond <= 0 selects 1e9 (above it the fit's rounding can exceed about 1e-7 of
+ * the density; the paper's conditioning study of Sec. 5 reaches 1/eps at p = 26).  Returns
+ * RRQ_ERR_ILLCONDITIONED if any patch is flagged, RRQ_OK otherwise; flagged patches still
+ * produce weights.  Synchronises `stream`; allocates and frees a small device buffer. */
+rrq_status rrq_plan_patch_flags(const rrq_plan* plan, double max_cond, int32_t* host_flags,
+                                void* stream);
+
+/* Number of weights per kernel that rrq_assemble writes for this near list: the sum of q_P^2
+ * over the near pairs, into *nweights (HOST).  Checks the near list on the host (row pointer
+ * from 0 to nnz and non-decreasing, patch indices in range) and returns RRQ_ERR_ARG if it is
+ * not valid.  Copies near_ptr and near_patch to the host: synchronous. */
+rrq_status rrq_weights_size(const rrq_plan* plan, const rrq_targets* tg, int64_t* nweights,
+                            void* stream);
+
 /* Bytes of caller-provided device workspace that rrq_assemble needs for this near list. */
 rrq_status rrq_workspace_size(const rrq_plan* plan, const rrq_targets* tg, size_t* bytes);
 
 /* pair_off[nnz+1] (device) = prefix sum of q_P^2 over the near list (the output offset of
  * every pair's weight block).  `workspace` is the rrq_assemble workspace (its scan partials
- * are used).  Asynchronous; if `nweights` (HOST) is non-NULL the call synchronises the stream
- * and returns there the total number of weights per kernel. */
+ * are used).  The targets, near list and self indices are first checked on the device
+ * (near_ptr from 0 to nnz and non-decreasing, near_patch in [0, P), self_patch in [-1, P),
+ * self_node among the self patch's nodes, finite target points and normals).  Asynchronous;
+ * if `nweights` (HOST) is non-NULL the call synchronises the stream, returns RRQ_ERR_ARG
+ * before computing anything if the check failed, and returns there the total number of
+ * weights per kernel.  Asynchronously, a failed check makes the call's kernels do nothing. */
 rrq_status rrq_pair_offsets(const rrq_plan* plan, const rrq_targets* tg, int64_t* pair_off,
                             void* workspace, size_t workspace_bytes, int64_t* nweights,
                             void* stream);
 
-/* Assemble the weight blocks of every near pair.  out_* are [nweights] device arrays (NULL
- * for a kernel not in kmask).  pair_off from rrq_pair_offsets.  `workspace` of at least
- * rrq_workspace_size bytes.  If `stats` (HOST) is non-NULL the call synchronises the
- * stream and fills it. */
+/* Assemble the weight blocks of every near pair.  out_* are device arrays of out_len doubles
+ * each (NULL for a kernel not in kmask); out_len must be at least the number of weights
+ * (rrq_weights_size).  pair_off from rrq_pair_offsets.  pair_flags (device, [nnz], may be
+ * NULL) receives one flag word per pair: 1 = the Newton solve of one of its edges did not
+ * converge (that edge used the plain Gauss-Legendre rule), 2 = the graded panels of one of
+ * its near edges exceeded the kernel's capacity (the deepest panels were dropped), 4 = a
+ * weight of the pair is NaN or Inf.  `workspace` of at least rrq_workspace_size bytes.
+ * The inputs are checked on the device first (as in rrq_pair_offsets, and pair_off against
+ * the near list and out_len); if the check fails the call's kernels write nothing.  If
+ * `stats` (HOST) is non-NULL the call synchronises the stream, fills it, and returns
+ * RRQ_ERR_ARG (near list, self indices or targets invalid), RRQ_ERR_BUFFER (pair offsets
+ * inconsistent or beyond out_len) or RRQ_ERR_NONFINITE (NaN or Inf weights written);
+ * without stats those conditions are not reported by this call. */
 rrq_status rrq_assemble(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
                         uint32_t flags, double* out_S, double* out_D, double* out_Sp,
-                        double* out_Dp, const int64_t* pair_off, void* workspace,
-                        size_t workspace_bytes, void* stream, rrq_stats* stats);
+                        double* out_Dp, int64_t out_len, const int64_t* pair_off,
+                        uint32_t* pair_flags, void* workspace, size_t workspace_bytes,
+                        void* stream, rrq_stats* stats);
 
 /* Allocation-free variant of rrq_assemble, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
@@ -162,12 +221,13 @@ rrq_status rrq_assemble(const rrq_plan* plan, const rrq_targets* tg, uint32_t km
  * GPU until the process ends.  Near lists whose rrq_workspace_size exceeds that return
  * RRQ_ERR_BUFFER before any launch (about 50,000 pairs when the largest order is 8).  The call
  * issues no hipMalloc, hipFree or memset, takes no statistics, and needs pair_off from
- * rrq_pair_offsets.  All calls on one GPU share that GPU's array: calls that overlap in time
+ * rrq_pair_offsets; out_len and pair_flags as for rrq_assemble.  All calls on one GPU share that GPU's array: calls that overlap in time
  * on one GPU (other streams, other threads) race and must be serialised by the caller. */
 #define RRQ_NOALLOC_SCRATCH_BYTES (64ll << 20)
 rrq_status rrq_assemble_noalloc(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
                                 uint32_t flags, double* out_S, double* out_D, double* out_Sp,
-                                double* out_Dp, const int64_t* pair_off, void* stream);
+                                double* out_Dp, int64_t out_len, const int64_t* pair_off,
+                                uint32_t* pair_flags, void* stream);
 
 /* pot[t] = sum over the near pairs of target t of W[block] . density[nodes of P]
  * (the sparse correction applied to nodal densities).  pot_* are [T]. */
@@ -187,11 +247,13 @@ rrq_status rrq_apply(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask
  * (self node excluded) is subtracted per pair.  density is [N] (device, the surface's node
  * order); pot_* are [T] device arrays (NULL for a kernel not in kmask).  Batched form only
  * (RRQ_F_PLAIN -> RRQ_ERR_UNSUPPORTED); RRQ_F_LEARNED needs an installed network.  Uses the
- * rrq_assemble workspace; needs no pair offsets.  `stats` as for rrq_assemble. */
+ * rrq_assemble workspace; needs no pair offsets.  pair_flags (bit 4: a NaN or Inf pair
+ * potential) and `stats` as for rrq_assemble. */
 rrq_status rrq_potentials(const rrq_plan* plan, const rrq_targets* tg, uint32_t kmask,
                           uint32_t flags, const double* density, double* pot_S, double* pot_D,
-                          double* pot_Sp, double* pot_Dp, void* workspace,
-                          size_t workspace_bytes, void* stream, rrq_stats* stats);
+                          double* pot_Sp, double* pot_Dp, uint32_t* pair_flags,
+                          void* workspace, size_t workspace_bytes, void* stream,
+                          rrq_stats* stats);
 
 /* The smooth quadrature rule summed directly over every surface node (the self node of an
  * on-surface target excluded): pot_K[t] = sum_j w_j K(x_t, y_j) density[j] (the far-field
@@ -202,22 +264,28 @@ rrq_status rrq_smooth_potentials(const rrq_plan* plan, const rrq_targets* tg, ui
                                  const double* density, double* pot_S, double* pot_D,
                                  double* pot_Sp, double* pot_Dp, void* stream);
 
-/* Autotuner of the batched form: times rrq_assemble on this near list for every supported
- * tile size (targets per workgroup: 4, 8) and grid size (1024, 2048, 4096 workgroups) with
- * HIP events on `stream`, keeps the fastest in the plan and returns it.  If `cache_path`
- * (HOST, may be NULL) names a readable file written by an earlier call with the same patch
- * orders, its choice is loaded instead of timing; otherwise the choice is written there.
- * Synchronous.  Overwrites the output buffers. */
+/* Autotuner of the batched form: runs the assembly of this near list for every tile size
+ * (targets per workgroup: 4, 8, where the order's LDS allows it) and grid size (512, 1024,
+ * 2048, 4096 persistent workgroups), times every order's tile kernel with HIP events on
+ * `stream`, and keeps for each patch order its own fastest (tile, grid) in the plan.  If
+ * `cache_path` (HOST, may be NULL) names a readable file written by an earlier call with the
+ * same patch orders and counts, its choices are loaded instead of timing; otherwise they are
+ * written there.  Synchronous.  Overwrites the output buffers.  Index i of the per-order
+ * arrays is order 4, 5, 6, 8, 10 for i = 0..4 (0 for absent orders). */
 typedef struct {
-  int32_t tile_targets;
+  int32_t tile_targets;   /* choice of the order with the longest tuned kernel time          */
   int32_t grid;
-  double best_ms;
+  double best_ms;         /* sum over orders of the tuned kernel times                       */
   int32_t from_cache;
+  int32_t order_tile[5];
+  int32_t order_grid[5];
+  double order_ms[5];
 } rrq_tune_result;
 rrq_status rrq_autotune(rrq_plan* plan, const rrq_targets* tg, uint32_t kmask, uint32_t flags,
                         double* out_S, double* out_D, double* out_Sp, double* out_Dp,
-                        const int64_t* pair_off, void* workspace, size_t workspace_bytes,
-                        const char* cache_path, void* stream, rrq_tune_result* result);
+                        int64_t out_len, const int64_t* pair_off, void* workspace,
+                        size_t workspace_bytes, const char* cache_path, void* stream,
+                        rrq_tune_result* result);
 
 /* One whole assembly step (rrq_plan_refit, rrq_pair_offsets, rrq_assemble with the given
  * arguments) captured into a HIP graph; rrq_graph_launch replays it on `stream`.  In the
@@ -227,12 +295,16 @@ rrq_status rrq_autotune(rrq_plan* plan, const rrq_targets* tg, uint32_t kmask, u
  * graph holds the pointers it was created with: the buffers must stay allocated and the
  * sizes unchanged until rrq_graph_destroy; their contents (surface, targets) may change
  * between replays.  Nothing in the captured step allocates memory or issues memset/memcpy
- * nodes. */
+ * nodes.  With patches of several orders the orders' tile kernels are branches of the graph
+ * that run side by side.  rrq_graph_create first runs the step once, eagerly, on a stream of
+ * its own that waits for the work already queued on `stream` (the caller's), then captures
+ * it; it returns when that pass has finished. */
 typedef struct rrq_graph rrq_graph;
 rrq_status rrq_graph_create(rrq_plan* plan, const rrq_surface* surf, const rrq_targets* tg,
                             uint32_t kmask, uint32_t flags, double* out_S, double* out_D,
-                            double* out_Sp, double* out_Dp, int64_t* pair_off,
-                            void* workspace, size_t workspace_bytes, rrq_graph** out);
+                            double* out_Sp, double* out_Dp, int64_t out_len, int64_t* pair_off,
+                            void* workspace, size_t workspace_bytes, void* stream,
+                            rrq_graph** out);
 rrq_status rrq_graph_launch(rrq_graph* g, void* stream);
 rrq_status rrq_graph_destroy(rrq_graph* g);
 

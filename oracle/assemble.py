@@ -26,10 +26,10 @@ def patch_arrays(surface, P):
     return xyz, nrm, wt, edges
 
 
-def fit_patch(surface, P, lsq_solver="qr"):
+def fit_patch(surface, P, lsq_solver="qr", weighted=True):
     q = int(surface["order"][P])
     xyz, nrm, wt, edges = patch_arrays(surface, P)
-    return PatchFit(q, xyz, nrm, edges, lsq_solver)
+    return PatchFit(q, xyz, nrm, edges, lsq_solver, weighted)
 
 
 def pair_offsets(surface, targets):
@@ -41,10 +41,12 @@ def pair_offsets(surface, targets):
     return off
 
 
-def pair_block(surface, targets, fits, t, P, correction=True, onsurf_pv=True, lsq_solver="qr"):
-    """Weights (dict of 4 arrays of length q_P^2) of the near pair (target t, patch P)."""
+def pair_block(surface, targets, fits, t, P, correction=True, onsurf_pv=True, lsq_solver="qr",
+               weighted=True):
+    """Weights (dict of 4 arrays of length q_P^2) of the near pair (target t, patch P).  `fits`
+    caches the patch fits by patch index (one cache per solver and weighting)."""
     if P not in fits:
-        fits[P] = fit_patch(surface, P, lsq_solver)
+        fits[P] = fit_patch(surface, P, lsq_solver, weighted)
     fit = fits[P]
     x = np.asarray(targets["xyz"])[:, t]
     nu_t = np.asarray(targets["nrm"])[:, t]

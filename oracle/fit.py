@@ -126,14 +126,16 @@ class PatchFit:
     M_S  (5 n_p, N): nodal sigma         -> [d; g] of Theorem thm:slpreduction
     """
 
-    def __init__(self, q, node_xyz, node_nrm, edge_samples, lsq_solver="qr"):
+    def __init__(self, q, node_xyz, node_nrm, edge_samples, lsq_solver="qr", weighted=True):
         self.q = q
         self.p = q
         self.frame = Frame(edge_samples, node_nrm)
         self.xl = self.frame.point(node_xyz)
         self.nl = self.frame.vector(node_nrm)
         t, w = gauss_legendre(q)
-        self.lsw = np.outer(w, w).reshape(-1)
+        # least-squares row weights: the tensor GL parameter weights, or all ones (the
+        # unweighted fit; the paper leaves the weighting open)
+        self.lsw = np.outer(w, w).reshape(-1) if weighted else np.ones(q * q)
         H, gH = H_basis(self.p, self.xl)
         self.Hmat = H
         self.gH = gH

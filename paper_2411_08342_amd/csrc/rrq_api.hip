@@ -63,8 +63,8 @@ struct rrq_plan {
   OrderDev od[kMaxQ + 1] = {};
   std::vector<void*> const_bufs;
   double rho_far[kMaxQ + 1] = {};
-  int tile = 8;                 // targets per tile of the batched form
-  int grid[kMaxQ + 1] = {};     // workgroups of the batched kernel per order
+  int tile[kMaxQ + 1] = {};     // targets per tile of the batched form, per order
+  int grid[kMaxQ + 1] = {};     // workgroups of the batched kernel, per order
 
   PlanDev dev() const {
     PlanDev d;
@@ -123,6 +123,8 @@ static rrq_status upload_consts(rrq_plan* p, int q) {
   o.gl_t = (const double*)b;
   if (!up(T.gl_w.data(), T.gl_w.size() * 8, &b)) return RRQ_ERR_OOM;
   o.gl_w = (const double*)b;
+  // least-squares row weights: the q-point GL weights, or ones for the unweighted fit
+  if (p->opt.ls_unweighted) std::fill(T.glq_w.begin(), T.glq_w.end(), 1.0);
   if (!up(T.glq_w.data(), T.glq_w.size() * 8, &b)) return RRQ_ERR_OOM;
   o.glq_w = (const double*)b;
   if (!up(T.LT.data(), T.LT.size() * 8, &b)) return RRQ_ERR_OOM;
@@ -249,8 +251,10 @@ const char* rrq_status_string(rrq_status s) {
     case RRQ_ERR_ARG: return "invalid argument";
     case RRQ_ERR_DEVICE: return "device error";
     case RRQ_ERR_OOM: return "out of device memory";
-    case RRQ_ERR_UNSUPPORTED: return "unsupported order or option";
+    case RRQ_ERR_ILLCONDITIONED: return "ill-conditioned or non-finite patch fit";
+    case RRQ_ERR_UNSUPPORTED: return "unsupported order, size or option";
     case RRQ_ERR_BUFFER: return "buffer too small";
+    case RRQ_ERR_NONFINITE: return "non-finite outputs";
   }
   return "unknown status";
 }
@@ -266,11 +270,26 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
   if (opts) p->opt = *opts;
   if (p->opt.newton_tol <= 0) p->opt.newton_tol = 1e-14;
   if (p->opt.newton_maxit <= 0) p->opt.newton_maxit = 60;
+  if (p->opt.ls_unweighted != 0 && p->opt.ls_unweighted != 1) {
+    delete p;
+    return RRQ_ERR_ARG;
+  }
+  if ((p->opt.ptilde_factor != 0 && p->opt.ptilde_factor != 2) || p->opt.u_rule != 0) {
+    delete p;
+    return RRQ_ERR_UNSUPPORTED;
+  }
+  // the near-edge kernels' panel capacity is sized for the default rho_far of each order
+  if (p->opt.rho_far > 0)
+    for (int P = 0; P < s->npatch; ++P)
+      if (p->opt.rho_far > pow(10.0, 8.0 / (2 * s->order_host[P]))) {
+        delete p;
+        return RRQ_ERR_UNSUPPORTED;
+      }
   if (p->opt.tile_targets != 0 && p->opt.tile_targets != 4 && p->opt.tile_targets != 8) {
     delete p;
     return RRQ_ERR_UNSUPPORTED;
   }
-  p->tile = p->opt.tile_targets > 0 ? p->opt.tile_targets : 4;
+  for (int q = 0; q <= kMaxQ; ++q) p->tile[q] = p->opt.tile_targets > 0 ? p->opt.tile_targets : 4;
   if (p->opt.grid < 0 || p->opt.grid > (1 << 20)) {
     delete p;
     return RRQ_ERR_ARG;
@@ -381,6 +400,8 @@ rrq_status rrq_plan_destroy(rrq_plan* p) {
 
 static rrq_status check_targets(const rrq_plan* p, const rrq_targets* tg) {
   if (!p || !tg || tg->ntarget < 0 || tg->nnz < 0) return RRQ_ERR_ARG;
+  // tile starts are 32-bit pair positions
+  if (tg->nnz >= (int64_t(1) << 31)) return RRQ_ERR_UNSUPPORTED;
   if (tg->ntarget > 0 && (!tg->xyz || !tg->nrm || !tg->self_patch || !tg->self_node ||
                           !tg->near_ptr))
     return RRQ_ERR_ARG;
@@ -388,8 +409,9 @@ static rrq_status check_targets(const rrq_plan* p, const rrq_targets* tg) {
   return RRQ_OK;
 }
 
-static TargetsDev tdev(const rrq_targets* tg) {
+static TargetsDev tdev(const rrq_targets* tg, const unsigned* bad = nullptr) {
   TargetsDev t;
+  t.bad = bad;
   t.T = tg->ntarget;
   t.nnz = tg->nnz;
   t.xyz = tg->xyz;
@@ -401,14 +423,15 @@ static TargetsDev tdev(const rrq_targets* tg) {
   return t;
 }
 
-// workspace layout: owner[nnz] i64 | counters[8] u64 | cnt[P] i32 | fill[P] i32 |
+// workspace layout: owner[nnz] i64 | counters[16] u64 | bad u32 | pflags[nnz] u32 |
+// cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders][xcds] u64 |
 // sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
 // nearf[4 nnz] u8 | pairpot[nnz][4] f64 | pcoef[P][kCoefStride] f64 | nlist[4 nnz] i64 |
 // lamg[4 nnz][lam_stride] f64 (near-edge moments; lam_stride = 2 ptilde_max + 1)
 struct WsLayout {
-  size_t owner, counters, cnt, fill, start, tstart, ntiles, queue, sorted, tiles, part, root,
-      nearf, pairpot, pcoef, nlist, lamg, total;
+  size_t owner, counters, bad, pflags, cnt, fill, start, tstart, ntiles, queue, sorted, tiles,
+      part, root, nearf, pairpot, pcoef, nlist, lamg, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P, int lam_stride) {
@@ -416,7 +439,9 @@ static WsLayout ws_layout(int64_t nnz, int P, int lam_stride) {
   WsLayout w;
   size_t o = 0;
   w.owner = o; o = al(o + n * 8);
-  w.counters = o; o = al(o + 64);
+  w.counters = o; o = al(o + 8 * kNumCounters);
+  w.bad = o; o = al(o + 4);
+  w.pflags = o; o = al(o + n * 4);
   w.cnt = o; o = al(o + (size_t)P * 4);
   w.fill = o; o = al(o + (size_t)P * 4);
   w.start = o; o = al(o + (size_t)(P + 1) * 8);
@@ -458,6 +483,62 @@ rrq_status rrq_plan_fit_condition(const rrq_plan* p, double* cond, void* stream)
   return RRQ_OK;
 }
 
+rrq_status rrq_plan_patch_flags(const rrq_plan* p, double max_cond, int32_t* flags,
+                                void* stream) {
+  if (!p || !flags) return RRQ_ERR_ARG;
+  const double lim = max_cond > 0 ? max_cond : 1e9;
+  hipStream_t st = (hipStream_t)stream;
+  int32_t* dflags = nullptr;
+  if (dalloc(&dflags, p->P) != hipSuccess) return RRQ_ERR_OOM;
+  std::vector<double> cond(2 * (size_t)p->P);
+  const bool ok = launch_patch_check(p->dev(), dflags, st) == hipSuccess &&
+                  hipMemcpyAsync(flags, dflags, (size_t)p->P * 4, hipMemcpyDeviceToHost, st) ==
+                      hipSuccess &&
+                  hipMemcpyAsync(cond.data(), p->fitcond_d, cond.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, st) == hipSuccess &&
+                  hipStreamSynchronize(st) == hipSuccess;
+  (void)hipFree(dflags);
+  if (!ok) return RRQ_ERR_DEVICE;
+  bool any = false;
+  for (int P = 0; P < p->P; ++P) {
+    int32_t f = flags[P] ? 4 : 0;
+    // a NaN estimate is flagged too (!(c <= lim))
+    if (!(cond[2 * (size_t)P] <= lim)) f |= 1;
+    if (!(cond[2 * (size_t)P + 1] <= lim)) f |= 2;
+    flags[P] = f;
+    any |= f != 0;
+  }
+  return any ? RRQ_ERR_ILLCONDITIONED : RRQ_OK;
+}
+
+rrq_status rrq_weights_size(const rrq_plan* p, const rrq_targets* tg, int64_t* nweights,
+                            void* stream) {
+  rrq_status c = check_targets(p, tg);
+  if (c != RRQ_OK) return c;
+  if (!nweights) return RRQ_ERR_ARG;
+  *nweights = 0;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int64_t> ptr((size_t)tg->ntarget + 1);
+  std::vector<int32_t> np((size_t)(tg->nnz > 0 ? tg->nnz : 1));
+  if (hipMemcpyAsync(ptr.data(), tg->near_ptr, ptr.size() * 8, hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      (tg->nnz > 0 && hipMemcpyAsync(np.data(), tg->near_patch, (size_t)tg->nnz * 4,
+                                     hipMemcpyDeviceToHost, st) != hipSuccess) ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return RRQ_ERR_DEVICE;
+  if (ptr[0] != 0 || ptr[(size_t)tg->ntarget] != tg->nnz) return RRQ_ERR_ARG;
+  for (int64_t t = 0; t < tg->ntarget; ++t)
+    if (ptr[(size_t)t] > ptr[(size_t)t + 1]) return RRQ_ERR_ARG;
+  int64_t n = 0;
+  for (int64_t k = 0; k < tg->nnz; ++k) {
+    const int32_t P = np[(size_t)k];
+    if (P < 0 || P >= p->P) return RRQ_ERR_ARG;
+    n += (int64_t)p->order_h[P] * p->order_h[P];
+  }
+  *nweights = n;
+  return RRQ_OK;
+}
+
 rrq_status rrq_workspace_size(const rrq_plan* p, const rrq_targets* tg, size_t* bytes) {
   if (!bytes) return RRQ_ERR_ARG;
   rrq_status c = check_targets(p, tg);
@@ -474,8 +555,20 @@ rrq_status rrq_pair_offsets(const rrq_plan* p, const rrq_targets* tg, int64_t* p
   if (!pair_off || !workspace) return RRQ_ERR_ARG;
   if (workspace_bytes < ws_bytes(p, tg->nnz)) return RRQ_ERR_BUFFER;
   hipStream_t st = (hipStream_t)stream;
-  int64_t* part = (int64_t*)((char*)workspace + ws_layout(p, tg->nnz).part);
-  if (launch_pair_offsets(p->dev(), tdev(tg), pair_off, part, st) != hipSuccess)
+  const WsLayout wl = ws_layout(p, tg->nnz);
+  int64_t* part = (int64_t*)((char*)workspace + wl.part);
+  unsigned* bad = (unsigned*)((char*)workspace + wl.bad);
+  const TargetsDev td = tdev(tg, bad);
+  if (launch_validate(p->dev(), td, nullptr, 0, bad, nullptr, st) != hipSuccess)
+    return RRQ_ERR_DEVICE;
+  if (nweights) {
+    unsigned hbad = 0;
+    if (hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+    if (hbad) return RRQ_ERR_ARG;
+  }
+  if (launch_pair_offsets(p->dev(), td, pair_off, part, st) != hipSuccess)
     return RRQ_ERR_DEVICE;
   if (nweights) {
     if (hipMemcpyAsync(nweights, pair_off + tg->nnz, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -485,18 +578,60 @@ rrq_status rrq_pair_offsets(const rrq_plan* p, const rrq_targets* tg, int64_t* p
   return RRQ_OK;
 }
 
+// Streams and events of the per-order branches of a captured step (owned by the capture).
+struct OrderBranches {
+  hipStream_t stream[kNumOrders];
+  hipEvent_t fork;
+  hipEvent_t join[kNumOrders];
+};
+
+// Timing events around each order's tile kernel (autotuner and statistics).
+struct OrderEvents {
+  hipEvent_t e[kNumOrders][2] = {};
+  hipError_t record(int qi, int which, hipStream_t st) {
+    if (!e[qi][which]) {
+      const hipError_t c = hipEventCreate(&e[qi][which]);
+      if (c != hipSuccess) return c;
+    }
+    return hipEventRecord(e[qi][which], st);
+  }
+  float elapsed(int qi) const {
+    float ms = 0.f;
+    if (e[qi][0] && e[qi][1] && hipEventElapsedTime(&ms, e[qi][0], e[qi][1]) == hipSuccess)
+      return ms;
+    return 0.f;
+  }
+  ~OrderEvents() {
+    for (auto& p : e)
+      for (hipEvent_t x : p)
+        if (x) (void)hipEventDestroy(x);
+  }
+};
+
 // Assembly of the near pairs: weights (outs) or, with a density, the potentials (pots).
 static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
-                            uint32_t flags, double* const* outs, const int64_t* pair_off,
-                            const double* density, double* const* pots, void* workspace,
-                            hipStream_t st, rrq_stats* stats, hipEvent_t maps_ready = nullptr) {
+                            uint32_t flags, double* const* outs, int64_t out_len,
+                            const int64_t* pair_off, const double* density, double* const* pots,
+                            uint32_t* pair_flags, void* workspace, hipStream_t st,
+                            rrq_stats* stats, hipEvent_t maps_ready = nullptr,
+                            const OrderBranches* branches = nullptr,
+                            float* order_ms = nullptr) {
   const bool pot = pots != nullptr;
+  float order_ms_local[kNumOrders] = {};
+  if (stats && !order_ms && !(flags & RRQ_F_PLAIN)) order_ms = order_ms_local;
   const WsLayout wl = ws_layout(p, tg->nnz);
   char* wb = (char*)workspace;
   int64_t* owner = (int64_t*)(wb + wl.owner);
   unsigned long long* counters = (unsigned long long*)(wb + wl.counters);
-  TargetsDev td = tdev(tg);
-  if (launch_owner(td, owner, counters, st) != hipSuccess) return RRQ_ERR_DEVICE;
+  unsigned* bad = (unsigned*)(wb + wl.bad);
+  uint32_t* pflags = pair_flags ? pair_flags : (uint32_t*)(wb + wl.pflags);
+  TargetsDev td = tdev(tg, bad);
+  // device check of the inputs first (it clears the counters); every later kernel returns at
+  // once if it failed
+  if (launch_validate(p->dev(), td, pot ? nullptr : pair_off, out_len, bad, counters, st) !=
+      hipSuccess)
+    return RRQ_ERR_DEVICE;
+  if (launch_owner(td, owner, pflags, st) != hipSuccess) return RRQ_ERR_DEVICE;
   AssembleOut ao;
   for (int K = 0; K < 4; ++K) ao.w[K] = (!pot && (kmask & (1u << K))) ? outs[K] : nullptr;
   ao.kmask = kmask;
@@ -504,6 +639,7 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
   ao.pair_off = pair_off;
   ao.owner = owner;
   ao.counters = counters;
+  ao.pflags = pflags;
   ao.root = nullptr;
   ao.nearf = nullptr;
   ao.lamg = nullptr;
@@ -534,7 +670,13 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       if (launch_pair_plain(q, pd, p->od[q], td, ao, so, st) != hipSuccess) return RRQ_ERR_DEVICE;
     }
   } else {
-    const int tile = p->tile;
+    // targets per tile of each order (the largest supported one not above the plan's choice)
+    BinOrders bo = p->bin_orders;
+    for (int q = 0; q <= kMaxQ; ++q) {
+      int T = p->tile[q] > 0 ? p->tile[q] : 4;
+      while (T > 4 && !tile_supported(q, T)) T /= 2;
+      bo.tile_of_q[q] = T;
+    }
     int32_t* cnt = (int32_t*)(wb + wl.cnt);
     int32_t* fill = (int32_t*)(wb + wl.fill);
     int64_t* start = (int64_t*)(wb + wl.start);
@@ -544,8 +686,8 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
     int4* tiles = (int4*)(wb + wl.tiles);
     int64_t* qtile = (int64_t*)(wb + wl.queue);
     unsigned long long* qctr = (unsigned long long*)(wb + wl.queue + 8 * (kNumOrders + 1));
-    if (launch_binning(td, p->P, tile, p->perm_d, p->bin_orders, cnt, fill, start, tstart,
-                       ntiles, sorted, tiles, qtile, qctr, st) != hipSuccess)
+    if (launch_binning(td, p->P, p->order_d, p->perm_d, bo, cnt, fill, start, tstart, ntiles,
+                       sorted, tiles, qtile, qctr, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
     {
       RootOpts ro;
@@ -558,13 +700,13 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       double* lamg = (double*)(wb + wl.lamg);
       const int lam_stride = lam_stride_of(p);
       if (launch_root(pd, td, owner, ro, (flags & RRQ_F_LEARNED) != 0, root, nearf, nlist,
-                      counters, st) != hipSuccess)
+                      counters, pflags, st) != hipSuccess)
         return RRQ_ERR_DEVICE;
       for (int qi = 0; qi < kNumOrders; ++qi) {
         const int q = kOrders[qi];
         if (p->patches_h[q].empty()) continue;
-        if (launch_lambda(q, pd, p->od[q], td, owner, root, nlist, counters, lamg, lam_stride,
-                          p->rho_far[q], st) != hipSuccess)
+        if (launch_lambda(q, pd, p->od[q], td, owner, root, nlist, counters, pflags, lamg,
+                          lam_stride, p->rho_far[q], st) != hipSuccess)
           return RRQ_ERR_DEVICE;
       }
       ao.root = root;
@@ -577,45 +719,82 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
     if (pot && launch_patch_coef(pd, density, (double*)(wb + wl.pcoef), st) != hipSuccess)
       return RRQ_ERR_DEVICE;
     if (stats && hipEventRecord(ev[0], st) != hipSuccess) return RRQ_ERR_DEVICE;
+    // the orders' tile kernels: one after another on the call's stream (timed per order when
+    // asked), or, in a captured step with several orders, on branches of their own that fork
+    // from and join the call's stream
+    int norders = 0;
+    for (int qi = 0; qi < kNumOrders; ++qi) norders += !p->patches_h[kOrders[qi]].empty();
+    const bool fork = branches != nullptr && norders > 1;
+    if (fork && hipEventRecord(branches->fork, st) != hipSuccess) return RRQ_ERR_DEVICE;
+    OrderEvents oe;
     for (int qi = 0; qi < kNumOrders; ++qi) {
       const int q = kOrders[qi];
       if (p->patches_h[q].empty()) continue;
       SolveOpts so{p->rho_far[q], p->opt.newton_tol, p->opt.newton_maxit};
-      int T = tile;
-      while (T > 4 && !tile_supported(q, T)) T /= 2;
+      const int T = bo.tile_of_q[q];
       if (!tile_supported(q, T)) return RRQ_ERR_UNSUPPORTED;
+      hipStream_t os = st;
+      if (fork) {
+        os = branches->stream[qi];
+        if (hipStreamWaitEvent(os, branches->fork, 0) != hipSuccess) return RRQ_ERR_DEVICE;
+      }
+      if (order_ms && oe.record(qi, 0, os) != hipSuccess) return RRQ_ERR_DEVICE;
       if (launch_pair_tile(q, T, pot, p->grid[q], pd, p->od[q], td, ao, so, tiles, qtile + qi,
-                           qctr + qi * kXcds, sorted, st) != hipSuccess)
+                           qctr + qi * kXcds, sorted, os) != hipSuccess)
         return RRQ_ERR_DEVICE;
+      if (order_ms && oe.record(qi, 1, os) != hipSuccess) return RRQ_ERR_DEVICE;
+      if (fork && (hipEventRecord(branches->join[qi], os) != hipSuccess ||
+                   hipStreamWaitEvent(st, branches->join[qi], 0) != hipSuccess))
+        return RRQ_ERR_DEVICE;
+    }
+    if (order_ms) {
+      if (hipStreamSynchronize(st) != hipSuccess) return RRQ_ERR_DEVICE;
+      for (int qi = 0; qi < kNumOrders; ++qi) order_ms[qi] = oe.elapsed(qi);
     }
     if (pot && launch_pot_reduce(td, kmask, ao.pairpot, pots, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
   }
   if (stats) {
-    unsigned long long h[8];
+    unsigned long long h[kNumCounters];
+    unsigned hbad = 0;
     float ms = 0.f;
     if (hipEventRecord(ev[1], st) != hipSuccess ||
         hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess || hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
       return RRQ_ERR_DEVICE;
+    *stats = rrq_stats{};
     stats->kernel_ms = ms;
     stats->pairs = tg->nnz;
-    stats->near_edges = (int64_t)h[0];
-    stats->newton_iters = (int64_t)h[1];
-    stats->newton_fail = (int64_t)h[2];
-    stats->learned_accept = (int64_t)h[3];
-    stats->newton_max = (int64_t)h[4];
+    stats->invalid = hbad;
+    if (hbad & (kBadNear | kBadSelf | kBadTarget)) return RRQ_ERR_ARG;
+    if (hbad & kBadOffsets) return RRQ_ERR_BUFFER;
+    stats->near_edges = (int64_t)h[kCNear];
+    stats->newton_iters = (int64_t)h[kCIters];
+    stats->newton_fail = (int64_t)h[kCFail];
+    stats->learned_accept = (int64_t)h[kCLearn];
+    stats->newton_max = (int64_t)h[kCMax];
+    stats->newton_wave_iters = (int64_t)h[kCWaveIters];
+    stats->panel_overflow = (int64_t)h[kCOverflow];
+    stats->nonfinite = (int64_t)h[kCNonfinite];
+    stats->flagged_pairs = (int64_t)h[kCFlagged];
+    for (int qi = 0; qi < kNumOrders; ++qi) stats->order_kernel_ms[qi] = order_ms ? order_ms[qi] : 0.0;
+    stats->newton_slots = (int64_t)h[kCNewtonSlots];
+    for (int j = 0; j < 5; ++j) stats->newton_over[j] = (int64_t)h[kCNewtonOver + j];
+    if (h[kCNonfinite]) return RRQ_ERR_NONFINITE;
   }
   return RRQ_OK;
 }
 
 rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
                         uint32_t flags, double* out_S, double* out_D, double* out_Sp,
-                        double* out_Dp, const int64_t* pair_off, void* workspace,
-                        size_t workspace_bytes, void* stream, rrq_stats* stats) {
+                        double* out_Dp, int64_t out_len, const int64_t* pair_off,
+                        uint32_t* pair_flags, void* workspace, size_t workspace_bytes,
+                        void* stream, rrq_stats* stats) {
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
-  if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
+  if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0 || out_len < 0)
+    return RRQ_ERR_ARG;
   if (workspace_bytes < ws_bytes(p, tg->nnz)) return RRQ_ERR_BUFFER;
   double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
   for (int K = 0; K < 4; ++K)
@@ -624,8 +803,8 @@ rrq_status rrq_assemble(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask
     if (flags & RRQ_F_PLAIN) return RRQ_ERR_UNSUPPORTED;
     if (!p->has_mlp) return RRQ_ERR_ARG;
   }
-  return run_pairs(p, tg, kmask, flags, outs, pair_off, nullptr, nullptr, workspace,
-                   (hipStream_t)stream, stats);
+  return run_pairs(p, tg, kmask, flags, outs, out_len, pair_off, nullptr, nullptr, pair_flags,
+                   workspace, (hipStream_t)stream, stats);
 }
 
 }  // extern "C"
@@ -665,10 +844,11 @@ extern "C" {
 
 rrq_status rrq_assemble_noalloc(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
                                 uint32_t flags, double* out_S, double* out_D, double* out_Sp,
-                                double* out_Dp, const int64_t* pair_off, void* stream) {
+                                double* out_Dp, int64_t out_len, const int64_t* pair_off,
+                                uint32_t* pair_flags, void* stream) {
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
-  if (!pair_off || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
+  if (!pair_off || (kmask & ~15u) || kmask == 0 || out_len < 0) return RRQ_ERR_ARG;
   if (ws_bytes(p, tg->nnz) > (size_t)RRQ_NOALLOC_SCRATCH_BYTES) return RRQ_ERR_BUFFER;
   double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
   for (int K = 0; K < 4; ++K)
@@ -682,14 +862,15 @@ rrq_status rrq_assemble_noalloc(const rrq_plan* p, const rrq_targets* tg, uint32
   if (c != RRQ_OK) return c;
   // every part of the workspace that must start at zero (counters, bins, queues) is cleared
   // by the kernels of the assembly itself, so the previous call's contents do not matter
-  return run_pairs(p, tg, kmask, flags, outs, pair_off, nullptr, nullptr, ws,
-                   (hipStream_t)stream, nullptr);
+  return run_pairs(p, tg, kmask, flags, outs, out_len, pair_off, nullptr, nullptr, pair_flags,
+                   ws, (hipStream_t)stream, nullptr);
 }
 
 rrq_status rrq_potentials(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
                           uint32_t flags, const double* density, double* pot_S, double* pot_D,
-                          double* pot_Sp, double* pot_Dp, void* workspace,
-                          size_t workspace_bytes, void* stream, rrq_stats* stats) {
+                          double* pot_Sp, double* pot_Dp, uint32_t* pair_flags,
+                          void* workspace, size_t workspace_bytes, void* stream,
+                          rrq_stats* stats) {
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
   if (!density || !workspace || (kmask & ~15u) || kmask == 0) return RRQ_ERR_ARG;
@@ -699,8 +880,8 @@ rrq_status rrq_potentials(const rrq_plan* p, const rrq_targets* tg, uint32_t kma
     if ((kmask & (1u << K)) && !pots[K]) return RRQ_ERR_ARG;
   if (flags & RRQ_F_PLAIN) return RRQ_ERR_UNSUPPORTED;
   if ((flags & RRQ_F_LEARNED) && !p->has_mlp) return RRQ_ERR_ARG;
-  return run_pairs(p, tg, kmask, flags, nullptr, nullptr, density, pots, workspace,
-                   (hipStream_t)stream, stats);
+  return run_pairs(p, tg, kmask, flags, nullptr, 0, nullptr, density, pots, pair_flags,
+                   workspace, (hipStream_t)stream, stats);
 }
 
 rrq_status rrq_smooth_potentials(const rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
@@ -765,8 +946,10 @@ extern "C" rrq_status rrq_collect_roots(const rrq_plan* p, const rrq_targets* tg
   std::vector<void*> keep;
   int64_t *owner = nullptr, *flag = nullptr, *part = nullptr;
   unsigned long long* counters = nullptr;
-  if (!talloc(keep, &owner, tg->nnz) || !talloc(keep, &counters, 8) ||
-      !talloc(keep, &flag, nslot + 1) || !talloc(keep, &part, scan_partials(nslot))) {
+  unsigned* bad = nullptr;
+  if (!talloc(keep, &owner, tg->nnz) || !talloc(keep, &counters, kNumCounters) ||
+      !talloc(keep, &flag, nslot + 1) || !talloc(keep, &part, scan_partials(nslot)) ||
+      !talloc(keep, &bad, 1)) {
     tfree(keep);
     return RRQ_ERR_OOM;
   }
@@ -775,9 +958,17 @@ extern "C" rrq_status rrq_collect_roots(const rrq_plan* p, const rrq_targets* tg
   co.newton_tol = p->opt.newton_tol;
   co.newton_maxit = p->opt.newton_maxit;
   const PlanDev pd = p->dev();
-  const TargetsDev td = tdev(tg);
+  const TargetsDev td = tdev(tg, bad);
   int64_t total = 0;
-  bool ok = launch_owner(td, owner, counters, st) == hipSuccess &&
+  unsigned hbad = 0;
+  bool ok = launch_validate(pd, td, nullptr, 0, bad, counters, st) == hipSuccess &&
+            hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
+            hipStreamSynchronize(st) == hipSuccess;
+  if (ok && hbad) {
+    tfree(keep);
+    return RRQ_ERR_ARG;
+  }
+  ok = ok && launch_owner(td, owner, nullptr, st) == hipSuccess &&
             hipMemsetAsync(flag, 0, 8, st) == hipSuccess &&
             launch_collect(pd, td, owner, co, 0, flag, cap, feat, dt, t0, st) == hipSuccess &&
             launch_scan_i64(flag, nslot, part, st) == hipSuccess &&
@@ -870,67 +1061,131 @@ static std::string order_key(const rrq_plan* p) {
 
 extern "C" rrq_status rrq_autotune(rrq_plan* p, const rrq_targets* tg, uint32_t kmask,
                                    uint32_t flags, double* out_S, double* out_D, double* out_Sp,
-                                   double* out_Dp, const int64_t* pair_off, void* workspace,
-                                   size_t workspace_bytes, const char* cache_path, void* stream,
+                                   double* out_Dp, int64_t out_len, const int64_t* pair_off,
+                                   void* workspace, size_t workspace_bytes,
+                                   const char* cache_path, void* stream,
                                    rrq_tune_result* result) {
   rrq_status c = check_targets(p, tg);
   if (c != RRQ_OK) return c;
   if (!result) return RRQ_ERR_ARG;
+  if (!pair_off || !workspace || (kmask & ~15u) || kmask == 0 || out_len < 0) return RRQ_ERR_ARG;
+  if (workspace_bytes < ws_bytes(p, tg->nnz)) return RRQ_ERR_BUFFER;
+  double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
+  for (int K = 0; K < 4; ++K)
+    if ((kmask & (1u << K)) && !outs[K]) return RRQ_ERR_ARG;
+  *result = rrq_tune_result{};
   const std::string key = order_key(p);
+  auto finish = [&](int from_cache) {
+    // summary choice: the order with the longest tuned kernel time
+    int big = -1;
+    double total = 0.0;
+    for (int qi = 0; qi < kNumOrders; ++qi) {
+      const int q = kOrders[qi];
+      if (p->patches_h[q].empty()) continue;
+      result->order_tile[qi] = p->tile[q];
+      result->order_grid[qi] = p->grid[q];
+      total += result->order_ms[qi];
+      if (big < 0 || result->order_ms[qi] > result->order_ms[big]) big = qi;
+    }
+    result->tile_targets = big >= 0 ? p->tile[kOrders[big]] : 4;
+    result->grid = big >= 0 ? p->grid[kOrders[big]] : 2048;
+    result->best_ms = total;
+    result->from_cache = from_cache;
+  };
   if (cache_path) {
     FILE* f = fopen(cache_path, "r");
     if (f) {
       char buf[512];
-      int T = 0, G = 0;
-      double ms = 0;
-      if (fgets(buf, sizeof buf, f) && fscanf(f, "%d %d %lf", &T, &G, &ms) == 3 &&
-          std::string(buf) == key + "\n" && (T == 4 || T == 8) && G > 0) {
-        fclose(f);
-        p->tile = T;
-        for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = G;
-        *result = rrq_tune_result{T, G, ms, 1};
-        return RRQ_OK;
+      bool ok = fgets(buf, sizeof buf, f) && std::string(buf) == key + "\n";
+      int tq[kMaxQ + 1] = {}, gq[kMaxQ + 1] = {};
+      double mq[kNumOrders] = {};
+      for (int qi = 0; ok && qi < kNumOrders; ++qi) {
+        const int q = kOrders[qi];
+        if (p->patches_h[q].empty()) continue;
+        int qq = 0, T = 0, G = 0;
+        double ms = 0;
+        ok = fscanf(f, "%d %d %d %lf", &qq, &T, &G, &ms) == 4 && qq == q && (T == 4 || T == 8) &&
+             G > 0 && G <= (1 << 20);
+        tq[q] = T;
+        gq[q] = G;
+        mq[qi] = ms;
       }
       fclose(f);
+      if (ok) {
+        for (int qi = 0; qi < kNumOrders; ++qi) {
+          const int q = kOrders[qi];
+          if (p->patches_h[q].empty()) continue;
+          p->tile[q] = tq[q];
+          p->grid[q] = gq[q];
+          result->order_ms[qi] = mq[qi];
+        }
+        finish(1);
+        return RRQ_OK;
+      }
     }
   }
+  // every (tile, grid) candidate times every order's tile kernel at once (the orders are
+  // separate launches), and each order keeps its own fastest candidate
   hipStream_t st = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RRQ_ERR_DEVICE;
   const int tiles[2] = {4, 8};
-  const int grids[3] = {1024, 2048, 4096};
-  double best = 1e300;
-  int bT = p->tile, bG = p->grid[kOrders[0]];
+  const int grids[4] = {512, 1024, 2048, 4096};
+  double best[kNumOrders];
+  int bT[kNumOrders], bG[kNumOrders];
+  for (int qi = 0; qi < kNumOrders; ++qi) {
+    best[qi] = 1e300;
+    bT[qi] = p->tile[kOrders[qi]];
+    bG[qi] = p->grid[kOrders[qi]];
+  }
   flags &= ~(uint32_t)RRQ_F_PLAIN;
   for (int T : tiles)
     for (int G : grids) {
-      p->tile = T;
-      for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = G;
-      rrq_status r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off,
-                                  workspace, workspace_bytes, stream, nullptr);  // warm
+      for (int q = 0; q <= kMaxQ; ++q) {
+        p->tile[q] = T;
+        p->grid[q] = G;
+      }
+      float ms[kNumOrders] = {};
+      rrq_status r = run_pairs(p, tg, kmask, flags, outs, out_len, pair_off, nullptr, nullptr,
+                               nullptr, workspace, st, nullptr);          // warm
+      if (r == RRQ_OK)
+        r = run_pairs(p, tg, kmask, flags, outs, out_len, pair_off, nullptr, nullptr, nullptr,
+                      workspace, st, nullptr, nullptr, nullptr, ms);
       if (r != RRQ_OK) continue;
-      (void)hipEventRecord(e0, st);
-      r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
-                       workspace_bytes, stream, nullptr);
-      (void)hipEventRecord(e1, st);
-      if (r != RRQ_OK || hipEventSynchronize(e1) != hipSuccess) continue;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) { best = ms; bT = T; bG = G; }
+      for (int qi = 0; qi < kNumOrders; ++qi) {
+        const int q = kOrders[qi];
+        if (p->patches_h[q].empty()) continue;
+        int Te = T;                         // the tile size this order actually ran with
+        while (Te > 4 && !tile_supported(q, Te)) Te /= 2;
+        if (ms[qi] > 0.f && ms[qi] < best[qi]) {
+          best[qi] = ms[qi];
+          bT[qi] = Te;
+          bG[qi] = G;
+        }
+      }
     }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  p->tile = bT;
-  for (int q = 0; q <= kMaxQ; ++q) p->grid[q] = bG;
-  *result = rrq_tune_result{bT, bG, best, 0};
+  bool any = false;
+  for (int qi = 0; qi < kNumOrders; ++qi) {
+    const int q = kOrders[qi];
+    p->tile[q] = bT[qi];
+    p->grid[q] = bG[qi];
+    if (!p->patches_h[q].empty()) {
+      if (best[qi] >= 1e300) return RRQ_ERR_DEVICE;
+      result->order_ms[qi] = best[qi];
+      any = true;
+    }
+  }
+  if (!any) return RRQ_ERR_DEVICE;
+  finish(0);
   if (cache_path) {
     FILE* f = fopen(cache_path, "w");
     if (f) {
-      fprintf(f, "%s\n%d %d %.6f\n", key.c_str(), bT, bG, best);
+      fprintf(f, "%s\n", key.c_str());
+      for (int qi = 0; qi < kNumOrders; ++qi)
+        if (!p->patches_h[kOrders[qi]].empty())
+          fprintf(f, "%d %d %d %.6f\n", kOrders[qi], bT[qi], bG[qi], best[qi]);
       fclose(f);
     }
   }
-  return best < 1e300 ? RRQ_OK : RRQ_ERR_DEVICE;
+  return RRQ_OK;
 }
 
 struct rrq_graph {
@@ -941,8 +1196,8 @@ struct rrq_graph {
 extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const rrq_targets* tg,
                                        uint32_t kmask, uint32_t flags, double* out_S,
                                        double* out_D, double* out_Sp, double* out_Dp,
-                                       int64_t* pair_off, void* workspace,
-                                       size_t workspace_bytes, rrq_graph** out) {
+                                       int64_t out_len, int64_t* pair_off, void* workspace,
+                                       size_t workspace_bytes, void* stream, rrq_graph** out) {
   if (!out || !p) return RRQ_ERR_ARG;
   *out = nullptr;
   rrq_status c = check_targets(p, tg);
@@ -951,12 +1206,24 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   if (c != RRQ_OK) return c;
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RRQ_ERR_DEVICE;
+  // the capture stream starts after the work already queued on the caller's stream
+  {
+    hipEvent_t after = nullptr;
+    const bool ok = hipEventCreateWithFlags(&after, hipEventDisableTiming) == hipSuccess &&
+                    hipEventRecord(after, (hipStream_t)stream) == hipSuccess &&
+                    hipStreamWaitEvent(cs, after, 0) == hipSuccess;
+    if (after) (void)hipEventDestroy(after);
+    if (!ok) {
+      (void)hipStreamDestroy(cs);
+      return RRQ_ERR_DEVICE;
+    }
+  }
   // one eager pass on the capture stream first: kernel attributes are set outside capture
   rrq_status r = rrq_plan_refit(p, s, cs);
   if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, workspace, workspace_bytes, nullptr, cs);
   if (r == RRQ_OK)
-    r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, pair_off, workspace,
-                     workspace_bytes, cs, nullptr);
+    r = rrq_assemble(p, tg, kmask, flags, out_S, out_D, out_Sp, out_Dp, out_len, pair_off,
+                     nullptr, workspace, workspace_bytes, cs, nullptr);
   if (r != RRQ_OK || hipStreamSynchronize(cs) != hipSuccess) {
     (void)hipStreamDestroy(cs);
     return r != RRQ_OK ? r : RRQ_ERR_DEVICE;
@@ -975,6 +1242,12 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   bool ok = hipStreamCreateWithFlags(&ms, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+  // branches of the orders' tile kernels
+  OrderBranches br{};
+  for (int qi = 0; ok && qi < kNumOrders; ++qi)
+    ok = hipStreamCreateWithFlags(&br.stream[qi], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&br.join[qi], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&br.fork, hipEventDisableTiming) == hipSuccess;
   r = ok ? run_geometry(p, s, cs) : RRQ_ERR_DEVICE;
   if (r == RRQ_OK && (hipEventRecord(fork, cs) != hipSuccess ||
                       hipStreamWaitEvent(ms, fork, 0) != hipSuccess))
@@ -985,13 +1258,18 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, workspace, workspace_bytes, nullptr, cs);
   if (r == RRQ_OK) {
     double* outs[4] = {out_S, out_D, out_Sp, out_Dp};
-    r = run_pairs(p, tg, kmask, flags, outs, pair_off, nullptr, nullptr, workspace, cs, nullptr,
-                  join);
+    r = run_pairs(p, tg, kmask, flags, outs, out_len, pair_off, nullptr, nullptr, nullptr,
+                  workspace, cs, nullptr, join, &br);
   }
   hipError_t ec = hipStreamEndCapture(cs, &g->graph);
   if (join) (void)hipEventDestroy(join);
   if (fork) (void)hipEventDestroy(fork);
   if (ms) (void)hipStreamDestroy(ms);
+  if (br.fork) (void)hipEventDestroy(br.fork);
+  for (int qi = 0; qi < kNumOrders; ++qi) {
+    if (br.join[qi]) (void)hipEventDestroy(br.join[qi]);
+    if (br.stream[qi]) (void)hipStreamDestroy(br.stream[qi]);
+  }
   if (r == RRQ_OK && ec == hipSuccess &&
       hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess) {
     (void)hipStreamDestroy(cs);

@@ -28,15 +28,16 @@ __global__ void k_bin_clear(int32_t* cnt, int32_t* fill, int P, unsigned long lo
 }
 
 __global__ void k_bin_count(TargetsDev tg, int32_t* cnt) {
+  if (input_bad(tg)) return;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tg.nnz;
        k += (int64_t)gridDim.x * blockDim.x)
     atomicAdd(&cnt[tg.near_patch[k]], 1);
 }
 
 // exclusive scans of cnt and of ceil(cnt / tile) over patches taken in the order perm
-// (patches grouped by order), one workgroup
+// (patches grouped by order; tile = the targets per tile of the patch's order), one workgroup
 __global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, const int32_t* perm,
-                                                   BinOrders bo, int P, int tile,
+                                                   BinOrders bo, int P,
                                                    int64_t* start, int64_t* tstart,
                                                    int64_t* ntiles, int64_t* qtile) {
   __shared__ int64_t s1[1024], s2[1024];
@@ -46,6 +47,9 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, const int
   for (int base = 0; base < P; base += 1024) {
     const int i = base + threadIdx.x;
     const int pp = i < P ? perm[i] : 0;
+    int tile = 1;
+    for (int qi = 0; qi < kNumOrders; ++qi)
+      if (i >= bo.off[qi] && i < bo.off[qi + 1]) tile = bo.tile_of_q[kOrders[qi]];
     const int64_t a = i < P ? cnt[pp] : 0;
     const int64_t b = i < P ? (cnt[pp] + tile - 1) / tile : 0;
     s1[threadIdx.x] = a;
@@ -78,6 +82,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, const int
 
 __global__ void k_bin_scatter(TargetsDev tg, const int64_t* start, int32_t* fill,
                               int64_t* sorted) {
+  if (input_bad(tg)) return;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tg.nnz;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int P = tg.near_patch[k];
@@ -86,9 +91,10 @@ __global__ void k_bin_scatter(TargetsDev tg, const int64_t* start, int32_t* fill
   }
 }
 
-__global__ void k_bin_tiles(const int32_t* cnt, int P, int tile, const int64_t* start,
-                            const int64_t* tstart, int4* tiles) {
+__global__ void k_bin_tiles(const int32_t* cnt, int P, const int32_t* order, BinOrders bo,
+                            const int64_t* start, const int64_t* tstart, int4* tiles) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+    const int tile = bo.tile_of_q[order[p]];
     const int c = cnt[p];
     const int nt = (c + tile - 1) / tile;
     for (int j = 0; j < nt; ++j) {
@@ -102,20 +108,21 @@ __global__ void k_bin_tiles(const int32_t* cnt, int P, int tile, const int64_t* 
   }
 }
 
-hipError_t launch_binning(const TargetsDev& tg, int P, int tile, const int32_t* perm,
-                          const BinOrders& bo, int32_t* cnt, int32_t* fill, int64_t* start,
-                          int64_t* tstart, int64_t* ntiles, int64_t* sorted, int4* tiles,
-                          int64_t* qtile, unsigned long long* qctr, hipStream_t st) {
+hipError_t launch_binning(const TargetsDev& tg, int P, const int32_t* order,
+                          const int32_t* perm, const BinOrders& bo, int32_t* cnt, int32_t* fill,
+                          int64_t* start, int64_t* tstart, int64_t* ntiles, int64_t* sorted,
+                          int4* tiles, int64_t* qtile, unsigned long long* qctr, hipStream_t st) {
   const int gp = (P + 255) / 256;
   int64_t gk = (tg.nnz + 255) / 256;
   if (gk < 1) gk = 1;
   const unsigned gkk = (unsigned)(gk < 65535 ? gk : 65535);
   hipLaunchKernelGGL(k_bin_clear, dim3(gp), dim3(256), 0, st, cnt, fill, P, qctr);
   hipLaunchKernelGGL(k_bin_count, dim3(gkk), dim3(256), 0, st, tg, cnt);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, cnt, perm, bo, P, tile, start,
-                     tstart, ntiles, qtile);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, cnt, perm, bo, P, start, tstart,
+                     ntiles, qtile);
   hipLaunchKernelGGL(k_bin_scatter, dim3(gkk), dim3(256), 0, st, tg, start, fill, sorted);
-  hipLaunchKernelGGL(k_bin_tiles, dim3(gp), dim3(256), 0, st, cnt, P, tile, start, tstart, tiles);
+  hipLaunchKernelGGL(k_bin_tiles, dim3(gp), dim3(256), 0, st, cnt, P, order, bo, start, tstart,
+                     tiles);
   return hipGetLastError();
 }
 
@@ -255,19 +262,22 @@ constexpr int kLearnedMaxit = 8;
 template <bool LEARNED>
 __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const int64_t* owner,
                                               RootOpts ro, double2* root, uint8_t* nearf,
-                                              int64_t* nlist, unsigned long long* counters) {
+                                              int64_t* nlist, unsigned long long* counters,
+                                              uint32_t* pflags) {
   constexpr int kQ = 1024;               // slots per chunk of a workgroup
+  if (input_bad(tg)) return;
   __shared__ float w[LEARNED ? kMlpParams : 1];
   __shared__ int64_t qslot[kQ];          // chunk slots whose chord root needs Newton
   __shared__ int64_t nslot_l[kQ];        // chunk slots of the singularity-swap class
   __shared__ int qn, nn;
   __shared__ long long nbase;
-  __shared__ unsigned long long cs[5];
+  __shared__ unsigned long long cs[12];
   const int tid = threadIdx.x;
-  if (tid < 5) cs[tid] = 0;
+  if (tid < 12) cs[tid] = 0;
   if (LEARNED)
     for (int i = tid; i < kMlpParams; i += blockDim.x) w[i] = pd.mlp[i];
-  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_learn = 0, c_max = 0;
+  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_learn = 0, c_max = 0, c_wave = 0;
+  unsigned long long c_slots = 0, c_over[5] = {0, 0, 0, 0, 0};
   const int64_t nslot = 4 * tg.nnz;
   for (int64_t base = (int64_t)blockIdx.x * kQ; base < nslot; base += (int64_t)gridDim.x * kQ) {
     __syncthreads();
@@ -302,79 +312,94 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
       }
     }
     __syncthreads();
-    // Newton (from the learned start first, if any) on the queued slots, all lanes busy
+    // Newton (from the learned start first, if any) on the queued slots, all lanes busy; a
+    // wavefront takes as long as its slowest lane, so the largest count of each wavefront is
+    // summed too
     const int nq = qn;
-    for (int i = tid; i < nq; i += blockDim.x) {
-      const int64_t slot = qslot[i];
-      const int64_t k = slot >> 2;
-      const int e = (int)(slot & 3);
-      const int P = tg.near_patch[k];
-      const int q = pd.order[P];
-      const int PT = 2 * q;
-      const int64_t g = owner[k];
-      const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
-      double xl[3];
-      frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
-      const double* cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * PT;
-      cplx ts, tl = mk(0.0, 0.0);
-      bool try_learned = false;
-      if (LEARNED) {
-        float x[kMlpIn];
-        edge_features(cf, PT, xl, x, &ts, 1, pd.E);
-        float h1[kMlpH];
-        for (int u = 0; u < kMlpH; ++u) {
-          float a = w[kMlpB1 + u];
+    for (int i0 = 0; i0 < nq; i0 += blockDim.x) {
+      const int i = i0 + tid;
+      int its_lane = 0;
+      if (i < nq) {
+        const int64_t slot = qslot[i];
+        const int64_t k = slot >> 2;
+        const int e = (int)(slot & 3);
+        const int P = tg.near_patch[k];
+        const int q = pd.order[P];
+        const int PT = 2 * q;
+        const int64_t g = owner[k];
+        const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
+        double xl[3];
+        frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
+        const double* cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * PT;
+        cplx ts, tl = mk(0.0, 0.0);
+        bool try_learned = false;
+        if (LEARNED) {
+          float x[kMlpIn];
+          edge_features(cf, PT, xl, x, &ts, 1, pd.E);
+          float h1[kMlpH];
+          for (int u = 0; u < kMlpH; ++u) {
+            float a = w[kMlpB1 + u];
 #pragma unroll
-          for (int c = 0; c < kMlpIn; ++c) a += w[kMlpW1 + c * kMlpH + u] * x[c];
-          h1[u] = tanhf(a);
-        }
-        float y0 = w[kMlpB3], y1 = w[kMlpB3 + 1];
-        for (int u = 0; u < kMlpH; ++u) {
-          float a = w[kMlpB2 + u];
+            for (int c = 0; c < kMlpIn; ++c) a += w[kMlpW1 + c * kMlpH + u] * x[c];
+            h1[u] = tanhf(a);
+          }
+          float y0 = w[kMlpB3], y1 = w[kMlpB3 + 1];
+          for (int u = 0; u < kMlpH; ++u) {
+            float a = w[kMlpB2 + u];
 #pragma unroll 16
-          for (int kk = 0; kk < kMlpH; ++kk) a += w[kMlpW2 + kk * kMlpH + u] * h1[kk];
-          const float h2 = tanhf(a);
-          y0 += w[kMlpW3 + u] * h2;
-          y1 += w[kMlpW3 + kMlpH + u] * h2;
+            for (int kk = 0; kk < kMlpH; ++kk) a += w[kMlpW2 + kk * kMlpH + u] * h1[kk];
+            const float h2 = tanhf(a);
+            y0 += w[kMlpW3 + u] * h2;
+            y1 += w[kMlpW3 + kMlpH + u] * h2;
+          }
+          tl = mk(ts.re + (double)y0, ts.im + (double)y1);
+          try_learned = isfinite(tl.re) && isfinite(tl.im);
+        } else {
+          double m[3], dv[3];
+          edge_chord(cf, PT, m, dv, 1, pd.E);
+          ts = chord_root(m, dv, xl);
         }
-        tl = mk(ts.re + (double)y0, ts.im + (double)y1);
-        try_learned = isfinite(tl.re) && isfinite(tl.im);
-      } else {
-        double m[3], dv[3];
-        edge_chord(cf, PT, m, dv, 1, pd.E);
-        ts = chord_root(m, dv, xl);
-      }
-      cplx t0 = ts;
-      int near = 0, its_all = 0;
-      for (int attempt = try_learned ? 0 : 1; attempt < 2; ++attempt) {
-        cplx tp = attempt == 0 ? tl : ts;
-        int its;
-        const int conv = newton_solve(cf, PT, xl, &tp, ro.newton_tol,
-                                      attempt == 0 ? kLearnedMaxit : ro.newton_maxit, &its, 1,
-                                      pd.E);
-        its_all += its;
-        if (tp.im < 0) tp.im = -tp.im;
-        const int inside = conv && bernstein_rho(tp) <= ro.rho_far[q];
-        if (attempt == 0) {
-          if (!inside) continue;
-          ++c_learn;
-        } else if (!conv) {
-          ++c_fail;
+        cplx t0 = ts;
+        int near = 0, its_all = 0;
+        for (int attempt = try_learned ? 0 : 1; attempt < 2; ++attempt) {
+          cplx tp = attempt == 0 ? tl : ts;
+          int its;
+          const int conv = newton_solve(cf, PT, xl, &tp, ro.newton_tol,
+                                        attempt == 0 ? kLearnedMaxit : ro.newton_maxit, &its, 1,
+                                        pd.E);
+          its_all += its;
+          if (tp.im < 0) tp.im = -tp.im;
+          const int inside = conv && bernstein_rho(tp) <= ro.rho_far[q];
+          if (attempt == 0) {
+            if (!inside) continue;
+            ++c_learn;
+          } else if (!conv) {
+            ++c_fail;
+            flag_pair(pflags, counters, k, kFlagNewton);
+          }
+          t0 = tp;
+          near = inside;
+          break;
         }
-        t0 = tp;
-        near = inside;
-        break;
+        c_iters += (unsigned long long)its_all;
+        if ((unsigned long long)its_all > c_max) c_max = its_all;
+        c_near += near;
+        root[slot] = make_double2(t0.re, t0.im);
+        nearf[slot] = (uint8_t)near;
+        if (near) nslot_l[atomicAdd(&nn, 1)] = slot;
+        its_lane = its_all;
+        ++c_slots;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) c_over[j] += its_all > kNewtonOver[j];
       }
-      c_iters += (unsigned long long)its_all;
-      if ((unsigned long long)its_all > c_max) c_max = its_all;
-      c_near += near;
-      root[slot] = make_double2(t0.re, t0.im);
-      nearf[slot] = (uint8_t)near;
-      if (near) nslot_l[atomicAdd(&nn, 1)] = slot;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) its_lane = max(its_lane, __shfl_xor(its_lane, o, 64));
+      if ((tid & 63) == 0) c_wave += (unsigned long long)its_lane;
     }
     // the chunk's near slots go to the global list with one reservation per chunk
     __syncthreads();
-    if (tid == 0) nbase = nn > 0 ? (long long)atomicAdd(&counters[5], (unsigned long long)nn) : 0;
+    if (tid == 0)
+      nbase = nn > 0 ? (long long)atomicAdd(&counters[kCNearList], (unsigned long long)nn) : 0;
     __syncthreads();
     for (int i = tid; i < nn; i += blockDim.x) nlist[nbase + i] = nslot_l[i];
   }
@@ -383,25 +408,33 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
   if (c_fail) atomicAdd(&cs[2], c_fail);
   if (c_learn) atomicAdd(&cs[3], c_learn);
   if (c_max) atomicMax(&cs[4], c_max);
+  if (c_wave) atomicAdd(&cs[5], c_wave);
+  if (c_slots) atomicAdd(&cs[6], c_slots);
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+    if (c_over[j]) atomicAdd(&cs[7 + j], c_over[j]);
   __syncthreads();
-  if (tid < 5 && cs[tid]) {
-    if (tid == 4) atomicMax(&counters[4], cs[4]);
-    else atomicAdd(&counters[tid], cs[tid]);
+  if (tid < 12 && cs[tid]) {
+    if (tid == 4) atomicMax(&counters[kCMax], cs[4]);
+    else if (tid < 4) atomicAdd(&counters[tid], cs[tid]);
+    else if (tid == 5) atomicAdd(&counters[kCWaveIters], cs[5]);
+    else atomicAdd(&counters[kCNewtonSlots + (tid - 6)], cs[tid]);
   }
 }
 
 hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
                        const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
-                       int64_t* nlist, unsigned long long* counters, hipStream_t st) {
+                       int64_t* nlist, unsigned long long* counters, uint32_t* pflags,
+                       hipStream_t st) {
   int64_t g = (4 * tg.nnz + 1023) / 1024;
   if (g < 1) g = 1;
   const dim3 grid((unsigned)(g < 4096 ? g : 4096));
   if (learned)
     hipLaunchKernelGGL(k_root<true>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
-                       counters);
+                       counters, pflags);
   else
     hipLaunchKernelGGL(k_root<false>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
-                       counters);
+                       counters, pflags);
   return hipGetLastError();
 }
 
@@ -427,8 +460,9 @@ __device__ __forceinline__ void wave_target_local(const PlanDev& pd, const doubl
     for (int c = 0; c < 3; ++c) u[c] = nl[c];
     return;
   }
+  // bi starts at a valid node, so that non-finite distances still select a node
   double bd = 1e300;
-  int bi = 0x7fffffff;
+  int bi = 0;
   for (int i = lane; i < Q2; i += 64) {
     double d2 = 0;
     for (int c = 0; c < 3; ++c) {
@@ -462,13 +496,9 @@ constexpr int kLamWaves = 4;
 
 template <int Q>
 __global__ __launch_bounds__(64 * kLamWaves) __attribute__((amdgpu_waves_per_eu(3)))
-void k_lambda(PlanDev pd, OrderDev od,
-                                                           TargetsDev tg, const int64_t* owner,
-                                                           const double2* root,
-                                                           const int64_t* nlist,
-                                                           unsigned long long* counters,
-                                                           double* lamg, int lam_stride,
-                                                           double rho_far) {
+void k_lambda(PlanDev pd, OrderDev od, TargetsDev tg, const int64_t* owner, const double2* root,
+              const int64_t* nlist, unsigned long long* counters, uint32_t* pflags,
+              double* lamg, int lam_stride, double rho_far) {
   constexpr int PT = 2 * Q;
   constexpr int NB8 = (PT + 7) / 8;
   constexpr int NPAN = wave_panel_cap(Q);
@@ -483,8 +513,9 @@ void k_lambda(PlanDev pd, OrderDev od,
     cbary[tid] = od.bary1[tid];
   }
   __syncthreads();
-  const int64_t nitems = (int64_t)counters[5];
-  unsigned long long c_fail = 0;
+  if (input_bad(tg)) return;
+  const int64_t nitems = (int64_t)counters[kCNearList];
+  unsigned long long c_over = 0;
   double* fr = sfr[wv];
   double* ecoef = scoef[wv];
   double* wpan = span[wv];
@@ -514,7 +545,10 @@ void k_lambda(PlanDev pd, OrderDev od,
     const double a = r0.x, b = r0.y;
     bool over;
     const int npan = wave_graded_panels(a, b, rho_far, wpan, NPAN, &over);
-    if (over && lane == 0) ++c_fail;
+    if (over && lane == 0) {
+      ++c_over;
+      flag_pair(pflags, counters, slot >> 2, kFlagPanels);
+    }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int npts = npan * PT;
@@ -582,17 +616,17 @@ void k_lambda(PlanDev pd, OrderDev od,
     if (lane == 0) outp[2 * PT] = om;
     __builtin_amdgcn_wave_barrier();
   }
-  if (c_fail) atomicAdd(&counters[2], c_fail);
+  if (c_over) atomicAdd(&counters[kCOverflow], c_over);
 }
 
 hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
                          const int64_t* owner, const double2* root, const int64_t* nlist,
-                         unsigned long long* counters, double* lamg, int lam_stride,
-                         double rho_far, hipStream_t st) {
+                         unsigned long long* counters, uint32_t* pflags, double* lamg,
+                         int lam_stride, double rho_far, hipStream_t st) {
   if (tg.nnz <= 0) return hipSuccess;
   const int grid = 2048;
   switch (q) {
-#define X(Q) case Q: hipLaunchKernelGGL(k_lambda<Q>, dim3(grid), dim3(64 * kLamWaves), 0, st, pd, od, tg, owner, root, nlist, counters, lamg, lam_stride, rho_far); break;
+#define X(Q) case Q: hipLaunchKernelGGL(k_lambda<Q>, dim3(grid), dim3(64 * kLamWaves), 0, st, pd, od, tg, owner, root, nlist, counters, pflags, lamg, lam_stride, rho_far); break;
     X(4) X(5) X(6) X(8) X(10)
 #undef X
     default: return hipErrorInvalidValue;
@@ -671,6 +705,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   int* sself = ints + L::i_self;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (input_bad(tg)) return;
   const int64_t tlo = qtile[0], thi = qtile[1];
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
@@ -1065,8 +1100,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
           a1 = wave_sum(a1);
           a2 = wave_sum(a2);
           a3 = wave_sum(a3);
-          if (lane < 4 && (out.kmask & (1u << lane)))
-            out.pairpot[k * 4 + lane] = lane == 0 ? a0 : (lane == 1 ? a1 : (lane == 2 ? a2 : a3));
+          if (lane < 4 && (out.kmask & (1u << lane))) {
+            const double v = lane == 0 ? a0 : (lane == 1 ? a1 : (lane == 2 ? a2 : a3));
+            if (!isfinite(v)) {
+              atomicAdd(&out.counters[kCNonfinite], 1ull);
+              flag_pair(out.pflags, out.counters, k, kFlagNonfinite);
+            }
+            out.pairpot[k * 4 + lane] = v;
+          }
         }
       } else {
         // ---- Step 8 (matrix rows): weights = rows x maps on the four-block 4x4x4 FP64 MFMA.
@@ -1166,6 +1207,10 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
                 }
                 val -= kv * wj;
               }
+              if (!isfinite(val)) {
+                atomicAdd(&out.counters[kCNonfinite], 1ull);
+                flag_pair(out.pflags, out.counters, sids[t * 3], kFlagNonfinite);
+              }
               out.w[K][sids[t * 3 + 2] + j] = val;
             }
           }
@@ -1244,6 +1289,7 @@ __global__ void k_patch_coef(PlanDev pd, const double* dens, double* pcoef) {
 
 __global__ void k_pot_reduce(TargetsDev tg, uint32_t kmask, const double* pairpot, double* p0,
                              double* p1, double* p2, double* p3) {
+  if (input_bad(tg)) return;
   double* Pp[4] = {p0, p1, p2, p3};
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tg.T;
        t += (int64_t)gridDim.x * blockDim.x)
@@ -1262,8 +1308,9 @@ __global__ void k_smooth_direct(PlanDev pd, TargetsDev tg, uint32_t kmask, const
   for (int64_t t = blockIdx.x; t < tg.T; t += gridDim.x) {
     const double x0 = tg.xyz[t], x1 = tg.xyz[tg.T + t], x2 = tg.xyz[2 * tg.T + t];
     const double nt0 = tg.nrm[t], nt1 = tg.nrm[tg.T + t], nt2 = tg.nrm[2 * tg.T + t];
+    // the self node is skipped only for an in-range index (this call has no validation word)
     const int sp = tg.self_patch[t];
-    const int64_t self = sp >= 0 ? pd.node_off[sp] + tg.self_node[t] : -1;
+    const int64_t self = (sp >= 0 && sp < pd.npatch) ? pd.node_off[sp] + tg.self_node[t] : -1;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t j = threadIdx.x; j < pd.N; j += blockDim.x) {
       if (j == self) continue;

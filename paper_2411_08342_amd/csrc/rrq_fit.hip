@@ -679,4 +679,40 @@ hipError_t launch_fit(const PlanDev& pd, const OrderDev& od, const int32_t* patc
   return hipGetLastError();
 }
 
+// Non-finite entries in a patch's source-only data (frame, local nodes and normals, edge
+// geometry, maps, edge tables): flags[P] = 1 if any, else 0.  One workgroup per patch.
+__global__ void k_patch_check(PlanDev pd, int32_t* flags) {
+  __shared__ int bad;
+  for (int P = blockIdx.x; P < pd.npatch; P += gridDim.x) {
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int q = pd.order[P], q2 = q * q, pt = 2 * q;
+    int b = 0;
+    for (int i = threadIdx.x; i < 13; i += blockDim.x)   // o, ex, ey, ez, s
+      b |= !isfinite(pd.frame[(int64_t)P * kFrame + i]);
+    const int64_t n0 = pd.node_off[P], e0 = pd.edge_off[P];
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x)
+      b |= !isfinite(pd.node_loc[(int64_t)(i / q2) * pd.N + n0 + i % q2]);
+    for (int i = threadIdx.x; i < 9 * 4 * pt; i += blockDim.x) {
+      const int a = i / (12 * pt), r = i % (12 * pt);
+      const double* arr = a == 0 ? pd.edge_loc : (a == 1 ? pd.edge_tan : pd.edge_coef);
+      b |= !isfinite(arr[(int64_t)(r / (4 * pt)) * pd.E + e0 + r % (4 * pt)]);
+    }
+    const double* M = pd.maps + pd.map_off[P];
+    for (int64_t i = threadIdx.x; i < map_doubles(q); i += blockDim.x) b |= !isfinite(M[i]);
+    const double* tb = pd.tabs + pd.tab_off[P];
+    for (int64_t i = threadIdx.x; i < tab_doubles(q); i += blockDim.x) b |= !isfinite(tb[i]);
+    if (b) atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) flags[P] = bad;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_patch_check(const PlanDev& pd, int32_t* flags, hipStream_t st) {
+  const int grid = pd.npatch < 4096 ? pd.npatch : 4096;
+  hipLaunchKernelGGL(k_patch_check, dim3(grid), dim3(256), 0, st, pd, flags);
+  return hipGetLastError();
+}
+
 }  // namespace rrq

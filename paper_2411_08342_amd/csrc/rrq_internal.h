@@ -66,14 +66,48 @@ struct TargetsDev {
   const int32_t* self_node;
   const int64_t* near_ptr;
   const int32_t* near_patch;
+  // validation word of the call (in its workspace), or null: non-zero when the near list,
+  // the self indices or the pair offsets failed the device check (kBad* bits); every kernel
+  // that indexes with them then returns at once
+  const unsigned* bad;
 };
+enum : unsigned { kBadNear = 1u, kBadSelf = 2u, kBadOffsets = 4u, kBadTarget = 8u };
+__device__ __forceinline__ bool input_bad(const TargetsDev& tg) {
+  return tg.bad != nullptr && *(const volatile unsigned*)tg.bad != 0u;
+}
+
+// statistics counters of a call (workspace): indices
+enum {
+  kCNear = 0,        // (pair, edge) slots integrated by singularity swap
+  kCIters = 1,       // Newton iterations
+  kCFail = 2,        // Newton solves that did not converge (plain rule used)
+  kCLearn = 3,       // learned starts accepted
+  kCMax = 4,         // largest iteration count of one slot
+  kCNearList = 5,    // length of the near-slot list (root pre-pass -> near-edge moments)
+  kCOverflow = 6,    // near slots whose graded panels exceeded the capacity
+  kCNonfinite = 7,   // non-finite outputs (weights or pair potentials)
+  kCFlagged = 8,     // pairs with a non-zero flag word
+  kCWaveIters = 9,   // sum over wavefronts of the largest Newton iteration count of a lane
+  kCNewtonSlots = 10,  // slots that ran Newton
+  kCNewtonOver = 11,   // [5]: of those, the ones that took more than kNewtonOver[i] iterations
+  kNumCounters = 16
+};
+constexpr int kNewtonOver[5] = {2, 4, 6, 8, 12};
+// per-pair flag bits (rrq_assemble's pair_flags)
+enum : uint32_t { kFlagNewton = 1u, kFlagPanels = 2u, kFlagNonfinite = 4u };
+__device__ __forceinline__ void flag_pair(uint32_t* pf, unsigned long long* counters, int64_t k,
+                                          uint32_t bit) {
+  if (pf == nullptr) return;
+  if (atomicOr(pf + k, bit) == 0u) atomicAdd(&counters[kCFlagged], 1ull);
+}
 
 struct AssembleOut {
   double* w[4];      // S, D, Sp, Dp
   uint32_t kmask, flags;
   const int64_t* pair_off;
   const int64_t* owner;     // [nnz] target of each pair
-  unsigned long long* counters;   // [8] stats
+  unsigned long long* counters;   // [kNumCounters] stats
+  uint32_t* pflags;         // [nnz] per-pair flag words (kFlag* bits)
   const double2* root;      // [4 nnz] singularity-swap roots t0 (root pre-pass)
   const uint8_t* nearf;     // [4 nnz] 1: singularity-swap class, 0: plain rule
   const double* lamg;       // [4 nnz][lam_stride] near-edge moments (near slots only)
@@ -97,7 +131,13 @@ hipError_t launch_edge_tables(const PlanDev& pd, const OrderDev& od, const int32
                               int count, hipStream_t st);
 hipError_t launch_fit(const PlanDev& pd, const OrderDev& od, const int32_t* patches, int count,
                       double* ws, int64_t ws_per_block, int blocks, hipStream_t st);
-hipError_t launch_owner(const TargetsDev& tg, int64_t* owner, unsigned long long* counters,
+// device check of the near list and self indices (and, with pair_off, of the pair offsets
+// against out_len) into *bad; clears *bad and the counters (if given) first
+hipError_t launch_validate(const PlanDev& pd, const TargetsDev& tg, const int64_t* pair_off,
+                           int64_t out_len, unsigned* bad, unsigned long long* counters,
+                           hipStream_t st);
+// owner[k] = target of near pair k; pflags[k] = 0 (if given)
+hipError_t launch_owner(const TargetsDev& tg, int64_t* owner, uint32_t* pflags,
                         hipStream_t st);
 hipError_t launch_pair_offsets(const PlanDev& pd, const TargetsDev& tg, int64_t* pair_off,
                                int64_t* part, hipStream_t st);
@@ -119,13 +159,14 @@ hipError_t launch_apply(const PlanDev& pd, const TargetsDev& tg, const double* c
 constexpr int kXcds = 8;
 
 struct BinOrders {
-  int32_t off[kNumOrders + 1];
+  int32_t off[kNumOrders + 1];     // first position of each order's patches in perm
+  int32_t tile_of_q[kMaxQ + 1];    // targets per tile for the patches of order q
 };
 
-hipError_t launch_binning(const TargetsDev& tg, int P, int tile, const int32_t* perm,
-                          const BinOrders& bo, int32_t* cnt, int32_t* fill, int64_t* start,
-                          int64_t* tstart, int64_t* ntiles, int64_t* sorted, int4* tiles,
-                          int64_t* qtile, unsigned long long* qctr, hipStream_t st);
+hipError_t launch_binning(const TargetsDev& tg, int P, const int32_t* order,
+                          const int32_t* perm, const BinOrders& bo, int32_t* cnt, int32_t* fill,
+                          int64_t* start, int64_t* tstart, int64_t* ntiles, int64_t* sorted,
+                          int4* tiles, int64_t* qtile, unsigned long long* qctr, hipStream_t st);
 hipError_t launch_pair_tile(int q, int T, bool pot, int grid, const PlanDev& pd,
                             const OrderDev& od, const TargetsDev& tg, const AssembleOut& out,
                             const SolveOpts& so, const int4* tiles, const int64_t* qtile,
@@ -139,6 +180,8 @@ size_t tile_lds_bytes(int q, int T);
 int tile_supported(int q, int T);
 
 int64_t fit_ws_doubles(int q);
+// flags[P] = 1 if the patch's frame, local geometry, maps or edge tables hold a NaN or Inf
+hipError_t launch_patch_check(const PlanDev& pd, int32_t* flags, hipStream_t st);
 
 struct RootOpts {
   double rho_far[kMaxQ + 1];
@@ -147,13 +190,14 @@ struct RootOpts {
 };
 hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
                        const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
-                       int64_t* nlist, unsigned long long* counters, hipStream_t st);
+                       int64_t* nlist, unsigned long long* counters, uint32_t* pflags,
+                       hipStream_t st);
 // near-edge moments of every singularity-swap slot listed by the root pre-pass (counters[5]
 // of them), for the patches of order q
 hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
                          const int64_t* owner, const double2* root, const int64_t* nlist,
-                         unsigned long long* counters, double* lamg, int lam_stride,
-                         double rho_far, hipStream_t st);
+                         unsigned long long* counters, uint32_t* pflags, double* lamg,
+                         int lam_stride, double rho_far, hipStream_t st);
 
 // learned initial guess: sample collection and training
 struct CollectOpts {

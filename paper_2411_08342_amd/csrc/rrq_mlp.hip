@@ -23,6 +23,7 @@ namespace rrq {
 __global__ void k_collect(PlanDev pd, TargetsDev tg, const int64_t* owner, CollectOpts co,
                           int pass, int64_t* flag, int64_t cap, float* feat, float* dt,
                           double* t0out) {
+  if (input_bad(tg)) return;
   const int64_t nslot = 4 * tg.nnz;
   for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < nslot;
        slot += (int64_t)gridDim.x * blockDim.x) {

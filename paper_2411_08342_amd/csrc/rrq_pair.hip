@@ -7,27 +7,96 @@
 namespace rrq {
 
 constexpr int PNT = 256;
-constexpr int kMaxPanels = 256;
+// panel capacity per near edge of the plain form: the largest of the batched form's
+// per-order capacities (wave_panel_cap), so that both forms keep the same leaves
+constexpr int kMaxPanels = 320;
 
-// owner[k] = target of near pair k; also clears the statistics counters
-__global__ void k_owner(TargetsDev tg, int64_t* owner, unsigned long long* counters) {
-  if (blockIdx.x == 0 && threadIdx.x < 8) counters[threadIdx.x] = 0ull;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tg.T;
-       t += (int64_t)gridDim.x * blockDim.x)
-    for (int64_t k = tg.near_ptr[t]; k < tg.near_ptr[t + 1]; ++k) owner[k] = t;
+// ---------------------------------------------------------------------------------------
+// device check of the caller's targets, near list, self indices and pair offsets.  Bits of
+// *bad: kBadNear (row pointer not from 0 to nnz or decreasing, patch index out of range),
+// kBadSelf (self_patch outside [-1, P), or self_node outside the self patch's nodes),
+// kBadTarget (a target point or normal not finite), kBadOffsets
+// (pair_off[0] != 0, a block size other than q_P^2, or pair_off[nnz] > out_len).  Only
+// in-range entries are read: near_ptr[0..T], near_patch[0..nnz), self_*[0..T),
+// pair_off[0..nnz].
+// ---------------------------------------------------------------------------------------
+__global__ void k_validate_clear(unsigned* bad, unsigned long long* counters) {
+  if (threadIdx.x == 0) *bad = 0u;
+  if (counters != nullptr && threadIdx.x < kNumCounters) counters[threadIdx.x] = 0ull;
 }
 
-hipError_t launch_owner(const TargetsDev& tg, int64_t* owner, unsigned long long* counters,
+__global__ void k_validate(PlanDev pd, TargetsDev tg, const int64_t* pair_off, int64_t out_len,
+                           unsigned* bad) {
+  unsigned f = 0u;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t t = gid; t <= tg.T; t += stride) {
+    const int64_t a = tg.near_ptr[t];
+    if (t == 0 && a != 0) f |= kBadNear;
+    if (t == tg.T) {
+      if (a != tg.nnz) f |= kBadNear;
+    } else {
+      if (a > tg.near_ptr[t + 1]) f |= kBadNear;
+      for (int c = 0; c < 3; ++c)
+        if (!isfinite(tg.xyz[c * tg.T + t]) || !isfinite(tg.nrm[c * tg.T + t])) f |= kBadTarget;
+      const int sp = tg.self_patch[t];
+      if (sp < -1 || sp >= pd.npatch) {
+        f |= kBadSelf;
+      } else if (sp >= 0) {
+        const int q = pd.order[sp], sn = tg.self_node[t];
+        if (sn < 0 || sn >= q * q) f |= kBadSelf;
+      }
+    }
+  }
+  for (int64_t k = gid; k < tg.nnz; k += stride) {
+    const int P = tg.near_patch[k];
+    if (P < 0 || P >= pd.npatch) {
+      f |= kBadNear;
+    } else if (pair_off != nullptr) {
+      const int q = pd.order[P];
+      if (pair_off[k + 1] - pair_off[k] != (int64_t)q * q) f |= kBadOffsets;
+    }
+  }
+  if (pair_off != nullptr && gid == 0 && (pair_off[0] != 0 || pair_off[tg.nnz] > out_len))
+    f |= kBadOffsets;
+  if (f) atomicOr(bad, f);
+}
+
+hipError_t launch_validate(const PlanDev& pd, const TargetsDev& tg, const int64_t* pair_off,
+                           int64_t out_len, unsigned* bad, unsigned long long* counters,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_validate_clear, dim3(1), dim3(64), 0, st, bad, counters);
+  const int64_t n = (tg.T + 1 > tg.nnz ? tg.T + 1 : tg.nnz);
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, st, pd,
+                     tg, pair_off, out_len, bad);
+  return hipGetLastError();
+}
+
+// owner[k] = target of near pair k; pflags[k] = 0
+__global__ void k_owner(TargetsDev tg, int64_t* owner, uint32_t* pflags) {
+  if (input_bad(tg)) return;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tg.T;
+       t += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t k = tg.near_ptr[t]; k < tg.near_ptr[t + 1]; ++k) {
+      owner[k] = t;
+      if (pflags != nullptr) pflags[k] = 0u;
+    }
+}
+
+hipError_t launch_owner(const TargetsDev& tg, int64_t* owner, uint32_t* pflags,
                         hipStream_t st) {
   int64_t g = (tg.T + 255) / 256;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_owner, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st, tg,
-                     owner, counters);
+                     owner, pflags);
   return hipGetLastError();
 }
 
 // pair sizes q_P^2, then an inclusive scan
 __global__ void k_pair_sizes(PlanDev pd, TargetsDev tg, int64_t* off) {
+  if (input_bad(tg)) return;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tg.nnz;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int q = pd.order[tg.near_patch[k]];
@@ -157,6 +226,7 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
   constexpr int PT = 2 * Q, NP = np_of(Q), NJK = njk_of(Q), Q2 = Q * Q;
   __shared__ PairSmem<Q> S;
   const int tid = threadIdx.x;
+  if (input_bad(tg)) return;
   for (int64_t k = blockIdx.x; k < tg.nnz; k += gridDim.x) {
     const int P = tg.near_patch[k];
     if (pd.order[P] != Q) continue;
@@ -192,8 +262,9 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
     if (self >= 0) {
       if (tid < 3) S.u[tid] = S.nu[tid];
     } else {
+      // bi starts at a valid node, so that non-finite distances still select a node
       double bd = 1e300;
-      int bi = 1 << 30;
+      int bi = 0;
       for (int i = tid; i < Q2; i += PNT) {
         double d2 = 0;
         for (int c = 0; c < 3; ++c) {
@@ -269,15 +340,18 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
         if (its > so.newton_maxit) its = so.newton_maxit;
         if (t0.im < 0) t0.im = -t0.im;
         if (conv && bernstein_rho(t0) <= so.rho_far) near = 1;
-        atomicAdd(&out.counters[1], (unsigned long long)its);
-        if (!conv) atomicAdd(&out.counters[2], 1ull);
-        atomicMax(&out.counters[4], (unsigned long long)its);
+        atomicAdd(&out.counters[kCIters], (unsigned long long)its);
+        if (!conv) {
+          atomicAdd(&out.counters[kCFail], 1ull);
+          flag_pair(out.pflags, out.counters, k, kFlagNewton);
+        }
+        atomicMax(&out.counters[kCMax], (unsigned long long)its);
       }
       S.near[e] = near;
       S.t0[e][0] = t0.re;
       S.t0[e][1] = t0.im;
       if (near) {
-        atomicAdd(&out.counters[0], 1ull);
+        atomicAdd(&out.counters[kCNear], 1ull);
         // graded panels: dyadic bisection toward Re t0 until every panel sees t0 at
         // Bernstein radius >= rho_far in its own scaled coordinate
         double stk[64][3];
@@ -295,7 +369,8 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
               S.pan[e][np_][1] = hi;
               ++np_;
             } else {
-              atomicAdd(&out.counters[2], 1ull);
+              atomicAdd(&out.counters[kCOverflow], 1ull);
+              flag_pair(out.pflags, out.counters, k, kFlagPanels);
             }
           } else {
             stk[sp][0] = c; stk[sp][1] = hi; stk[sp][2] = lev + 1; ++sp;
@@ -593,6 +668,10 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
         else kv = (v0 * nt0 + v1 * nt1 + v2 * nt2) / R3 - 3.0 * dn * dnt / (R3 * R2);
         acc -= kv * wj;
       }
+      if (!isfinite(acc)) {
+        atomicAdd(&out.counters[kCNonfinite], 1ull);
+        flag_pair(out.pflags, out.counters, k, kFlagNonfinite);
+      }
       out.w[K][ob + j] = acc;
     }
   }
@@ -628,8 +707,13 @@ __global__ void k_apply(PlanDev pd, TargetsDev tg, const double* w0, const doubl
   for (int K = 0; K < 4; ++K) {
     if (!(kmask & (1u << K)) || W[K] == nullptr || Pp[K] == nullptr) continue;
     double acc = 0.0;
-    for (int64_t k = tg.near_ptr[t]; k < tg.near_ptr[t + 1]; ++k) {
+    // the row range and patch indices are clamped to the arrays' sizes (this call has no
+    // validation word; rrq_pair_offsets checks the near list)
+    const int64_t k0 = tg.near_ptr[t] > 0 ? tg.near_ptr[t] : 0;
+    const int64_t k1 = tg.near_ptr[t + 1] < tg.nnz ? tg.near_ptr[t + 1] : tg.nnz;
+    for (int64_t k = k0; k < k1; ++k) {
       const int P = tg.near_patch[k];
+      if (P < 0 || P >= pd.npatch) continue;
       const int q2 = pd.order[P] * pd.order[P];
       const int64_t n0 = pd.node_off[P], ob = pair_off[k];
       for (int j = threadIdx.x; j < q2; j += blockDim.x) acc += W[K][ob + j] * dens[n0 + j];

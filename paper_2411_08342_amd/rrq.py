@@ -22,12 +22,20 @@ EXPORTED = ("rrq_plan_create", "rrq_plan_refit", "rrq_plan_destroy", "rrq_worksp
             "rrq_graph_launch", "rrq_graph_destroy", "rrq_collect_roots", "rrq_mlp_train",
             "rrq_mlp_loss_grad", "rrq_mlp_predict", "rrq_plan_set_mlp", "rrq_potentials",
             "rrq_smooth_potentials", "rrq_plan_fit_condition", "rrq_assemble_noalloc",
-            "rrq_status_string")
+            "rrq_plan_patch_flags", "rrq_weights_size", "rrq_status_string")
+RRQ_ERR_ARG, RRQ_ERR_DEVICE, RRQ_ERR_OOM, RRQ_ERR_ILLCONDITIONED = -1, -2, -3, -4
+RRQ_ERR_UNSUPPORTED, RRQ_ERR_BUFFER, RRQ_ERR_NONFINITE = -5, -6, -7
 MLP_PARAMS = 4866
 
 
 class RRQError(RuntimeError):
-    pass
+    """A non-zero rrq_status; `code` is the status, `stats` the statistics of the call when it
+    took any."""
+
+    def __init__(self, msg, code=0, stats=None):
+        super().__init__(msg)
+        self.code = code
+        self.stats = stats
 
 
 class Surface(ctypes.Structure):
@@ -49,18 +57,37 @@ class Targets(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("rho_far", ctypes.c_double), ("newton_tol", ctypes.c_double),
                 ("newton_maxit", ctypes.c_int32), ("tile_targets", ctypes.c_int32),
-                ("grid", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("ls_unweighted", ctypes.c_int32),
+                ("ptilde_factor", ctypes.c_int32), ("u_rule", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("near_edges", ctypes.c_int64),
                 ("newton_iters", ctypes.c_int64), ("newton_fail", ctypes.c_int64),
                 ("learned_accept", ctypes.c_int64), ("newton_max", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("newton_wave_iters", ctypes.c_int64),
+                ("panel_overflow", ctypes.c_int64), ("nonfinite", ctypes.c_int64),
+                ("flagged_pairs", ctypes.c_int64), ("invalid", ctypes.c_uint32),
+                ("order_kernel_ms", ctypes.c_double * 5),
+                ("newton_slots", ctypes.c_int64), ("newton_over", ctypes.c_int64 * 5)]
+    NEWTON_OVER = (2, 4, 6, 8, 12)
 
     def as_dict(self):
-        return {k: (float(getattr(self, k)) if k == "kernel_ms" else int(getattr(self, k)))
-                for k, _ in self._fields_}
+        return _struct_dict(self)
+
+
+ORDERS = (4, 5, 6, 8, 10)   # index of the per-order arrays of Stats and TuneResult
+
+
+def _struct_dict(st):
+    d = {}
+    for k, t in st._fields_:
+        v = getattr(st, k)
+        if hasattr(v, "__len__"):
+            d[k] = [float(x) if isinstance(x, float) else int(x) for x in v]
+        else:
+            d[k] = float(v) if isinstance(v, float) else int(v)
+    return d
 
 
 class MlpCfg(ctypes.Structure):
@@ -70,7 +97,9 @@ class MlpCfg(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("tile_targets", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("best_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+                ("best_ms", ctypes.c_double), ("from_cache", ctypes.c_int32),
+                ("order_tile", ctypes.c_int32 * 5), ("order_grid", ctypes.c_int32 * 5),
+                ("order_ms", ctypes.c_double * 5)]
 
 
 _lib = None
@@ -89,24 +118,26 @@ def lib():
         L.rrq_plan_refit.argtypes = [vp, ctypes.POINTER(Surface), vp]
         L.rrq_plan_destroy.argtypes = [vp]
         L.rrq_plan_fit_condition.argtypes = [vp, vp, vp]
+        L.rrq_plan_patch_flags.argtypes = [vp, ctypes.c_double, vp, vp]
+        L.rrq_weights_size.argtypes = [vp, ctypes.POINTER(Targets), ctypes.POINTER(i64), vp]
         L.rrq_workspace_size.argtypes = [vp, ctypes.POINTER(Targets), ctypes.POINTER(ctypes.c_size_t)]
         L.rrq_pair_offsets.argtypes = [vp, ctypes.POINTER(Targets), vp, vp, ctypes.c_size_t,
                                        ctypes.POINTER(i64), vp]
-        L.rrq_assemble.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp, vp,
-                                   ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
+        L.rrq_assemble.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, i64,
+                                   vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
         L.rrq_assemble_noalloc.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp,
-                                           vp, vp, vp]
+                                           vp, i64, vp, vp, vp]
         L.rrq_apply.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp]
         L.rrq_potentials.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp,
-                                     vp, ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
+                                     vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(Stats)]
         L.rrq_smooth_potentials.argtypes = [vp, ctypes.POINTER(Targets), u32, vp, vp, vp, vp, vp,
                                             vp]
-        L.rrq_autotune.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, vp, vp,
-                                   ctypes.c_size_t, ctypes.c_char_p, vp,
+        L.rrq_autotune.argtypes = [vp, ctypes.POINTER(Targets), u32, u32, vp, vp, vp, vp, i64,
+                                   vp, vp, ctypes.c_size_t, ctypes.c_char_p, vp,
                                    ctypes.POINTER(TuneResult)]
         L.rrq_graph_create.argtypes = [vp, ctypes.POINTER(Surface), ctypes.POINTER(Targets), u32,
-                                       u32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                       u32, vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp,
                                        ctypes.POINTER(vp)]
         L.rrq_graph_launch.argtypes = [vp, vp]
         L.rrq_graph_destroy.argtypes = [vp]
@@ -125,9 +156,10 @@ def lib():
     return _lib
 
 
-def _check(rc):
+def _check(rc, stats=None):
     if rc != 0:
-        raise RRQError(f"rrq call failed: {rc} ({lib().rrq_status_string(rc).decode()})")
+        raise RRQError(f"rrq call failed: {rc} ({lib().rrq_status_string(rc).decode()})", rc,
+                       stats.as_dict() if stats is not None else None)
 
 
 def _stream():
@@ -185,10 +217,11 @@ class Plan:
     """rrq_plan: per-patch frames, coefficient maps and edge tables on the device."""
 
     def __init__(self, dsurf, rho_far=0.0, newton_tol=0.0, newton_maxit=0, tile_targets=0,
-                 grid=0):
+                 grid=0, ls_unweighted=0, ptilde_factor=0, u_rule=0):
         self.dsurf = dsurf
         self._s = dsurf.cstruct()
-        self._o = Options(rho_far, newton_tol, newton_maxit, tile_targets, grid)
+        self._o = Options(rho_far, newton_tol, newton_maxit, tile_targets, grid, ls_unweighted,
+                          ptilde_factor, u_rule)
         h = ctypes.c_void_p()
         _check(lib().rrq_plan_create(ctypes.byref(self._s), ctypes.byref(self._o), _stream(),
                                      ctypes.byref(h)))
@@ -204,6 +237,15 @@ class Plan:
         out = np.zeros((self.dsurf.npatch, 2))
         _check(lib().rrq_plan_fit_condition(self.handle, out.ctypes.data, _stream()))
         return out
+
+    def patch_flags(self, max_cond=0.0):
+        """rrq_plan_patch_flags: (status, int32 host array [P]) with bit 1 / 2 = DLP / SLP fit
+        condition estimate above max_cond, bit 4 = non-finite source data."""
+        out = np.zeros(self.dsurf.npatch, dtype=np.int32)
+        rc = lib().rrq_plan_patch_flags(self.handle, max_cond, out.ctypes.data, _stream())
+        if rc not in (0, RRQ_ERR_ILLCONDITIONED):
+            _check(rc)
+        return rc, out
 
     def refit(self, dsurf=None):
         if dsurf is not None:
@@ -224,21 +266,26 @@ class Plan:
 
 
 class Assembler:
-    """Pair offsets, workspace and output buffers for one near list."""
+    """Pair offsets, workspace, output buffers and per-pair flags for one near list."""
 
     def __init__(self, plan, dtg, kmask=RRQ_K_ALL):
         import torch
         self.plan, self.dtg, self.kmask = plan, dtg, kmask
         self._t = dtg.cstruct()
+        nw = ctypes.c_int64()
+        _check(lib().rrq_weights_size(plan.handle, ctypes.byref(self._t), ctypes.byref(nw),
+                                      _stream()))
+        self.nweights = int(nw.value)
         self.pair_off = torch.empty(dtg.nnz + 1, dtype=torch.int64, device="cuda")
+        self.pair_flags = torch.zeros(max(dtg.nnz, 1), dtype=torch.int32, device="cuda")
         sz = ctypes.c_size_t()
         _check(lib().rrq_workspace_size(plan.handle, ctypes.byref(self._t), ctypes.byref(sz)))
         self.workspace = torch.empty(int(sz.value), dtype=torch.uint8, device="cuda")
-        nw = ctypes.c_int64()
+        nw2 = ctypes.c_int64()
         _check(lib().rrq_pair_offsets(plan.handle, ctypes.byref(self._t), self.pair_off.data_ptr(),
                                       self.workspace.data_ptr(), self.workspace.numel(),
-                                      ctypes.byref(nw), _stream()))
-        self.nweights = int(nw.value)
+                                      ctypes.byref(nw2), _stream()))
+        assert int(nw2.value) == self.nweights
         self.out = {k: (torch.empty(self.nweights, dtype=torch.float64, device="cuda")
                         if kmask & (1 << i) else None) for i, k in enumerate(KERNELS)}
 
@@ -248,12 +295,16 @@ class Assembler:
                                       self.workspace.numel(), None, _stream()))
 
     def assemble(self, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV, stats=False):
+        """rrq_assemble into self.out (and the per-pair flags into self.pair_flags); with
+        stats, synchronises and returns the statistics (a failed device check or NaN/Inf
+        outputs raise RRQError carrying them)."""
         st = Stats() if stats else None
         ptr = [self.out[k].data_ptr() if self.out[k] is not None else None for k in KERNELS]
         _check(lib().rrq_assemble(self.plan.handle, ctypes.byref(self._t), self.kmask, flags,
-                                  ptr[0], ptr[1], ptr[2], ptr[3], self.pair_off.data_ptr(),
+                                  ptr[0], ptr[1], ptr[2], ptr[3], self.nweights,
+                                  self.pair_off.data_ptr(), self.pair_flags.data_ptr(),
                                   self.workspace.data_ptr(), self.workspace.numel(), _stream(),
-                                  ctypes.byref(st) if st is not None else None))
+                                  ctypes.byref(st) if st is not None else None), st)
         return st.as_dict() if st is not None else None
 
     def assemble_noalloc(self, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV):
@@ -261,8 +312,9 @@ class Assembler:
         instead of this object's workspace (no statistics)."""
         ptr = [self.out[k].data_ptr() if self.out[k] is not None else None for k in KERNELS]
         _check(lib().rrq_assemble_noalloc(self.plan.handle, ctypes.byref(self._t), self.kmask,
-                                          flags, ptr[0], ptr[1], ptr[2], ptr[3],
-                                          self.pair_off.data_ptr(), _stream()))
+                                          flags, ptr[0], ptr[1], ptr[2], ptr[3], self.nweights,
+                                          self.pair_off.data_ptr(), self.pair_flags.data_ptr(),
+                                          _stream()))
 
     def apply(self, density):
         import torch
@@ -302,9 +354,9 @@ class Evaluator:
         ptr = [pots[k].data_ptr() if pots[k] is not None else None for k in KERNELS]
         st = Stats() if stats else None
         _check(lib().rrq_potentials(self.plan.handle, ctypes.byref(self._t), self.kmask, flags,
-                                    dens.data_ptr(), ptr[0], ptr[1], ptr[2], ptr[3],
+                                    dens.data_ptr(), ptr[0], ptr[1], ptr[2], ptr[3], None,
                                     self.workspace.data_ptr(), self.workspace.numel(), _stream(),
-                                    ctypes.byref(st) if st is not None else None))
+                                    ctypes.byref(st) if st is not None else None), st)
         return (pots, st.as_dict()) if stats else pots
 
     def smooth(self, density):
@@ -327,11 +379,11 @@ def autotune(asm, flags=RRQ_F_CORRECTION | RRQ_F_ONSURF_PV, cache_path=None):
     r = TuneResult()
     p = _out_ptrs(asm)
     _check(lib().rrq_autotune(asm.plan.handle, ctypes.byref(asm._t), asm.kmask, flags, p[0], p[1],
-                              p[2], p[3], asm.pair_off.data_ptr(), asm.workspace.data_ptr(),
-                              asm.workspace.numel(),
+                              p[2], p[3], asm.nweights, asm.pair_off.data_ptr(),
+                              asm.workspace.data_ptr(), asm.workspace.numel(),
                               cache_path.encode() if cache_path else None, _stream(),
                               ctypes.byref(r)))
-    return {k: getattr(r, k) for k, _ in r._fields_}
+    return _struct_dict(r)
 
 
 class Graph:
@@ -343,9 +395,9 @@ class Graph:
         p = _out_ptrs(asm)
         h = ctypes.c_void_p()
         _check(lib().rrq_graph_create(asm.plan.handle, ctypes.byref(self._s), ctypes.byref(asm._t),
-                                      asm.kmask, flags, p[0], p[1], p[2], p[3],
+                                      asm.kmask, flags, p[0], p[1], p[2], p[3], asm.nweights,
                                       asm.pair_off.data_ptr(), asm.workspace.data_ptr(),
-                                      asm.workspace.numel(), ctypes.byref(h)))
+                                      asm.workspace.numel(), _stream(), ctypes.byref(h)))
         self.handle = h
 
     def launch(self):

@@ -69,15 +69,16 @@ def perturbed(s1, t1, member, P, t, seed=0):
     return s2, t2
 
 
-def oracle_pair(surf, tg, t, P, correction, onsurf_pv, fits=None):
+def oracle_pair(surf, tg, t, P, correction, onsurf_pv, fits=None, weighted=True):
     s1, t1 = sub_problem(surf, tg, t, P)
     f = {} if fits is None else fits
-    ref, _ = pair_block(s1, t1, f, 0, 0, correction, onsurf_pv)
-    raw, _ = pair_block(s1, t1, f, 0, 0, False, onsurf_pv)
+    ref, _ = pair_block(s1, t1, f, 0, 0, correction, onsurf_pv, weighted=weighted)
+    raw, _ = pair_block(s1, t1, f, 0, 0, False, onsurf_pv, weighted=weighted)
     return ref, raw
 
 
-def ensemble_spread(surf, tg, t, P, ref, correction, onsurf_pv, members=ENS_MEMBERS, cache=None):
+def ensemble_spread(surf, tg, t, P, ref, correction, onsurf_pv, members=ENS_MEMBERS, cache=None,
+                    weighted=True):
     """Per kernel: max over the ensemble (input perturbations and the SVD-solved fits) of
     ||W_e - W_or||_inf and of |(W_e - W_or) . f|."""
     s1, t1 = sub_problem(surf, tg, t, P)
@@ -91,7 +92,7 @@ def ensemble_spread(surf, tg, t, P, ref, correction, onsurf_pv, members=ENS_MEMB
         if cache is not None:
             if key in cache:
                 fits = {0: cache[key]}
-        We, _ = pair_block(s2, t2, fits, 0, 0, correction, onsurf_pv)
+        We, _ = pair_block(s2, t2, fits, 0, 0, correction, onsurf_pv, weighted=weighted)
         if cache is not None:
             cache[key] = fits[0]
         for k in ref:
@@ -100,7 +101,7 @@ def ensemble_spread(surf, tg, t, P, ref, correction, onsurf_pv, members=ENS_MEMB
             sp[k] = max(sp[k], float(abs(d @ f)))
     key = ("svd", P)
     fits = {0: cache[key]} if cache is not None and key in cache else {}
-    Ws, _ = pair_block(s1, t1, fits, 0, 0, correction, onsurf_pv, "svd")
+    Ws, _ = pair_block(s1, t1, fits, 0, 0, correction, onsurf_pv, "svd", weighted)
     if cache is not None:
         cache[key] = fits[0]
     for k in ref:
@@ -128,13 +129,15 @@ def block_scales(raw, f, s):
 
 
 def compare_pairs(surf, tg, pairs, gpu_block=None, gpu_pot=None, correction=True,
-                  onsurf_pv=True, flat_potential=False, tol=TOL, label="", strict=True):
+                  onsurf_pv=True, flat_potential=False, tol=TOL, label="", strict=True,
+                  weighted=True):
     """Check GPU results of the near pairs `pairs` (indices into the near list) against the
     oracle with the gates above.  gpu_block(i) gives the dict of the four weight blocks of
     pair i, gpu_pot(i) the dict of its four pair potentials for the density smooth_density
     (either may be None).  With flat_potential every pair's potential must meet the flat
-    bound with no allowance.  Returns per-kernel statistics; asserts the gates (with
-    strict=False it counts the blocks that miss them instead)."""
+    bound with no allowance; `weighted` selects the oracle's least-squares weighting.
+    Returns per-kernel statistics; asserts the gates (with strict=False it counts the blocks
+    that miss them instead)."""
 
     def gate(ok, *what):
         if strict:
@@ -148,7 +151,7 @@ def compare_pairs(surf, tg, pairs, gpu_block=None, gpu_pot=None, correction=True
     for i in pairs:
         t, P = int(owner[i]), int(tg["near_patch"][i])
         fits = fitc.setdefault(P, {})
-        ref, raw = oracle_pair(surf, tg, t, P, correction, onsurf_pv, fits)
+        ref, raw = oracle_pair(surf, tg, t, P, correction, onsurf_pv, fits, weighted)
         s1, _ = sub_problem(surf, tg, t, P)
         f = smooth_density(s1)
         sw, sp = block_scales(raw, f, fits[0].frame.s)
@@ -179,7 +182,8 @@ def compare_pairs(surf, tg, pairs, gpu_block=None, gpu_pot=None, correction=True
         miss = [k for k in ew if ew[k] > tol * sw[k] or ep[k] > tol * sp[k]]
         if not miss:
             continue
-        spw, spp = ensemble_spread(surf, tg, t, P, ref, correction, onsurf_pv, cache=cache)
+        spw, spp = ensemble_spread(surf, tg, t, P, ref, correction, onsurf_pv, cache=cache,
+                                   weighted=weighted)
         for k in miss:
             s = st[k]
             s["ens"] += 1

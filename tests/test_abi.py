@@ -49,4 +49,17 @@ def test_argument_errors_return_before_launch():
     s.npatch = 0
     assert L.rrq_plan_create(ctypes.byref(s), None, None, ctypes.byref(out)) == -1
     assert L.rrq_plan_destroy(None) == -1
-    assert L.rrq_assemble(None, None, 15, 0, None, None, None, None, None, None, 0, None, None) == -1
+    assert L.rrq_assemble(None, None, 15, 0, None, None, None, None, 0, None, None, None, 0, None,
+                          None) == -1
+    assert L.rrq_weights_size(None, None, None, None) == -1
+    assert L.rrq_plan_patch_flags(None, 0.0, None, None) == -1
+    assert L.rrq_assemble_noalloc(None, None, 15, 0, None, None, None, None, 0, None, None,
+                                  None) == -1
+
+
+def test_status_strings_cover_every_code():
+    if not os.path.exists(rrq.LIB_PATH):
+        pytest.skip("library not built")
+    L = rrq.lib()
+    for code in range(-7, 1):
+        assert L.rrq_status_string(code) != b"unknown status", code

@@ -1,0 +1,274 @@
+"""GPU tests of the boundary's failure handling and options (the errors of the problem
+statement's inputs, the per-pair and per-patch flags, the options of the plan):
+
+* a near list, self index or target outside its range is caught on the device before any
+  kernel uses it: the synchronising calls return RRQ_ERR_ARG and no output is written;
+* pair offsets inconsistent with the near list, or an output shorter than the weights,
+  return RRQ_ERR_BUFFER;
+* a patch whose fitted data hold NaN is flagged by rrq_plan_patch_flags, its pairs' weights
+  are counted as non-finite and flagged per pair (RRQ_ERR_NONFINITE), and every other pair
+  keeps its weights bit for bit;
+* Newton solves cut short (newton_maxit) fall back to the plain rule, are counted and
+  flagged per pair, and leave the weights of every other pair bit for bit;
+* a network with NaN parameters proposes no accepted start and changes no weight;
+* the unweighted least-squares option against the oracle's unweighted fit;
+* options outside what the build supports are refused at plan creation.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2411_08342_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ("S", "D", "Sp", "Dp")
+FLAGS = 3   # RRQ_F_CORRECTION | RRQ_F_ONSURF_PV
+
+
+def _setup(surf, tg, **opts):
+    from paper_2411_08342_amd import rrq
+    plan = rrq.Plan(rrq.DeviceSurface(surf), **opts)
+    dtg = rrq.DeviceTargets(tg)
+    return plan, dtg, rrq.Assembler(plan, dtg)
+
+
+def _host(asm):
+    return {k: asm.out[k].cpu().numpy().copy() for k in KERNELS}
+
+
+def _expect(code, fn, *a, **k):
+    from paper_2411_08342_amd import rrq
+    with pytest.raises(rrq.RRQError) as ei:
+        fn(*a, **k)
+    assert ei.value.code == code, (ei.value.code, code)
+    return ei.value
+
+
+@pytest.mark.parametrize("fault", ["patch index", "row pointer", "self node", "target"])
+def test_invalid_inputs_are_caught_on_the_device(fault):
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    plan, dtg, asm = _setup(surf, tg)
+    asm.assemble()
+    torch.cuda.synchronize()
+    with torch.no_grad():
+        if fault == "patch index":
+            dtg.near_patch[17] = 6                       # P = 6 patches: out of range
+        elif fault == "row pointer":
+            a, b = int(tg["near_ptr"][40]), int(tg["near_ptr"][41])
+            dtg.near_ptr[40], dtg.near_ptr[41] = b, a    # decreasing
+        elif fault == "self node":
+            dtg.self_node[3] = 36                        # q = 6: 36 nodes
+        else:
+            dtg.xyz[1, 250] = float("nan")
+    for k in KERNELS:
+        asm.out[k].fill_(-7.0)
+    e = _expect(rrq.RRQ_ERR_ARG, asm.assemble, stats=True)
+    assert e.stats["invalid"] != 0
+    torch.cuda.synchronize()
+    for k in KERNELS:                                    # nothing written
+        assert torch.all(asm.out[k] == -7.0), k
+    # the synchronising offsets call refuses before computing anything
+    nw = ctypes.c_int64()
+    rc = rrq.lib().rrq_pair_offsets(plan.handle, ctypes.byref(asm._t), asm.pair_off.data_ptr(),
+                                    asm.workspace.data_ptr(), asm.workspace.numel(),
+                                    ctypes.byref(nw), rrq._stream())
+    assert rc == rrq.RRQ_ERR_ARG
+    if fault in ("patch index", "row pointer"):
+        rc = rrq.lib().rrq_weights_size(plan.handle, ctypes.byref(asm._t), ctypes.byref(nw),
+                                        rrq._stream())
+        assert rc == rrq.RRQ_ERR_ARG
+    # the potentials mode checks the same inputs
+    ev = rrq.Evaluator(plan, dtg)
+    _expect(rrq.RRQ_ERR_ARG, ev.potentials, np.ones(surf["node_xyz"].shape[1]), stats=True)
+
+
+def test_output_length_and_offsets_are_checked():
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    plan, dtg, asm = _setup(surf, tg)
+    L = rrq.lib()
+    nw = ctypes.c_int64()
+    assert L.rrq_weights_size(plan.handle, ctypes.byref(asm._t), ctypes.byref(nw),
+                              rrq._stream()) == 0
+    assert nw.value == int(asm.pair_off[-1].item()) == asm.nweights
+    ptr = [asm.out[k].data_ptr() for k in KERNELS]
+
+    def call(out_len, stats):
+        return L.rrq_assemble(plan.handle, ctypes.byref(asm._t), 15, FLAGS, *ptr, out_len,
+                              asm.pair_off.data_ptr(), None, asm.workspace.data_ptr(),
+                              asm.workspace.numel(), rrq._stream(), ctypes.byref(stats))
+
+    for k in KERNELS:
+        asm.out[k].fill_(-7.0)
+    st = rrq.Stats()
+    assert call(asm.nweights - 1, st) == rrq.RRQ_ERR_BUFFER
+    assert st.invalid == 4
+    torch.cuda.synchronize()
+    for k in KERNELS:
+        assert torch.all(asm.out[k] == -7.0), k
+    assert call(-1, st) == rrq.RRQ_ERR_ARG
+    # offsets that do not match the near list
+    saved = asm.pair_off.clone()
+    with torch.no_grad():
+        asm.pair_off[5] += 1
+    assert call(asm.nweights, st) == rrq.RRQ_ERR_BUFFER
+    asm.pair_off.copy_(saved)
+    assert call(asm.nweights, st) == 0 and st.invalid == 0 and st.nonfinite == 0
+    # the sphere's unconverged solves (plain rule used) are flagged per pair
+    assert st.panel_overflow == 0 and 0 < st.flagged_pairs <= st.newton_fail
+
+
+def test_nonfinite_patch_is_flagged_and_isolated():
+    """A NaN node normal on one patch: its SLP and S' fits become NaN, rrq_plan_patch_flags
+    flags the patch, the non-finite weights of its pairs are counted and flagged, and every
+    pair of the other patches keeps its weights bit for bit."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    plan, dtg, asm = _setup(surf, tg)
+    asm.assemble()
+    torch.cuda.synchronize()
+    clean = _host(asm)
+    rc, flags = plan.patch_flags()
+    assert rc == 0 and not np.any(flags)
+    bad = dict(surf)
+    nrm = np.array(surf["node_nrm"], copy=True)
+    P = 2
+    nrm[:, int(surf["node_off"][P]) + 5] = np.nan
+    bad["node_nrm"] = nrm
+    plan2, dtg2, asm2 = _setup(bad, tg)
+    rc, flags = plan2.patch_flags()
+    assert rc == rrq.RRQ_ERR_ILLCONDITIONED
+    assert flags[P] & 4 and not np.any(np.delete(flags, P)), flags
+    e = _expect(rrq.RRQ_ERR_NONFINITE, asm2.assemble, stats=True)
+    assert e.stats["nonfinite"] > 0
+    torch.cuda.synchronize()
+    pf = asm2.pair_flags.cpu().numpy()[:len(tg["near_patch"])]
+    onP = np.asarray(tg["near_patch"]) == P
+    assert np.all(pf[onP] & 4) and not np.any(pf[~onP] & 4)
+    assert e.stats["flagged_pairs"] == np.count_nonzero(pf)
+    got = _host(asm2)
+    off = asm.pair_off.cpu().numpy()
+    keep = np.concatenate([np.arange(off[i], off[i + 1]) for i in np.nonzero(~onP)[0]])
+    for k in KERNELS:
+        assert np.array_equal(got[k][keep], clean[k][keep]), k
+    # the flagged patch's pairs: the SLP map is NaN throughout (its least-squares system has a
+    # NaN row), so every S weight of those pairs is
+    sel = np.concatenate([np.arange(off[i], off[i + 1]) for i in np.nonzero(onP)[0]])
+    assert not np.any(np.isfinite(got["S"][sel]))
+
+
+def test_condition_flags_follow_the_threshold():
+    """Curved paraboloid pieces (q = 10): no flag at the default limit, and exactly the
+    patches whose oracle QR diagonal ratio (1.3e2 .. 3.6e4 here) exceeds a lowered limit."""
+    from paper_2411_08342_amd import rrq
+    from oracle.assemble import fit_patch
+    cases = [(0.0, 1.0), (2.0, 1.0), (10.0, 1.0), (10.0, 1.0 / 16), (10.0, 1.0 / 1024)]
+    surf, tg = wl.paraboloid_workload(cases, 10)
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    rc, flags = plan.patch_flags()
+    assert rc == 0 and not np.any(flags)
+    lim = 2e4
+    rc, flags = plan.patch_flags(lim)
+    expect = np.zeros(len(cases), dtype=np.int32)
+    for P in range(len(cases)):
+        f = fit_patch(surf, P)
+        sw = np.sqrt(np.tile(f.lsw, 4))
+        for bit, (Msys, w) in ((1, (f.A, sw)), (2, (f.B, np.sqrt(f.lsw)))):
+            rd = np.abs(np.diag(np.linalg.qr(w[:, None] * Msys, mode="r")))
+            expect[P] |= bit if rd.max() / rd.min() > lim else 0
+    print("flags", flags, "expected", expect)
+    assert np.any(expect) and not np.all(expect) and np.array_equal(flags, expect)
+    assert rc == rrq.RRQ_ERR_ILLCONDITIONED
+
+
+def test_newton_cut_short_falls_back_and_is_flagged(monkeypatch):
+    """newton_maxit = 2: solves that have not converged after two steps use the plain GL rule
+    and flag their pair; every unflagged pair keeps the weights of the default plan bit for
+    bit, and flagged pairs match the oracle run with the same iteration limit."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    import oracle.ssq as ossq
+    from _parity import compare_pairs
+    surf, tg, _ = wl.config1()
+    _, _, ref = _setup(surf, tg)
+    s0 = ref.assemble(stats=True)
+    plan, dtg, asm = _setup(surf, tg, newton_maxit=2)
+    st = asm.assemble(stats=True)
+    torch.cuda.synchronize()
+    print("default", s0, "cut short", st)
+    assert s0["newton_fail"] == 0 or s0["newton_fail"] < st["newton_fail"]
+    assert st["newton_fail"] > 100 and st["newton_max"] <= 2
+    pf = asm.pair_flags.cpu().numpy()[:len(tg["near_patch"])]
+    assert st["flagged_pairs"] == np.count_nonzero(pf) > 0
+    assert not np.any(pf & ~1)
+    off = asm.pair_off.cpu().numpy()
+    a, b = _host(ref), _host(asm)
+    pf0 = ref.pair_flags.cpu().numpy()[:len(tg["near_patch"])]
+    unflagged = np.nonzero((pf == 0) & (pf0 == 0))[0]
+    idx = np.concatenate([np.arange(off[i], off[i + 1]) for i in unflagged])
+    for k in KERNELS:
+        assert np.array_equal(a[k][idx], b[k][idx]), k
+    # the oracle with the same limit
+    plain_root = ossq.newton_root
+    monkeypatch.setattr(ossq, "newton_root",
+                        lambda coef, x, ts, tol=ossq.NEWTON_TOL, maxit=2: plain_root(coef, x, ts, tol, 2))
+    flagged = [int(i) for i in np.nonzero(pf)[0][::7]]
+    compare_pairs(surf, tg, flagged, gpu_block=lambda i: {k: b[k][off[i]:off[i + 1]] for k in KERNELS},
+                  label="newton_maxit=2, flagged pairs")
+
+
+def test_nan_network_changes_nothing():
+    """A network with NaN parameters: every learned start is rejected before Newton runs, so
+    the learned form gives the plain form's roots, iteration counts and weights bit for bit."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    plan, dtg, asm = _setup(surf, tg)
+    s0 = asm.assemble(stats=True)
+    w0 = _host(asm)
+    plan.set_mlp(torch.full((rrq.MLP_PARAMS,), float("nan"), dtype=torch.float32, device="cuda"))
+    s1 = asm.assemble(flags=FLAGS | rrq.RRQ_F_LEARNED, stats=True)
+    torch.cuda.synchronize()
+    assert s1["learned_accept"] == 0 and s1["newton_iters"] == s0["newton_iters"]
+    w1 = _host(asm)
+    for k in KERNELS:
+        assert np.array_equal(w0[k], w1[k]), k
+
+
+def test_unweighted_least_squares_option():
+    """ls_unweighted = 1: unit least-squares row weights in the fits, against the oracle's
+    unweighted fit; the weights differ from the weighted fit's."""
+    import torch
+    from _parity import compare_pairs
+    surf, tg, _ = wl.config1()
+    _, _, wasm = _setup(surf, tg)
+    wasm.assemble()
+    plan, dtg, asm = _setup(surf, tg, ls_unweighted=1)
+    asm.assemble()
+    torch.cuda.synchronize()
+    g = _host(asm)
+    assert np.max(np.abs(g["D"] - _host(wasm)["D"])) > 1e-8
+    off = asm.pair_off.cpu().numpy()
+    rng = np.random.default_rng(31)
+    pairs = sorted(int(i) for i in rng.choice(len(tg["near_patch"]), 80, replace=False))
+    compare_pairs(surf, tg, pairs, gpu_block=lambda i: {k: g[k][off[i]:off[i + 1]] for k in KERNELS},
+                  flat_potential=True, weighted=False, label="unweighted fits")
+
+
+def test_unsupported_options_are_refused():
+    from paper_2411_08342_amd import rrq
+    surf, tg, _ = wl.config1()
+    ds = rrq.DeviceSurface(surf)
+    for opts, code in ((dict(rho_far=100.0), rrq.RRQ_ERR_UNSUPPORTED),
+                       (dict(ptilde_factor=3), rrq.RRQ_ERR_UNSUPPORTED),
+                       (dict(u_rule=1), rrq.RRQ_ERR_UNSUPPORTED),
+                       (dict(ls_unweighted=2), rrq.RRQ_ERR_ARG),
+                       (dict(tile_targets=5), rrq.RRQ_ERR_UNSUPPORTED)):
+        _expect(code, rrq.Plan, ds, **opts)
+    rrq.Plan(ds, rho_far=3.0).close()          # below the default 10^(8/12): accepted

@@ -319,10 +319,57 @@ def test_autotune_and_cache(tmp_path):
     asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
     cache = str(tmp_path / "tune.txt")
     r1 = rrq.autotune(asm, cache_path=cache)
-    assert r1["tile_targets"] in (4, 8) and r1["grid"] in (1024, 2048, 4096) and r1["from_cache"] == 0
+    assert r1["tile_targets"] in (4, 8) and r1["grid"] in (512, 1024, 2048, 4096)
+    assert r1["from_cache"] == 0 and r1["order_tile"][3] in (4, 8) and r1["order_ms"][3] > 0
     r2 = rrq.autotune(asm, cache_path=cache)
     assert r2["from_cache"] == 1 and r2["tile_targets"] == r1["tile_targets"]
     asm.assemble()
     torch.cuda.synchronize()
     gpu = {k: asm.out[k].cpu().numpy() for k in KERNELS}
     _compare(surf, tg, gpu, asm.pair_off.cpu().numpy(), _sample(tg, 40, np.random.default_rng(8)))
+
+
+def test_mixed_orders_tuning_and_graph_branches(tmp_path):
+    """Patches of orders 4, 5, 6, 8, 10 in one surface: the autotuner keeps a (tile, grid) per
+    order, the statistics time each order's tile kernel, and the captured step (the orders'
+    tile kernels on branches of their own) replays bit for bit like the eager assembly."""
+    import torch
+    from paper_2411_08342_amd import rrq
+    rng = np.random.default_rng(9)
+    maps = wl.cubed_sphere_patches(2, scale=(1.3, 0.8, 1.0), rot=wl._random_rotation(rng))
+    orders = rng.choice(np.array([4, 5, 6, 8, 10]), size=len(maps))
+    orders[:5] = [4, 5, 6, 8, 10]
+    surf = wl.discretize(maps, orders)
+    xyz, nrm = wl.offsurface_targets(surf, rng, count_per_patch=np.full(len(maps), 6),
+                                     rel_dist=(1e-5, 0.5))
+    T = xyz.shape[1]
+    tg = wl.make_targets(surf, xyz, nrm, np.full(T, -1), np.full(T, -1), eta=1.0)
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
+    cache = str(tmp_path / "tune.txt")
+    r1 = rrq.autotune(asm, cache_path=cache)
+    print("tuned per order:", r1)
+    for i, q in enumerate(rrq.ORDERS):
+        assert r1["order_ms"][i] > 0 and r1["order_grid"][i] in (512, 1024, 2048, 4096)
+        assert r1["order_tile"][i] == 4 or (r1["order_tile"][i] == 8 and q < 10)
+    r2 = rrq.autotune(asm, cache_path=cache)
+    assert r2["from_cache"] == 1 and r2["order_tile"] == r1["order_tile"]
+    assert r2["order_grid"] == r1["order_grid"]
+    st = asm.assemble(stats=True)
+    torch.cuda.synchronize()
+    print("per-order kernel ms:", st["order_kernel_ms"], "total", st["kernel_ms"])
+    assert all(v > 0 for v in st["order_kernel_ms"])
+    assert sum(st["order_kernel_ms"]) <= st["kernel_ms"] * 1.001 + 0.01
+    eager = {k: asm.out[k].cpu().numpy().copy() for k in KERNELS}
+    g = rrq.Graph(asm)
+    for rep in range(2):
+        for k in KERNELS:
+            asm.out[k].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for k in KERNELS:
+            assert np.array_equal(asm.out[k].cpu().numpy(), eager[k]), (rep, k)
+    g.close()
+    _compare(surf, tg, eager, asm.pair_off.cpu().numpy(), _sample(tg, 40, rng),
+             flat_potential=True, label="mixed orders, tuned per order")

@@ -131,18 +131,20 @@ def test_flat_basis_spans_polynomials_theorem_trianglebasis():
 
 # ---------------------------------------------------------------- fit
 
-def _quad_patch(q, ptf=2, **kw):
+def _quad_patch(q, ptf=2, weighted=True, **kw):
     s = wl.discretize([wl.quadratic_patch(**kw)], [q], ptilde_factor=ptf)
     xyz = s["node_xyz"].T
     nrm = s["node_nrm"].T
     edges = s["edge_xyz"].T.reshape(4, -1, 3)
-    return s, PatchFit(q, xyz, nrm, edges)
+    return s, PatchFit(q, xyz, nrm, edges, weighted=weighted)
 
 
-def test_constant_density_fit_is_exact_on_curved_patch():
+@pytest.mark.parametrize("weighted", [True, False])
+def test_constant_density_fit_is_exact_on_curved_patch(weighted):
     """(1, 0) = (0, grad H^{11}) c^{11} with c^{11} = (0, 0, 0, -1): a constant density lies in
-    the span of eq. dlpdensappr on any patch, so the least-squares map reproduces it."""
-    _, fit = _quad_patch(6)
+    the span of eq. dlpdensappr on any patch, so the least-squares map reproduces it, with or
+    without the row weights."""
+    _, fit = _quad_patch(6, weighted=weighted)
     c = fit.M_D @ np.ones(36)
     n_p = 21
     ref = np.zeros(4 * n_p)
@@ -150,11 +152,17 @@ def test_constant_density_fit_is_exact_on_curved_patch():
     assert np.max(np.abs(c - ref)) < 1e-12
 
 
-def test_flat_patch_reproduces_polynomials_all_kernels():
+@pytest.mark.parametrize("weighted", [True, False])
+def test_flat_patch_reproduces_polynomials_all_kernels(weighted):
     """On a flat patch every density of degree <= p-1 is in the fitted spans (remarks after
-    Theorem thm:trianglebasis): DLP, S' and SLP fits reproduce it at arbitrary points."""
+    Theorem thm:trianglebasis): DLP, S' and SLP fits reproduce it at arbitrary points, with
+    or without the row weights; a density outside the span is fitted differently by the two
+    weightings."""
     q = 6
-    _, fit = _quad_patch(q, k=(0.0, 0.0, 0.0))
+    _, fit = _quad_patch(q, k=(0.0, 0.0, 0.0), weighted=weighted)
+    _, other = _quad_patch(q, k=(0.0, 0.0, 0.0), weighted=not weighted)
+    g = np.cos(3.0 * fit.xl[:, 0]) * np.exp(fit.xl[:, 1])
+    assert np.max(np.abs(fit.M_D @ g - other.M_D @ g)) > 1e-8
     xy = fit.xl[:, :2]
     pts = np.column_stack([RNG.uniform(-0.4, 0.4, 30), RNG.uniform(-0.4, 0.4, 30), np.zeros(30)])
     n_p = q * (q + 1) // 2

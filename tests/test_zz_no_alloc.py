@@ -65,13 +65,13 @@ def test_noalloc_rejects_near_lists_beyond_the_scratch():
     assert rrq.lib().rrq_workspace_size(plan.handle, ctypes.byref(t), ctypes.byref(sz)) == 0
     assert sz.value > (64 << 20)
     rc = rrq.lib().rrq_assemble_noalloc(plan.handle, ctypes.byref(t), rrq.RRQ_K_ALL,
-                                        rrq.RRQ_F_CORRECTION, None, None, None, None, None,
-                                        rrq._stream())
+                                        rrq.RRQ_F_CORRECTION, None, None, None, None, 0, None,
+                                        None, rrq._stream())
     assert rc == -1      # null outputs are an argument error, checked first
     import torch
     off = torch.zeros(dt.nnz + 1, dtype=torch.int64, device="cuda")
     outs = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in range(4)]
     rc = rrq.lib().rrq_assemble_noalloc(plan.handle, ctypes.byref(t), rrq.RRQ_K_ALL,
-                                        rrq.RRQ_F_CORRECTION, *[o.data_ptr() for o in outs],
-                                        off.data_ptr(), rrq._stream())
+                                        rrq.RRQ_F_CORRECTION, *[o.data_ptr() for o in outs], 1,
+                                        off.data_ptr(), None, rrq._stream())
     assert rc == -6      # RRQ_ERR_BUFFER: beyond the scratch, nothing launched
