@@ -442,3 +442,52 @@ def test_smooth_kernels_against_derivatives_of_green_function():
                 # D' is a difference of two terms, each at most w / (4 pi R^3) and 3 times that
                 scale = 4 * w[j] / (4 * math.pi * R ** 3) if k == "Dp" else abs(exact)
                 assert abs(K[k][j] - exact) <= 1e-14 * scale, (k, j, K[k][j], exact)
+
+
+# ---------------------------------------------------------------- exact arithmetic
+
+def test_exact_far_pairs_agree_with_double_oracle_within_its_spread():
+    """The oracle's far-pair steps in 40-digit arithmetic (oracle/exact.py) against the double
+    oracle on a curved q = 6 patch with two far targets: the double result lies within its
+    own rounding spread (one-ulp input perturbations, SVD-solved fits) of the exact one, and
+    the exact weights are not identical to it (the double oracle does round)."""
+    from oracle.assemble import pair_block
+    from oracle.exact import pair_weights_exact
+    import _parity as pr
+    q = 6
+    s = wl.discretize([wl.quadratic_patch()], [q])
+    x = np.array([[0.4, -1.2], [0.3, 0.9], [3.0, 2.2]])
+    n = x / np.linalg.norm(x, axis=0)
+    tg = wl.make_targets(s, x, n, np.array([-1, -1]), np.array([-1, -1]), eta=100.0)
+    fits = {}
+    for t in range(2):
+        We = pair_weights_exact(s, tg, t, 0, True, fits)
+        Wo, _ = pair_block(s, tg, {}, t, 0, True, True)
+        spw, _ = pr.ensemble_spread(s, tg, t, 0, Wo, True, True)
+        for k in ("S", "D", "Sp", "Dp"):
+            d = np.max(np.abs(Wo[k] - We[k]))
+            assert 0 < d <= 3 * spw[k], (t, k, d, spw[k])
+
+
+def test_double_oracle_within_its_spread_of_stored_exact_weights():
+    """Ten far pairs of the star-shaped benchmark surface (1536 patches, q = 8), stored by
+    tests/golden/make_exact_far_pairs.py from the oracle's steps in 40-digit arithmetic: the
+    double oracle's weights lie within three times its own rounding spread (one-ulp input
+    perturbations, SVD-solved fits) of the exact ones, for all four kernels."""
+    import os
+    import _parity as pr
+    from oracle.assemble import pair_block
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "exact_far_pairs_star.npz"))
+    surf, tg, _ = wl.config2()
+    owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
+    worst = 0.0
+    for n, i in enumerate(g["pairs"]):
+        t, P = int(owner[i]), int(tg["near_patch"][i])
+        s1, t1 = pr.sub_problem(surf, tg, t, P)
+        Wo, _ = pair_block(s1, t1, {}, 0, 0, True, True)
+        spw, _ = pr.ensemble_spread(surf, tg, t, P, Wo, True, True)
+        for k in ("S", "D", "Sp", "Dp"):
+            d = np.max(np.abs(Wo[k] - g[k][n]))
+            worst = max(worst, d / spw[k])
+            assert d <= 3 * spw[k], (int(i), k, d, spw[k])
+    print(f"double oracle vs exact: largest |W_or - W_exact| / spread {worst:.2f}")
