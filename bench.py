@@ -76,31 +76,123 @@ def assemble_ms(asm, flags, reps):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-def learned_form(rrq, asm, flags, w_ref, reps=2):
-    """Train the learned Newton guess on its own seeded geometry (not the benchmark surface),
-    then time the batched form with it.  Returns a summary dict."""
+def _p99_bound(st):
+    """Smallest of the iteration thresholds 2, 4, 6, 8, 12 that at most 1% of the Newton solves
+    exceed (None if more than 1% take over 12)."""
+    n = st["newton_slots"]
+    for thr, over in zip((2, 4, 6, 8, 12), st["newton_over"]):
+        if over <= 0.01 * n:
+            return thr
+    return None
+
+
+def _newton_summary(st, ms, nweights):
+    return {"assemble_ms": ms, "weights_per_s": 4 * nweights / (ms / 1e3),
+            "newton_iters": st["newton_iters"], "newton_slots": st["newton_slots"],
+            "newton_iters_mean": st["newton_iters"] / max(1, st["newton_slots"]),
+            "newton_iters_p99_at_most": _p99_bound(st), "newton_iters_max": st["newton_max"],
+            "newton_wave_iters": st["newton_wave_iters"],
+            "newton_slots_over_2_4_6_8_12": st["newton_over"],
+            "learned_accept": st["learned_accept"], "newton_fail": st["newton_fail"]}
+
+
+def learned_form(rrq, reps=3, train_per_patch=110):
+    """The learned Newton start on the star surface plus the 2048-patch torus: trained on
+    about 2M samples the method produces on its own seeded training geometry (a deformed
+    sphere and a torus with off-surface targets, kept apart from the evaluation surfaces),
+    then plain and learned batched assemblies of the same near list compared on Newton
+    iterations (mean, tail, per-wavefront), assembly time and weights."""
     import torch
     from paper_2411_08342_amd import workloads as wl
     t0 = time.perf_counter()
-    surf, tg, _ = wl.learned_guess_training()
+    surf, tg, _ = wl.learned_guess_training(per_patch=train_per_patch)
     plan = rrq.Plan(rrq.DeviceSurface(surf))
     feat, dt, _ = rrq.collect_roots(plan, rrq.DeviceTargets(tg), 4 * len(tg["near_patch"]))
     plan.close()
     params, curve = rrq.mlp_train(feat, dt, steps=4000, batch=8192, lr=3e-3, seed=1)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    asm.plan.set_mlp(params)
-    lf = flags | rrq.RRQ_F_LEARNED
-    st = [asm.assemble(flags=lf, stats=True) for _ in range(reps)]
-    a_ms = assemble_ms(asm, lf, reps)
-    dev = max(((asm.out[k] - w_ref[k]).abs().max() / w_ref[k].abs().max()).item()
-              for k in rrq.KERNELS)
-    asm.plan.set_mlp(None)
+    del surf, tg
+    surf, tg, _ = wl.config4()
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
+    flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    out = {"workload": "star r=1+0.2ReY43+0.1ReY21 (1536 quads) + torus R=1 r=0.35 (2048 quads), "
+                       "q=8, node targets, near 1.5 patch diameters",
+           "pairs": int(len(tg["near_patch"])), "train_samples": int(feat.shape[1]),
+           "train_s": t_train}
     c = curve.cpu().numpy()
-    return {"assemble_ms": a_ms, "kernel_ms": float(np.mean([x["kernel_ms"] for x in st])),
-            "newton_iters": st[-1]["newton_iters"], "learned_accept": st[-1]["learned_accept"],
-            "max_rel_weight_dev_vs_batched": dev, "train_samples": int(feat.shape[1]),
-            "train_s": t_train, "train_loss_first_last": [float(c[:10].mean()), float(c[-100:].mean())]}
+    out["train_loss_first_last"] = [float(c[:10].mean()), float(c[-100:].mean())]
+    sp = asm.assemble(flags=flags, stats=True)
+    w_plain = {k: asm.out[k].clone() for k in rrq.KERNELS}
+    plain_ms = assemble_ms(asm, flags, reps)
+    plan.set_mlp(params)
+    sl = asm.assemble(flags=flags | rrq.RRQ_F_LEARNED, stats=True)
+    learned_ms = assemble_ms(asm, flags | rrq.RRQ_F_LEARNED, reps)
+    out["plain"] = _newton_summary(sp, plain_ms, asm.nweights)
+    out["learned"] = _newton_summary(sl, learned_ms, asm.nweights)
+    out["max_rel_weight_dev_learned_vs_plain"] = max(
+        ((asm.out[k] - w_plain[k]).abs().max() / w_plain[k].abs().max()).item()
+        for k in rrq.KERNELS)
+    plan.set_mlp(None)
+    del asm, w_plain
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def other_workload(rrq, name, steps=3):
+    """A whole step (refit, pair offsets, assembly; one HIP graph, autotuned per order) on one
+    of the other workloads, with each order's tile kernel against the FP64 roofline."""
+    import torch
+    from paper_2411_08342_amd import workloads as wl
+    t0 = time.perf_counter()
+    if name == "ellipsoids":
+        surf, tg, _ = wl.config3()
+        desc = ("12 ellipsoids, semi-axes U[0.5, 2], 96..1536 quads each, per-patch order "
+                "from {4, 6, 8, 10}, Poisson(150) off-surface targets per patch at "
+                "1e-5..0.5 patch sizes, near 1 patch diameter")
+    else:
+        surf, tg, _ = wl.config5()
+        desc = ("40 deformed spheres, 24,576 quads q=8, node targets and a 200k-point cloud at "
+                "1e-6..0.3, near 1 patch diameter")
+    t_gen = time.perf_counter() - t0
+    plan = rrq.Plan(rrq.DeviceSurface(surf))
+    asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
+    flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    tune = rrq.autotune(asm, flags)
+    graph = rrq.Graph(asm, flags)
+    graph.launch()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t1) / steps
+    st = asm.assemble(flags=flags, stats=True)
+    order = np.asarray(surf["order"])[np.asarray(tg["near_patch"])]
+    per_order = {}
+    for i, q in enumerate(rrq.ORDERS):
+        npq = int(np.count_nonzero(order == q))
+        if not npq:
+            continue
+        kms = st["order_kernel_ms"][i]
+        tf = npq * flops_per_pair(q) / (kms / 1e3) / 1e12
+        per_order[str(q)] = {"pairs": npq, "kernel_ms": kms, "tile": tune["order_tile"][i],
+                             "grid": tune["order_grid"][i], "achieved_TFLOPs": tf,
+                             "frac": tf / FP64_VALU_PEAK, "flops_per_pair": flops_per_pair(q)}
+    out = {"workload": desc, "pairs": int(len(tg["near_patch"])),
+           "weights_per_step": int(4 * asm.nweights), "ms_per_step": ms,
+           "value": 4 * asm.nweights / (ms / 1e3), "unit": "weights/s", "steps": steps,
+           "kernel_ms": st["kernel_ms"], "per_order": per_order,
+           "near_edges": st["near_edges"], "newton_fail": st["newton_fail"],
+           "panel_overflow": st["panel_overflow"], "nonfinite": st["nonfinite"],
+           "generate_s": t_gen}
+    graph.close()
+    del asm
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def potentials_form(rrq, asm, flags, w_ref, reps=3):
@@ -244,6 +336,38 @@ def cpu_model():
     return "unknown"
 
 
+def exact_reference(name, surf, tg, gpu_block):
+    """GPU and double oracle against the exact-arithmetic weights of ten far pairs of the
+    benchmark surface (tests/golden, written from the oracle's steps in 40 digits): the
+    largest difference relative to the pair's raw block and to the double oracle's rounding
+    spread (one-ulp input perturbations, SVD-solved fits)."""
+    path = os.path.join(ROOT, "tests", "golden", "exact_far_pairs_star.npz")
+    if name != "star" or not os.path.exists(path):
+        return None
+    from _parity import oracle_pair, ensemble_spread
+    g = np.load(path)
+    owner = np.repeat(np.arange(len(tg["near_ptr"]) - 1), np.diff(tg["near_ptr"]))
+    out = {"pairs": int(len(g["pairs"]))}
+    for k in ("S", "D", "Sp", "Dp"):
+        out[k] = {"gpu_rel_to_raw": 0.0, "oracle_rel_to_raw": 0.0, "gpu_over_spread": 0.0,
+                  "oracle_over_spread": 0.0}
+    for n, i in enumerate(g["pairs"]):
+        t, P = int(owner[i]), int(tg["near_patch"][i])
+        ref, raw = oracle_pair(surf, tg, t, P, True, True)
+        spw, _ = ensemble_spread(surf, tg, t, P, ref, True, True)
+        gb = gpu_block(int(i))
+        for k in ("S", "D", "Sp", "Dp"):
+            sc = float(np.max(np.abs(raw[k])))
+            dg = float(np.max(np.abs(gb[k] - g[k][n])))
+            do = float(np.max(np.abs(ref[k] - g[k][n])))
+            o = out[k]
+            o["gpu_rel_to_raw"] = max(o["gpu_rel_to_raw"], dg / sc)
+            o["oracle_rel_to_raw"] = max(o["oracle_rel_to_raw"], do / sc)
+            o["gpu_over_spread"] = max(o["gpu_over_spread"], dg / spw[k])
+            o["oracle_over_spread"] = max(o["oracle_over_spread"], do / spw[k])
+    return out
+
+
 def cpu_baseline(pool, workers, name, surf, tg, gpu_block, seconds=10.0, seed=0, gate_pairs=150):
     """The oracle timed (i) on one core over all near pairs of a run of consecutive targets from
     a seeded start, (ii) on `workers` cores (one process each, a run from its own start), (iii)
@@ -323,6 +447,9 @@ def cpu_baseline(pool, workers, name, surf, tg, gpu_block, seconds=10.0, seed=0,
             flat[k] += e <= TOL
     acc = {k: dict(gate[k], potential_flat_all_sampled=flat[k] / len(pairs),
                    potential_max_all_sampled=worst[k]) for k in gate}
+    exact = exact_reference(name, surf, tg, gpu_block)
+    if exact is not None:
+        acc["exact_far_pairs"] = exact
     allc.update(single_core=single, sphere_full=cfg1, nproc=os.cpu_count(), cpu_model=cpu_model(),
                 gpu_vs_oracle_on_sample=acc)
     return allc
@@ -355,6 +482,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-form and learned-guess measurements")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the mixed-order ellipsoids and the forty-sphere workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "known-size reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -419,7 +548,7 @@ def main():
         forms["plain_assemble_ms"] = assemble_ms(asm, flags | rrq.RRQ_F_PLAIN, 2)
         forms["plain_max_rel_weight_dev_vs_batched"] = max(
             ((asm.out[k] - w_ref[k]).abs().max() / w_ref[k].abs().max()).item() for k in rrq.KERNELS)
-        forms["learned"] = learned_form(rrq, asm, flags, w_ref)
+        forms["learned_star_torus"] = learned_form(rrq)
         forms["potentials"] = potentials_form(rrq, asm, flags, w_ref)
         print(f"[bench] forms: {forms}", flush=True)
         asm.assemble(flags=flags)      # leave the batched weights in the outputs
@@ -445,6 +574,9 @@ def main():
                    "assemble_ms": asm_ms,
                    "newton_iters_per_near_edge": stats["newton_iters"] / max(1, stats["near_edges"]),
                    "near_edges": stats["near_edges"], "newton_fail": stats["newton_fail"],
+                   "newton_wave_iters": stats["newton_wave_iters"],
+                   "panel_overflow": stats["panel_overflow"], "nonfinite": stats["nonfinite"],
+                   "flagged_pairs": stats["flagged_pairs"],
                    "forms": forms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": traffic,
@@ -453,6 +585,11 @@ def main():
                                 else f"k_pair_tile<{q},{tune['tile_targets'] if tune else 'T'}>"),
                      "flops_per_pair": flops_per_pair(q)},
     }
+    if not args.no_other_workloads:
+        out["other_workloads"] = {}
+        for name in ("ellipsoids", "forty_spheres"):
+            out["other_workloads"][name] = other_workload(rrq, name)
+            print(f"[bench] {name}: {out['other_workloads'][name]}", flush=True)
     if pool is not None:
         off = asm.pair_off.cpu().numpy()
 

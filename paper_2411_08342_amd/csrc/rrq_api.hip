@@ -57,7 +57,7 @@ struct rrq_plan {
   std::vector<int32_t> patches_h[kMaxQ + 1];
   int32_t* patches_d[kMaxQ + 1] = {};
   int32_t* perm_d = nullptr;    // patches grouped by order (kOrders order)
-  float* mlp_d = nullptr;       // learned-guess network, inference layout
+  float* mlp_d = nullptr;       // learned-guess network (ABI parameter layout)
   bool has_mlp = false;
   BinOrders bin_orders{};
   OrderDev od[kMaxQ + 1] = {};

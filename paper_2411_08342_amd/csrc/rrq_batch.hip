@@ -263,10 +263,10 @@ template <bool LEARNED>
 __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const int64_t* owner,
                                               RootOpts ro, double2* root, uint8_t* nearf,
                                               int64_t* nlist, unsigned long long* counters,
-                                              uint32_t* pflags) {
+                                              uint32_t* pflags,
+                                              const float* __restrict__ mw) {
   constexpr int kQ = 1024;               // slots per chunk of a workgroup
   if (input_bad(tg)) return;
-  __shared__ float w[LEARNED ? kMlpParams : 1];
   __shared__ int64_t qslot[kQ];          // chunk slots whose chord root needs Newton
   __shared__ int64_t nslot_l[kQ];        // chunk slots of the singularity-swap class
   __shared__ int qn, nn;
@@ -274,8 +274,6 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
   __shared__ unsigned long long cs[12];
   const int tid = threadIdx.x;
   if (tid < 12) cs[tid] = 0;
-  if (LEARNED)
-    for (int i = tid; i < kMlpParams; i += blockDim.x) w[i] = pd.mlp[i];
   unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_learn = 0, c_max = 0, c_wave = 0;
   unsigned long long c_slots = 0, c_over[5] = {0, 0, 0, 0, 0};
   const int64_t nslot = 4 * tg.nnz;
@@ -336,21 +334,28 @@ __global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const i
         if (LEARNED) {
           float x[kMlpIn];
           edge_features(cf, PT, xl, x, &ts, 1, pd.E);
+          // Parameters in the ABI layout, read at wave-uniform addresses (scalar loads, no
+          // LDS traffic); the hidden layer h1 is indexed by constants only (unrolled loops),
+          // so it stays in registers, and one first-layer unit is finished (fence) before
+          // the next starts, which bounds the registers the tanh evaluations take.
           float h1[kMlpH];
-          for (int u = 0; u < kMlpH; ++u) {
-            float a = w[kMlpB1 + u];
 #pragma unroll
-            for (int c = 0; c < kMlpIn; ++c) a += w[kMlpW1 + c * kMlpH + u] * x[c];
-            h1[u] = tanhf(a);
-          }
-          float y0 = w[kMlpB3], y1 = w[kMlpB3 + 1];
           for (int u = 0; u < kMlpH; ++u) {
-            float a = w[kMlpB2 + u];
-#pragma unroll 16
-            for (int kk = 0; kk < kMlpH; ++kk) a += w[kMlpW2 + kk * kMlpH + u] * h1[kk];
+            float a = mw[kMlpB1 + u];
+#pragma unroll
+            for (int c = 0; c < kMlpIn; ++c) a += mw[kMlpW1 + u * kMlpIn + c] * x[c];
+            h1[u] = tanhf(a);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          float y0 = mw[kMlpB3], y1 = mw[kMlpB3 + 1];
+#pragma unroll 1
+          for (int u = 0; u < kMlpH; ++u) {
+            float a = mw[kMlpB2 + u];
+#pragma unroll
+            for (int kk = 0; kk < kMlpH; ++kk) a += mw[kMlpW2 + u * kMlpH + kk] * h1[kk];
             const float h2 = tanhf(a);
-            y0 += w[kMlpW3 + u] * h2;
-            y1 += w[kMlpW3 + kMlpH + u] * h2;
+            y0 += mw[kMlpW3 + u] * h2;
+            y1 += mw[kMlpW3 + kMlpH + u] * h2;
           }
           tl = mk(ts.re + (double)y0, ts.im + (double)y1);
           try_learned = isfinite(tl.re) && isfinite(tl.im);
@@ -431,10 +436,10 @@ hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* o
   const dim3 grid((unsigned)(g < 4096 ? g : 4096));
   if (learned)
     hipLaunchKernelGGL(k_root<true>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
-                       counters, pflags);
+                       counters, pflags, (const float*)pd.mlp);
   else
     hipLaunchKernelGGL(k_root<false>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
-                       counters, pflags);
+                       counters, pflags, (const float*)nullptr);
   return hipGetLastError();
 }
 
@@ -634,6 +639,10 @@ hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const Tar
   return hipGetLastError();
 }
 
+// n rounded up to 4 mod 8: a per-target stride of that many doubles is 8 or 24 dwords mod 32,
+// so the 8-dword spans of four consecutive targets use disjoint LDS banks
+__host__ __device__ constexpr int pad_banks(int n) { return n + ((4 - n) % 8 + 8) % 8; }
+
 template <int Q, int T>
 struct TileLds {
   static constexpr int PT = 2 * Q, NP = np_of(Q), NJK = njk_of(Q), NR = tri(Q, Q) + 1;
@@ -647,11 +656,17 @@ struct TileLds {
   static constexpr int o_ids = o_dom + 4 * T;              // [T][3] i64: pair, target, offset
   static constexpr int o_xg = o_ids + 3 * T;               // [T][6]: global point, normal
   static constexpr int o_part = o_xg + 6 * T;              // [T][4][8]: edge partial sums
-  static constexpr int o_td = o_part + 32 * T;             // [T][4][PT][8] (aliased by rows)
-  static constexpr int n_td = T * 4 * PT * 8;
-  static constexpr int n_rows = T * 17 * NP;
+  // Per-target strides of the edge-point data and of the rows, padded so that the four
+  // targets a wave reads at once (lanes t = 0..3 of the contraction; the target quad of the
+  // MFMA operands) fall in different LDS banks: the unpadded strides are multiples of 32
+  // dwords, which put all four in one bank.
+  static constexpr int TDS = 4 * PT * 8 + 2;                // doubles per target of td
+  static constexpr int R4 = pad_banks(4 * NP), R5 = pad_banks(5 * NP);
+  static constexpr int o_td = o_part + 32 * T;             // [T][TDS] (aliased by rows)
+  static constexpr int n_td = T * TDS;
+  static constexpr int n_rows = T * (3 * R4 + R5);
   static constexpr int n_scrA = n_td > n_rows ? n_td : n_rows;
-  static constexpr int o_rows = o_td;                      // rD [T][4NP], rSp, rS [T][5NP], rDp
+  static constexpr int o_rows = o_td;                      // rD [T][R4], rSp, rS [T][R5], rDp
   static constexpr int o_vq = o_td + n_scrA;               // [T][NJK][18]
   static constexpr int o_rt = o_vq + T * NJK * 18;         // [T][NR] cplx
   static constexpr int o_gs = o_rt + 2 * T * NR;           // [T][NR] cplx
@@ -824,7 +839,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             om0 = cgl_w[i] * omega0_at(xl, su + t * 3, rr, rp);
           }
           const double dn = d[0] * nl[0] + d[1] * nl[1] + d[2] * nl[2];
-          double* o = td + (te * PT + i) * 8;
+          double* o = td + t * L::TDS + (e * PT + i) * 8;
           o[0] = w1;
           for (int c = 0; c < 3; ++c) {
             o[1 + c] = d[c];
@@ -892,7 +907,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         // loaded before this point's products, so that their latency overlaps them
         constexpr int NPTS = 4 * PT;
         const double* ob = tb + (int64_t)n * 12;
-        const double* tdb = td + t * NPTS * 8;
+        const double* tdb = td + t * L::TDS;
         double cur[12];
 #pragma unroll
         for (int u = 0; u < 12; ++u) cur[u] = ob[u];
@@ -1026,10 +1041,10 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         Eq[1] = Dq[0] * n0_ + (n1_ * Dq[3] - n2_ * Dq[2]);
         Eq[2] = Dq[0] * n1_ + (n2_ * Dq[1] - n0_ * Dq[3]);
         Eq[3] = Dq[0] * n2_ + (n0_ * Dq[2] - n1_ * Dq[1]);
-        double* rD = rows + t * 4 * NP;
-        double* rSp = rows + T * 4 * NP + t * 4 * NP;
-        double* rS = rows + T * 8 * NP + t * 5 * NP;
-        double* rDp = rows + T * 13 * NP + t * 4 * NP;
+        double* rD = rows + t * L::R4;
+        double* rSp = rows + T * L::R4 + t * L::R4;
+        double* rS = rows + 2 * T * L::R4 + t * L::R5;
+        double* rDp = rows + 2 * T * L::R4 + T * L::R5 + t * L::R4;
         const double sgn[4] = {1.0, -1.0, -1.0, -1.0};
         for (int c = 0; c < 4; ++c) {
           rD[c * NP + lm] = sgn[c] * Dq[c];
@@ -1061,10 +1076,10 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         for (int t = wv; t < nt; t += BNT / 64) {
           const int64_t k = sids[t * 3];
           const double* xt = sxg + t * 6;
-          const double* rD = rows + t * 4 * NP;
-          const double* rSp = rows + T * 4 * NP + t * 4 * NP;
-          const double* rS = rows + T * 8 * NP + t * 5 * NP;
-          const double* rDp = rows + T * 13 * NP + t * 4 * NP;
+          const double* rD = rows + t * L::R4;
+          const double* rSp = rows + T * L::R4 + t * L::R4;
+          const double* rS = rows + 2 * T * L::R4 + t * L::R5;
+          const double* rDp = rows + 2 * T * L::R4 + T * L::R5 + t * L::R4;
           double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
           for (int i = lane; i < 5 * NP; i += 64) a0 += rS[i] * cP[8 * NP + i];
           for (int i = lane; i < 4 * NP; i += 64) {
@@ -1154,9 +1169,10 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
                 int t = (a % TQ) * 4 + am;
                 if (t >= nt) t = 0;
                 const double* rowp;
-                if (grp == 0) rowp = a < TQ ? rows + t * 4 * NP : rows + T * 13 * NP + t * 4 * NP;
-                else if (grp == 1) rowp = rows + T * 4 * NP + t * 4 * NP;
-                else rowp = rows + T * 8 * NP + t * 5 * NP;
+                if (grp == 0)
+                  rowp = a < TQ ? rows + t * L::R4 : rows + 2 * T * L::R4 + T * L::R5 + t * L::R4;
+                else if (grp == 1) rowp = rows + T * L::R4 + t * L::R4;
+                else rowp = rows + 2 * T * L::R4 + t * L::R5;
                 double av[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) av[u] = rowp[min(kb + 4 * u + kr, KR - 1)];

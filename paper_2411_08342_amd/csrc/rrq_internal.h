@@ -54,7 +54,7 @@ struct PlanDev {
   const int64_t* map_off;
   double* tabs;             // per patch: [4][pt][njk][12]: c (3 cplx), h (3 cplx)
   const int64_t* tab_off;
-  const float* mlp;         // learned-guess network, inference layout (or null)
+  const float* mlp;         // learned-guess network, ABI parameter layout (or null)
   double* fitcond;          // [P][2]: max|R_ii| / min|R_ii| of the DLP and SLP fits
 };
 

@@ -4,8 +4,8 @@
 // training run is reproducible bit for bit.
 //
 // Parameter vector (the ABI layout): W1 [64][8], b1 [64], W2 [64][64], b2 [64], W3 [2][64],
-// b3 [2].  The plan keeps a copy in the inference layout, with W1 and W2 transposed so that
-// the lanes of a wave read consecutive weights.
+// b3 [2].  The plan keeps a copy in the same layout, which the root pre-pass reads at
+// wave-uniform addresses.
 #include "rrq_device.h"
 #include "rrq_internal.h"
 
@@ -296,19 +296,11 @@ __global__ void k_mlp_fold(const float* p, const float* stats, float* out) {
   out[i] = v;
 }
 
-// ABI layout -> inference layout (W1 and W2 transposed)
+// the plan's copy of the parameters, in the ABI layout (the root pre-pass reads it with
+// wave-uniform indices)
 __global__ void k_mlp_pack(const float* p, float* q) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kMlpParams) return;
-  float v = p[i];
-  if (i < kMlpB1) {                                  // q: W1t [8][64]
-    const int c = i / kMlpH, u = i % kMlpH;
-    v = p[kMlpW1 + u * kMlpIn + c];
-  } else if (i >= kMlpW2 && i < kMlpB2) {            // q: W2t [64][64], W2t[k][u] = W2[u][k]
-    const int k = (i - kMlpW2) / kMlpH, u = (i - kMlpW2) % kMlpH;
-    v = p[kMlpW2 + u * kMlpH + k];
-  }
-  q[i] = v;
+  if (i < kMlpParams) q[i] = p[i];
 }
 
 // outputs for features [8][n] -> out [2][n] (ABI layout, one sample per thread)

@@ -65,6 +65,23 @@ def test_star_full_size():
     pairs = _pairs(tg, np.random.default_rng(21), 70)
     _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="star full size")
     assert stats["newton_fail"] == 0
+    # against the exact-arithmetic weights of ten far pairs (tests/golden, written from the
+    # oracle's steps in 40 digits): the GPU lies within three times the double oracle's own
+    # rounding spread of them, as the double oracle itself does
+    import os
+    import _parity as pr
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "exact_far_pairs_star.npz"))
+    owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
+    worst = 0.0
+    for n, i in enumerate(g["pairs"]):
+        t, P = int(owner[i]), int(tg["near_patch"][i])
+        ref, _ = pr.oracle_pair(surf, tg, t, P, True, True)
+        spw, _ = pr.ensemble_spread(surf, tg, t, P, ref, True, True)
+        for k in KERNELS:
+            d = np.max(np.abs(gpu[k][off[i]:off[i + 1]] - g[k][n]))
+            worst = max(worst, d / spw[k])
+            assert d <= 3 * spw[k], (int(i), k, d, spw[k])
+    print(f"GPU vs exact weights: largest |W_gpu - W_exact| / spread {worst:.2f}")
 
 
 def test_uneven_ellipsoids_full_size():
