@@ -113,7 +113,7 @@ def learned_form(rrq, reps=3, train_per_patch=110):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del surf, tg
-    surf, tg, _ = wl.config4()
+    surf, tg, _ = wl.star_torus()
     plan = rrq.Plan(rrq.DeviceSurface(surf))
     asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
     flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
@@ -148,12 +148,12 @@ def other_workload(rrq, name, steps=3):
     from paper_2411_08342_amd import workloads as wl
     t0 = time.perf_counter()
     if name == "ellipsoids":
-        surf, tg, _ = wl.config3()
+        surf, tg, _ = wl.ellipsoids_mixed_orders()
         desc = ("12 ellipsoids, semi-axes U[0.5, 2], 96..1536 quads each, per-patch order "
                 "from {4, 6, 8, 10}, Poisson(150) off-surface targets per patch at "
                 "1e-5..0.5 patch sizes, near 1 patch diameter")
     else:
-        surf, tg, _ = wl.config5()
+        surf, tg, _ = wl.forty_spheres()
         desc = ("40 deformed spheres, 24,576 quads q=8, node targets and a 200k-point cloud at "
                 "1e-6..0.3, near 1 patch diameter")
     t_gen = time.perf_counter() - t0
@@ -225,14 +225,14 @@ def potentials_form(rrq, asm, flags, w_ref, reps=3):
 def build_workload(name):
     from paper_2411_08342_amd import workloads as wl
     if name == "star":
-        surf, tg, dens = wl.config2()
+        surf, tg, dens = wl.star()
         desc = ("star r=1+0.2ReY43+0.1ReY21, 1536 quads q=8, 98304 node targets, "
                 "near 1.5 patch diameters")
     elif name == "star-small":
-        surf, tg, dens = wl.config2(n=4)
+        surf, tg, dens = wl.star(n=4)
         desc = "star, 96 quads q=8, node targets, near 1.5 patch diameters"
     elif name == "sphere":
-        surf, tg, dens = wl.config1()
+        surf, tg, dens = wl.sphere_q6()
         desc = ("unit sphere, 6 quads q=6, 216 node targets and 200 off-surface targets "
                 "1e-4..1e-1 away, near 1 patch diameter")
     else:

@@ -423,12 +423,13 @@ static TargetsDev tdev(const rrq_targets* tg, const unsigned* bad = nullptr) {
   return t;
 }
 
-// workspace layout: owner[nnz] i64 | counters[16] u64 | bad u32 | pflags[nnz] u32 |
+// workspace layout: owner[nnz] i64 | counters[kNumCounters] u64 | bad u32 | pflags[nnz] u32 |
 // cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders][xcds] u64 |
 // sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
 // nearf[4 nnz] u8 | pairpot[nnz][4] f64 | pcoef[P][kCoefStride] f64 | nlist[4 nnz] i64 |
-// lamg[4 nnz][lam_stride] f64 (near-edge moments; lam_stride = 2 ptilde_max + 1)
+// lamg[4 nnz][lam_stride] f64 (near-edge moments; lam_stride = 2 ptilde_max + 1 >= 5; before
+// them, the root passes' Newton and retry lists, 4 nnz i64 each)
 struct WsLayout {
   size_t owner, counters, bad, pflags, cnt, fill, start, tstart, ntiles, queue, sorted, tiles,
       part, root, nearf, pairpot, pcoef, nlist, lamg, total;
@@ -699,8 +700,12 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       int64_t* nlist = (int64_t*)(wb + wl.nlist);
       double* lamg = (double*)(wb + wl.lamg);
       const int lam_stride = lam_stride_of(p);
-      if (launch_root(pd, td, owner, ro, (flags & RRQ_F_LEARNED) != 0, root, nearf, nlist,
-                      counters, pflags, st) != hipSuccess)
+      // the Newton and retry lists of the root passes live in the moments' region, which the
+      // near-edge moments overwrite only after the root passes (stream order)
+      int64_t* qlist = (int64_t*)(wb + wl.lamg);
+      int64_t* rlist = qlist + 4 * (tg->nnz > 0 ? tg->nnz : 1);
+      if (launch_root(pd, td, owner, ro, (flags & RRQ_F_LEARNED) != 0, root, nearf, qlist,
+                      rlist, nlist, counters, pflags, st) != hipSuccess)
         return RRQ_ERR_DEVICE;
       for (int qi = 0; qi < kNumOrders; ++qi) {
         const int q = kOrders[qi];

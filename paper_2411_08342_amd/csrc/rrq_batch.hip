@@ -250,196 +250,244 @@ __device__ int wave_graded_panels(double a, double b, double rho, double* wpan, 
 }
 
 // ---------------------------------------------------------------------------------------
-// Step 5 for every (pair, edge), one per thread: chord root t_s; if it lies inside the
-// Bernstein ellipse of radius rho_far, Newton on the distance function.  With a network
-// (learned form) Newton first starts from t_s + dt(features) for at most kLearnedMaxit
-// iterations and keeps that root if it converges inside the ellipse; otherwise plain Newton
-// from t_s decides.  root[slot] = t0 (Im t0 >= 0), nearf[slot] = 1 for the singularity-swap
-// class.  Counters: near edges, iterations, failures, learned accepts, max iterations.
+// Step 5 for every (pair, edge) slot: chord root t_s; if it lies inside the Bernstein ellipse
+// of radius rho_far, Newton on the distance function.  With a network (learned form) Newton
+// first starts from t_s + dt(features) for at most kLearnedMaxit iterations and keeps that
+// root if it converges inside the ellipse; otherwise plain Newton from t_s decides.
+// root[slot] = t0 (Im t0 >= 0), nearf[slot] = 1 for the singularity-swap class.
+//
+// Three passes, each over a list packed across the whole grid, so that every wavefront of a
+// Newton pass is full and a lane's iteration count competes only with slots of the same
+// pass: classification (chord root of every slot; Newton list), Newton from the chord start
+// or from the learned start (near list; learned form: retry list of the rejected guesses),
+// and, in the learned form, plain Newton over the retry list.  List entries are reserved
+// once per wavefront.  Counters: near edges, iterations, failures, learned accepts, largest
+// count, the sum over wavefronts of their largest count, and the count histogram.
 // ---------------------------------------------------------------------------------------
 constexpr int kLearnedMaxit = 8;
+constexpr int kItsShift = 56;            // retry entries: learned iterations above the slot
 
-template <bool LEARNED>
-__global__ __launch_bounds__(256) void k_root(PlanDev pd, TargetsDev tg, const int64_t* owner,
-                                              RootOpts ro, double2* root, uint8_t* nearf,
-                                              int64_t* nlist, unsigned long long* counters,
-                                              uint32_t* pflags,
-                                              const float* __restrict__ mw) {
-  constexpr int kQ = 1024;               // slots per chunk of a workgroup
-  if (input_bad(tg)) return;
-  __shared__ int64_t qslot[kQ];          // chunk slots whose chord root needs Newton
-  __shared__ int64_t nslot_l[kQ];        // chunk slots of the singularity-swap class
-  __shared__ int qn, nn;
-  __shared__ long long nbase;
-  __shared__ unsigned long long cs[12];
-  const int tid = threadIdx.x;
-  if (tid < 12) cs[tid] = 0;
-  unsigned long long c_near = 0, c_iters = 0, c_fail = 0, c_learn = 0, c_max = 0, c_wave = 0;
-  unsigned long long c_slots = 0, c_over[5] = {0, 0, 0, 0, 0};
-  const int64_t nslot = 4 * tg.nnz;
-  for (int64_t base = (int64_t)blockIdx.x * kQ; base < nslot; base += (int64_t)gridDim.x * kQ) {
+// Geometry of a slot: pair k, order q, target in the patch frame, edge coefficients
+// (component-major, read in place).
+struct RootSlot {
+  int64_t k;
+  int q, PT;
+  double xl[3];
+  const double* cf;
+};
+
+__device__ __forceinline__ RootSlot root_slot(const PlanDev& pd, const TargetsDev& tg,
+                                              const int64_t* owner, int64_t slot) {
+  RootSlot r;
+  r.k = slot >> 2;
+  const int e = (int)(slot & 3);
+  const int P = tg.near_patch[r.k];
+  r.q = pd.order[P];
+  r.PT = 2 * r.q;
+  const int64_t g = owner[r.k];
+  const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
+  frame_point(pd.frame + (int64_t)P * kFrame, xg, r.xl);
+  r.cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * r.PT;
+  return r;
+}
+
+// Appends v of the lanes with take set to list, one counter reservation per wavefront;
+// called by every lane of the wavefront.
+__device__ __forceinline__ void wave_append(bool take, int64_t v, int64_t* list,
+                                            unsigned long long* ctr) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63, lead = __builtin_ctzll(m);
+  long long b = 0;
+  if (lane == lead) b = (long long)atomicAdd(ctr, (unsigned long long)__popcll(m));
+  b = __shfl(b, lead, 64);
+  if (take) list[b + __popcll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+// Per-thread statistics of the Newton slots, folded into the counters at the kernel's end.
+struct RootCounts {
+  unsigned long long near = 0, iters = 0, fail = 0, learn = 0, most = 0, wave = 0, slots = 0;
+  unsigned long long over[5] = {0, 0, 0, 0, 0};
+  __device__ __forceinline__ void finish(int its) {
+    iters += (unsigned long long)its;
+    if ((unsigned long long)its > most) most = its;
+    ++slots;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) over[j] += its > kNewtonOver[j];
+  }
+  // a wavefront takes as long as its slowest lane: the largest count of the round
+  __device__ __forceinline__ void wave_max(int its_lane) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) its_lane = max(its_lane, __shfl_xor(its_lane, o, 64));
+    if ((threadIdx.x & 63) == 0) wave += (unsigned long long)its_lane;
+  }
+  __device__ void fold(unsigned long long* counters) {
+    __shared__ unsigned long long cs[12];
+    const int tid = threadIdx.x;
+    if (tid < 12) cs[tid] = 0;
     __syncthreads();
-    if (tid == 0) {
-      qn = 0;
-      nn = 0;
+    if (near) atomicAdd(&cs[0], near);
+    if (iters) atomicAdd(&cs[1], iters);
+    if (fail) atomicAdd(&cs[2], fail);
+    if (learn) atomicAdd(&cs[3], learn);
+    if (most) atomicMax(&cs[4], most);
+    if (wave) atomicAdd(&cs[5], wave);
+    if (slots) atomicAdd(&cs[6], slots);
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+      if (over[j]) atomicAdd(&cs[7 + j], over[j]);
+    __syncthreads();
+    if (tid < 12 && cs[tid]) {
+      if (tid == 4) atomicMax(&counters[kCMax], cs[4]);
+      else if (tid < 4) atomicAdd(&counters[tid], cs[tid]);
+      else if (tid == 5) atomicAdd(&counters[kCWaveIters], cs[5]);
+      else atomicAdd(&counters[kCNewtonSlots + (tid - 6)], cs[tid]);
     }
-    __syncthreads();
-    // classify the chunk; slots with the chord root outside the ellipse are done here
-    for (int i = tid; i < kQ; i += blockDim.x) {
-      const int64_t slot = base + i;
-      if (slot >= nslot) break;
-      const int64_t k = slot >> 2;
-      const int e = (int)(slot & 3);
-      const int P = tg.near_patch[k];
-      const int q = pd.order[P];
-      const int PT = 2 * q;
-      const int64_t g = owner[k];
-      const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
-      double xl[3];
-      frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
-      // the edge's Legendre coefficients are read in place (component-major plan arrays)
-      const double* cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * PT;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_root_classify(PlanDev pd, TargetsDev tg,
+                                                       const int64_t* owner, RootOpts ro,
+                                                       double2* root, uint8_t* nearf,
+                                                       int64_t* qlist,
+                                                       unsigned long long* counters) {
+  if (input_bad(tg)) return;
+  const int64_t nslot = 4 * tg.nnz;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x; s0 < nslot; s0 += stride) {
+    const int64_t slot = s0 + threadIdx.x;
+    bool queue = false;
+    if (slot < nslot) {
+      const RootSlot r = root_slot(pd, tg, owner, slot);
       double m[3], dv[3];
-      edge_chord(cf, PT, m, dv, 1, pd.E);
-      const cplx ts = chord_root(m, dv, xl);
-      if (bernstein_rho(ts) <= ro.rho_far[q]) {
-        qslot[atomicAdd(&qn, 1)] = slot;
-      } else {
+      edge_chord(r.cf, r.PT, m, dv, 1, pd.E);
+      const cplx ts = chord_root(m, dv, r.xl);
+      queue = bernstein_rho(ts) <= ro.rho_far[r.q];
+      if (!queue) {
         root[slot] = make_double2(ts.re, ts.im);
         nearf[slot] = 0;
       }
     }
-    __syncthreads();
-    // Newton (from the learned start first, if any) on the queued slots, all lanes busy; a
-    // wavefront takes as long as its slowest lane, so the largest count of each wavefront is
-    // summed too
-    const int nq = qn;
-    for (int i0 = 0; i0 < nq; i0 += blockDim.x) {
-      const int i = i0 + tid;
-      int its_lane = 0;
-      if (i < nq) {
-        const int64_t slot = qslot[i];
-        const int64_t k = slot >> 2;
-        const int e = (int)(slot & 3);
-        const int P = tg.near_patch[k];
-        const int q = pd.order[P];
-        const int PT = 2 * q;
-        const int64_t g = owner[k];
-        const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
-        double xl[3];
-        frame_point(pd.frame + (int64_t)P * kFrame, xg, xl);
-        const double* cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * PT;
-        cplx ts, tl = mk(0.0, 0.0);
-        bool try_learned = false;
-        if (LEARNED) {
-          float x[kMlpIn];
-          edge_features(cf, PT, xl, x, &ts, 1, pd.E);
-          // Parameters in the ABI layout, read at wave-uniform addresses (scalar loads, no
-          // LDS traffic); the hidden layer h1 is indexed by constants only (unrolled loops),
-          // so it stays in registers, and one first-layer unit is finished (fence) before
-          // the next starts, which bounds the registers the tanh evaluations take.
-          float h1[kMlpH];
+    wave_append(queue, slot, qlist, &counters[kCQueueList]);
+  }
+}
+
+// MODE 0: plain Newton from the chord start over the Newton list; 1: Newton from the learned
+// start over the Newton list, rejected slots to the retry list; 2: plain Newton over the retry
+// list, with the learned iterations added to the slot's count.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_root_newton(PlanDev pd, TargetsDev tg,
+                                                     const int64_t* owner, RootOpts ro,
+                                                     double2* root, uint8_t* nearf,
+                                                     const int64_t* list, int64_t* rlist,
+                                                     int64_t* nlist,
+                                                     unsigned long long* counters,
+                                                     uint32_t* pflags,
+                                                     const float* __restrict__ mw) {
+  if (input_bad(tg)) return;
+  constexpr int kNT = 256;
+  RootCounts c;
+  const int tid = threadIdx.x;
+  const int64_t n = (int64_t)counters[MODE == 2 ? kCRetryList : kCQueueList];
+  for (int64_t i0 = (int64_t)blockIdx.x * kNT; i0 < n; i0 += (int64_t)gridDim.x * kNT) {
+    const int64_t i = i0 + tid;
+    int its = 0;
+    bool near = false, retry = false;
+    int64_t slot = 0;
+    if (i < n) {
+      const int64_t ent = list[i];
+      slot = MODE == 2 ? (ent & ((1ll << kItsShift) - 1)) : ent;
+      const RootSlot r = root_slot(pd, tg, owner, slot);
+      if (MODE == 1) {
+        float x[kMlpIn];
+        cplx ts;
+        edge_features(r.cf, r.PT, r.xl, x, &ts, 1, pd.E);
+        // Parameters in the ABI layout, read at wave-uniform addresses (scalar loads, no LDS
+        // traffic); the hidden layer h1 is indexed by constants only (unrolled loops), so it
+        // stays in registers, and one first-layer unit is finished (fence) before the next
+        // starts, which bounds the registers the tanh evaluations take.
+        float h1[kMlpH];
 #pragma unroll
-          for (int u = 0; u < kMlpH; ++u) {
-            float a = mw[kMlpB1 + u];
+        for (int u = 0; u < kMlpH; ++u) {
+          float a = mw[kMlpB1 + u];
 #pragma unroll
-            for (int c = 0; c < kMlpIn; ++c) a += mw[kMlpW1 + u * kMlpIn + c] * x[c];
-            h1[u] = tanhf(a);
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          float y0 = mw[kMlpB3], y1 = mw[kMlpB3 + 1];
+          for (int cc = 0; cc < kMlpIn; ++cc) a += mw[kMlpW1 + u * kMlpIn + cc] * x[cc];
+          h1[u] = tanhf(a);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        float y0 = mw[kMlpB3], y1 = mw[kMlpB3 + 1];
 #pragma unroll 1
-          for (int u = 0; u < kMlpH; ++u) {
-            float a = mw[kMlpB2 + u];
+        for (int u = 0; u < kMlpH; ++u) {
+          float a = mw[kMlpB2 + u];
 #pragma unroll
-            for (int kk = 0; kk < kMlpH; ++kk) a += mw[kMlpW2 + u * kMlpH + kk] * h1[kk];
-            const float h2 = tanhf(a);
-            y0 += mw[kMlpW3 + u] * h2;
-            y1 += mw[kMlpW3 + kMlpH + u] * h2;
-          }
-          tl = mk(ts.re + (double)y0, ts.im + (double)y1);
-          try_learned = isfinite(tl.re) && isfinite(tl.im);
-        } else {
-          double m[3], dv[3];
-          edge_chord(cf, PT, m, dv, 1, pd.E);
-          ts = chord_root(m, dv, xl);
+          for (int kk = 0; kk < kMlpH; ++kk) a += mw[kMlpW2 + u * kMlpH + kk] * h1[kk];
+          const float h2 = tanhf(a);
+          y0 += mw[kMlpW3 + u] * h2;
+          y1 += mw[kMlpW3 + kMlpH + u] * h2;
         }
-        cplx t0 = ts;
-        int near = 0, its_all = 0;
-        for (int attempt = try_learned ? 0 : 1; attempt < 2; ++attempt) {
-          cplx tp = attempt == 0 ? tl : ts;
-          int its;
-          const int conv = newton_solve(cf, PT, xl, &tp, ro.newton_tol,
-                                        attempt == 0 ? kLearnedMaxit : ro.newton_maxit, &its, 1,
-                                        pd.E);
-          its_all += its;
+        cplx tp = mk(ts.re + (double)y0, ts.im + (double)y1);
+        if (isfinite(tp.re) && isfinite(tp.im)) {
+          const int conv = newton_solve(r.cf, r.PT, r.xl, &tp, ro.newton_tol, kLearnedMaxit,
+                                        &its, 1, pd.E);
           if (tp.im < 0) tp.im = -tp.im;
-          const int inside = conv && bernstein_rho(tp) <= ro.rho_far[q];
-          if (attempt == 0) {
-            if (!inside) continue;
-            ++c_learn;
-          } else if (!conv) {
-            ++c_fail;
-            flag_pair(pflags, counters, k, kFlagNewton);
-          }
-          t0 = tp;
-          near = inside;
-          break;
+          near = conv && bernstein_rho(tp) <= ro.rho_far[r.q];
         }
-        c_iters += (unsigned long long)its_all;
-        if ((unsigned long long)its_all > c_max) c_max = its_all;
-        c_near += near;
-        root[slot] = make_double2(t0.re, t0.im);
+        if (near) {
+          ++c.learn;
+          ++c.near;
+          c.finish(its);
+          root[slot] = make_double2(tp.re, tp.im);
+          nearf[slot] = 1;
+        } else {
+          retry = true;
+        }
+      } else {
+        const int its0 = MODE == 2 ? (int)(ent >> kItsShift) : 0;
+        double m[3], dv[3];
+        edge_chord(r.cf, r.PT, m, dv, 1, pd.E);
+        cplx tp = chord_root(m, dv, r.xl);
+        const int conv = newton_solve(r.cf, r.PT, r.xl, &tp, ro.newton_tol, ro.newton_maxit,
+                                      &its, 1, pd.E);
+        if (tp.im < 0) tp.im = -tp.im;
+        near = conv && bernstein_rho(tp) <= ro.rho_far[r.q];
+        if (!conv) {
+          ++c.fail;
+          flag_pair(pflags, counters, r.k, kFlagNewton);
+        }
+        c.near += near;
+        c.finish(its0 + its);
+        root[slot] = make_double2(tp.re, tp.im);
         nearf[slot] = (uint8_t)near;
-        if (near) nslot_l[atomicAdd(&nn, 1)] = slot;
-        its_lane = its_all;
-        ++c_slots;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) c_over[j] += its_all > kNewtonOver[j];
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) its_lane = max(its_lane, __shfl_xor(its_lane, o, 64));
-      if ((tid & 63) == 0) c_wave += (unsigned long long)its_lane;
     }
-    // the chunk's near slots go to the global list with one reservation per chunk
-    __syncthreads();
-    if (tid == 0)
-      nbase = nn > 0 ? (long long)atomicAdd(&counters[kCNearList], (unsigned long long)nn) : 0;
-    __syncthreads();
-    for (int i = tid; i < nn; i += blockDim.x) nlist[nbase + i] = nslot_l[i];
+    c.wave_max(its);
+    wave_append(near, slot, nlist, &counters[kCNearList]);
+    if (MODE == 1)
+      wave_append(retry, slot | ((int64_t)its << kItsShift), rlist, &counters[kCRetryList]);
   }
-  if (c_near) atomicAdd(&cs[0], c_near);
-  if (c_iters) atomicAdd(&cs[1], c_iters);
-  if (c_fail) atomicAdd(&cs[2], c_fail);
-  if (c_learn) atomicAdd(&cs[3], c_learn);
-  if (c_max) atomicMax(&cs[4], c_max);
-  if (c_wave) atomicAdd(&cs[5], c_wave);
-  if (c_slots) atomicAdd(&cs[6], c_slots);
-#pragma unroll
-  for (int j = 0; j < 5; ++j)
-    if (c_over[j]) atomicAdd(&cs[7 + j], c_over[j]);
-  __syncthreads();
-  if (tid < 12 && cs[tid]) {
-    if (tid == 4) atomicMax(&counters[kCMax], cs[4]);
-    else if (tid < 4) atomicAdd(&counters[tid], cs[tid]);
-    else if (tid == 5) atomicAdd(&counters[kCWaveIters], cs[5]);
-    else atomicAdd(&counters[kCNewtonSlots + (tid - 6)], cs[tid]);
-  }
+  c.fold(counters);
 }
 
 hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
                        const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
-                       int64_t* nlist, unsigned long long* counters, uint32_t* pflags,
-                       hipStream_t st) {
-  int64_t g = (4 * tg.nnz + 1023) / 1024;
+                       int64_t* qlist, int64_t* rlist, int64_t* nlist,
+                       unsigned long long* counters, uint32_t* pflags, hipStream_t st) {
+  const int64_t nslot = 4 * tg.nnz;
+  int64_t g = (nslot + 255) / 256;
   if (g < 1) g = 1;
-  const dim3 grid((unsigned)(g < 4096 ? g : 4096));
-  if (learned)
-    hipLaunchKernelGGL(k_root<true>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
-                       counters, pflags, (const float*)pd.mlp);
-  else
-    hipLaunchKernelGGL(k_root<false>, grid, dim3(256), 0, st, pd, tg, owner, ro, root, nearf, nlist,
-                       counters, pflags, (const float*)nullptr);
+  const dim3 gc((unsigned)(g < 8192 ? g : 8192)), gn(1024), b(256);
+  const float* mw = (const float*)pd.mlp;
+  hipLaunchKernelGGL(k_root_classify, gc, b, 0, st, pd, tg, owner, ro, root, nearf, qlist,
+                     counters);
+  if (learned) {
+    hipLaunchKernelGGL(k_root_newton<1>, gn, b, 0, st, pd, tg, owner, ro, root, nearf, qlist,
+                       rlist, nlist, counters, pflags, mw);
+    hipLaunchKernelGGL(k_root_newton<2>, gn, b, 0, st, pd, tg, owner, ro, root, nearf, rlist,
+                       nullptr, nlist, counters, pflags, nullptr);
+  } else {
+    hipLaunchKernelGGL(k_root_newton<0>, gn, b, 0, st, pd, tg, owner, ro, root, nearf, qlist,
+                       nullptr, nlist, counters, pflags, nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -328,8 +328,8 @@ __device__ __forceinline__ void edge_features(const double* cf, int n, const dou
   }
 }
 
-// Multilayer perceptron 8 -> 64 -> 64 -> 2 (tanh hidden units), parameters in the
-// device layout: W1t [8][64], b1 [64], W2t [64][64], b2 [64], W3 [2][64], b3 [2]
+// Multilayer perceptron 8 -> 64 -> 64 -> 2 (tanh hidden units), float32 parameters, row-major
+// [out][in] in this order: W1 [64][8], b1 [64], W2 [64][64], b2 [64], W3 [2][64], b3 [2]
 constexpr int kMlpIn = 8, kMlpH = 64, kMlpOut = 2;
 constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
 constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpH * kMlpIn, kMlpW2 = kMlpB1 + kMlpH,

@@ -90,7 +90,9 @@ enum {
   kCWaveIters = 9,   // sum over wavefronts of the largest Newton iteration count of a lane
   kCNewtonSlots = 10,  // slots that ran Newton
   kCNewtonOver = 11,   // [5]: of those, the ones that took more than kNewtonOver[i] iterations
-  kNumCounters = 16
+  kCQueueList = 16,    // length of the Newton list (slots whose chord root needs Newton)
+  kCRetryList = 17,    // length of the retry list (learned starts rejected)
+  kNumCounters = 18
 };
 constexpr int kNewtonOver[5] = {2, 4, 6, 8, 12};
 // per-pair flag bits (rrq_assemble's pair_flags)
@@ -188,10 +190,11 @@ struct RootOpts {
   double newton_tol;
   int newton_maxit;
 };
+// qlist and rlist: 4 nnz entries each (the Newton and retry lists of the root passes)
 hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
                        const RootOpts& ro, bool learned, double2* root, uint8_t* nearf,
-                       int64_t* nlist, unsigned long long* counters, uint32_t* pflags,
-                       hipStream_t st);
+                       int64_t* qlist, int64_t* rlist, int64_t* nlist,
+                       unsigned long long* counters, uint32_t* pflags, hipStream_t st);
 // near-edge moments of every singularity-swap slot listed by the root pre-pass (counters[5]
 // of them), for the patches of order q
 hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,

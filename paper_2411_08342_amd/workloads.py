@@ -300,10 +300,10 @@ def merge_surfaces(surfs):
 
 
 # ----------------------------------------------------------------------------
-# the five workloads
+# the workloads of the evaluation (synthetic stand-ins of the paper's tests)
 # ----------------------------------------------------------------------------
 
-def config1():
+def sphere_q6():
     """Unit sphere, 6 cubed-sphere patches, q = 6; density Re Y_3^2; 216 node targets and
     200 off-surface targets (100 inside, 100 outside) at log-uniform distances [1e-4, 1e-1]."""
     rng = np.random.default_rng(SEED_BASE + 1)
@@ -331,7 +331,7 @@ def _random_density(rng, xyz, L=6):
     return sum(rng.normal() * Y[k] for k in sorted(Y))
 
 
-def config2(n=16, q=8):
+def star(n=16, q=8):
     """Star-shaped surface r = 1 + 0.2 Re Y_4^3 + 0.1 Re Y_2^1, 6 n^2 patches of order q;
     targets all nodes, near radius 1.5 patch diameters."""
     rng = np.random.default_rng(SEED_BASE + 2)
@@ -349,7 +349,7 @@ def _random_rotation(rng):
     return Qm
 
 
-def config3(n_ell=12, nmin=4, nmax=16, orders=(4, 6, 8, 10), mean_targets=150):
+def ellipsoids_mixed_orders(n_ell=12, nmin=4, nmax=16, orders=(4, 6, 8, 10), mean_targets=150):
     """12 ellipsoids (semi-axes U[0.5, 2]), seeded rotations, non-overlapping bounding
     spheres; 6 n^2 patches each with n ~ U{nmin..nmax}; per-patch order from `orders`;
     Poisson(mean_targets) off-surface targets per patch at log-U[1e-5, 0.5] D_P."""
@@ -376,8 +376,8 @@ def config3(n_ell=12, nmin=4, nmax=16, orders=(4, 6, 8, 10), mean_targets=150):
     return surf, tg, None
 
 
-def config4(n=16, q=8, nt=32, nphi=64):
-    """Config-2 surface plus a torus (R = 1, r = 0.35, nt x nphi patches, order q) placed
+def star_torus(n=16, q=8, nt=32, nphi=64):
+    """The star surface plus a torus (R = 1, r = 0.35, nt x nphi patches, order q) placed
     beside it; targets all nodes of both surfaces."""
     s1 = discretize(cubed_sphere_patches(n, radial=star_radius), np.full(6 * n * n, q))
     s2 = discretize(torus_patches(nt, nphi, center=(3.0, 0.0, 0.0)), np.full(nt * nphi, q))
@@ -387,7 +387,7 @@ def config4(n=16, q=8, nt=32, nphi=64):
     return surf, tg, None
 
 
-def config5(cloud=200_000, spheres=40, lattice=(4, 5, 2), spacing=2.3,
+def forty_spheres(cloud=200_000, spheres=40, lattice=(4, 5, 2), spacing=2.3,
             ns=(9,) * 3 + (10,) * 33 + (11,) + (12,) * 3, q=8):
     """40 deformed spheres r = 1 + sum_{l<=5} a_lm Y_lm (orthonormal real basis, a ~ N(0, 0.03^2))
     on a lattice with spacing 2.3; sub-grid sizes n as listed (24,576 patches, order 8); targets

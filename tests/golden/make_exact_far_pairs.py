@@ -21,7 +21,7 @@ SEED = 77
 
 def _workload():
     from paper_2411_08342_amd import workloads as wl
-    surf, tg, _ = wl.config2()
+    surf, tg, _ = wl.star()
     return surf, tg
 
 

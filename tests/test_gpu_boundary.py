@@ -50,7 +50,7 @@ def _expect(code, fn, *a, **k):
 def test_invalid_inputs_are_caught_on_the_device(fault):
     import torch
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     plan, dtg, asm = _setup(surf, tg)
     asm.assemble()
     torch.cuda.synchronize()
@@ -89,7 +89,7 @@ def test_invalid_inputs_are_caught_on_the_device(fault):
 def test_output_length_and_offsets_are_checked():
     import torch
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     plan, dtg, asm = _setup(surf, tg)
     L = rrq.lib()
     nw = ctypes.c_int64()
@@ -129,7 +129,7 @@ def test_nonfinite_patch_is_flagged_and_isolated():
     pair of the other patches keeps its weights bit for bit."""
     import torch
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     plan, dtg, asm = _setup(surf, tg)
     asm.assemble()
     torch.cuda.synchronize()
@@ -195,7 +195,7 @@ def test_newton_cut_short_falls_back_and_is_flagged(monkeypatch):
     from paper_2411_08342_amd import rrq
     import oracle.ssq as ossq
     from _parity import compare_pairs
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     _, _, ref = _setup(surf, tg)
     s0 = ref.assemble(stats=True)
     plan, dtg, asm = _setup(surf, tg, newton_maxit=2)
@@ -228,7 +228,7 @@ def test_nan_network_changes_nothing():
     the learned form gives the plain form's roots, iteration counts and weights bit for bit."""
     import torch
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     plan, dtg, asm = _setup(surf, tg)
     s0 = asm.assemble(stats=True)
     w0 = _host(asm)
@@ -246,7 +246,7 @@ def test_unweighted_least_squares_option():
     unweighted fit; the weights differ from the weighted fit's."""
     import torch
     from _parity import compare_pairs
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     _, _, wasm = _setup(surf, tg)
     wasm.assemble()
     plan, dtg, asm = _setup(surf, tg, ls_unweighted=1)
@@ -263,7 +263,7 @@ def test_unweighted_least_squares_option():
 
 def test_unsupported_options_are_refused():
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     ds = rrq.DeviceSurface(surf)
     for opts, code in ((dict(rho_far=100.0), rrq.RRQ_ERR_UNSUPPORTED),
                        (dict(ptilde_factor=3), rrq.RRQ_ERR_UNSUPPORTED),

@@ -60,7 +60,7 @@ def _pairs(tg, rng, n, surf=None, per_order=0):
 
 def test_star_full_size():
     """1536-patch star surface, order 8, 98,304 node targets (the benchmark workload)."""
-    surf, tg, _ = wl.config2()
+    surf, tg, _ = wl.star()
     gpu, off, stats, keep = _assemble_bench_config(surf, tg)
     pairs = _pairs(tg, np.random.default_rng(21), 70)
     _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="star full size")
@@ -87,7 +87,7 @@ def test_star_full_size():
 def test_uneven_ellipsoids_full_size():
     """12 ellipsoids, per-patch orders 4/6/8/10 in one launch, Poisson off-surface targets
     down to 1e-5 patch diameters."""
-    surf, tg, _ = wl.config3()
+    surf, tg, _ = wl.ellipsoids_mixed_orders()
     gpu, off, stats, keep = _assemble_bench_config(surf, tg)
     pairs = _pairs(tg, np.random.default_rng(22), 40, surf, per_order=12)
     _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="ellipsoids full size")
@@ -98,7 +98,7 @@ def test_uneven_ellipsoids_full_size():
 def test_forty_spheres_full_size():
     """40 deformed spheres, 24,576 order-8 patches, node targets plus a 200k-point cloud
     down to 1e-6 away (about 26 GB of weights on the device)."""
-    surf, tg, _ = wl.config5()
+    surf, tg, _ = wl.forty_spheres()
     gpu, off, stats, keep = _assemble_bench_config(surf, tg)
     pairs = _pairs(tg, np.random.default_rng(23), 40)
     _compare(surf, tg, gpu, off, pairs, label="forty spheres full size")

@@ -46,7 +46,7 @@ def _oracle_samples(surf, tg):
 def test_collected_samples_match_oracle():
     import torch
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     plan = rrq.Plan(rrq.DeviceSurface(surf))
     dtg = rrq.DeviceTargets(tg)
     feat, dt, t0 = rrq.collect_roots(plan, dtg, 4 * len(tg["near_patch"]))
@@ -147,7 +147,7 @@ def test_learned_guess_gains_iterations_and_keeps_weights():
     from paper_2411_08342_amd import rrq
     feat, dt = _train_samples(small=False)
     params, _ = rrq.mlp_train(feat, dt, steps=4000, batch=8192, lr=3e-3, seed=1)
-    surf, tg, _ = wl.config2(n=6)
+    surf, tg, _ = wl.star(n=6)
     plan = rrq.Plan(rrq.DeviceSurface(surf))
     asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
     flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
@@ -162,6 +162,7 @@ def test_learned_guess_gains_iterations_and_keeps_weights():
     assert s1["near_edges"] == s0["near_edges"] > 0
     assert s1["learned_accept"] >= 0.99 * s1["near_edges"]
     assert s1["newton_iters"] <= 0.95 * s0["newton_iters"]
+    assert s1["newton_wave_iters"] < s0["newton_wave_iters"]
     # both solves stop at a step below 1e-14 |t0|, so the roots agree to rounding; the
     # weights then agree within the parity target (1e-11 of the largest weight)
     for k in KERNELS:
@@ -190,7 +191,7 @@ def test_learned_guess_star_torus():
     assert feat.shape[1] >= 1_900_000
     params, _ = rrq.mlp_train(feat, dt, steps=4000, batch=8192, lr=3e-3, seed=1)
     del feat, dt
-    surf, tg, _ = wl.config4()
+    surf, tg, _ = wl.star_torus()
     plan = rrq.Plan(rrq.DeviceSurface(surf))
     asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
     flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
@@ -204,6 +205,7 @@ def test_learned_guess_star_torus():
     assert s1["newton_slots"] == s0["newton_slots"]
     assert s1["learned_accept"] >= 0.99 * s1["near_edges"]
     assert s1["newton_iters"] < s0["newton_iters"]
+    assert s1["newton_wave_iters"] < s0["newton_wave_iters"]
     for k in KERNELS:
         d = (asm.out[k] - w0[k]).abs().max().item()
         sc = w0[k].abs().max().item()

@@ -60,14 +60,14 @@ def _sample(tg, n, rng, must=()):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    surf, tg, dens = wl.config1()
+def sphere():
+    surf, tg, dens = wl.sphere_q6()
     gpu, off, stats, keep = _run_gpu(surf, tg)
     return surf, tg, dens, gpu, off, stats, keep
 
 
-def test_config1_parity_sampled(cfg1):
-    surf, tg, dens, gpu, off, stats, _ = cfg1
+def test_sphere_parity_sampled(sphere):
+    surf, tg, dens, gpu, off, stats, _ = sphere
     rng = np.random.default_rng(1)
     self_pairs = [k for t in range(0, 216, 13)
                   for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])
@@ -75,21 +75,21 @@ def test_config1_parity_sampled(cfg1):
     off_surface = [k for t in (216, 260, 330, 400)
                    for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])]
     pairs = _sample(tg, 120, rng, must=self_pairs + off_surface)
-    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="config1")
+    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="sphere_q6")
 
 
-def test_config1_offsurface_targets_all_pairs(cfg1):
+def test_sphere_offsurface_targets_all_pairs(sphere):
     """Every pair of 40 off-surface targets (inside and outside, 1e-4..1e-1 away)."""
-    surf, tg, dens, gpu, off, stats, _ = cfg1
+    surf, tg, dens, gpu, off, stats, _ = sphere
     ts = list(range(216, 236)) + list(range(316, 336))
     pairs = [k for t in ts for k in range(tg["near_ptr"][t], tg["near_ptr"][t + 1])]
-    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="config1 off-surface")
+    _compare(surf, tg, gpu, off, pairs, flat_potential=True, label="sphere_q6 off-surface")
 
 
-def test_config1_raw_and_exterior_limit():
+def test_sphere_raw_and_exterior_limit():
     """No correction, exterior one-sided limit for self targets."""
     from paper_2411_08342_amd import rrq
-    surf, tg, dens = wl.config1()
+    surf, tg, dens = wl.sphere_q6()
     gpu, off, stats, _ = _run_gpu(surf, tg, flags=0)
     rng = np.random.default_rng(2)
     self_pairs = [k for t in range(0, 216, 29)
@@ -97,7 +97,7 @@ def test_config1_raw_and_exterior_limit():
                   if tg["near_patch"][k] == tg["self_patch"][t]]
     pairs = _sample(tg, 40, rng, must=self_pairs)
     _compare(surf, tg, gpu, off, pairs, correction=False, onsurf_pv=False, flat_potential=True,
-             label="config1 raw exterior")
+             label="sphere_q6 raw exterior")
 
 
 def _small_star(n=3, q=8):
@@ -182,7 +182,7 @@ def test_paraboloid_curvature_and_size_parity(q):
 def test_empty_rows_and_kernel_mask():
     """Targets with no near patch, and a kernel mask that skips S and D'."""
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     far = np.array([[5.0, -7.0], [0.0, 3.0], [0.0, 1.0]])
     xyz = np.concatenate([far, tg["xyz"][:, 216:230]], axis=1)
     nrm = np.concatenate([far / np.linalg.norm(far, axis=0), tg["nrm"][:, 216:230]], axis=1)
@@ -195,9 +195,9 @@ def test_empty_rows_and_kernel_mask():
 
 
 def test_plain_form_parity():
-    """The reference one-pair-per-workgroup form (RRQ_F_PLAIN) on config-1 pairs."""
+    """The reference one-pair-per-workgroup form (RRQ_F_PLAIN) on unit-sphere pairs."""
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     gpu, off, stats, _ = _run_gpu(surf, tg, flags=rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
                                   | rrq.RRQ_F_PLAIN)
     rng = np.random.default_rng(4)
@@ -237,9 +237,9 @@ def test_batched_tiles_vs_oracle_and_plain(tile):
     _compare(surf, tg, gpu, asm.pair_off.cpu().numpy(), _sample(tg, 80, rng, must=close))
 
 
-def test_apply_matches_weights(cfg1):
+def test_apply_matches_weights(sphere):
     """rrq_apply = blockwise dot of the weights with the nodal density (float64 host sum)."""
-    surf, tg, dens, gpu, off, stats, keep = cfg1
+    surf, tg, dens, gpu, off, stats, keep = sphere
     plan, asm = keep
     pots = asm.apply(dens)
     near_ptr, near_patch = tg["near_ptr"], tg["near_patch"]
@@ -254,10 +254,10 @@ def test_apply_matches_weights(cfg1):
         assert np.max(np.abs(p - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
 
 
-def test_refit_reproduces_plan(cfg1):
+def test_refit_reproduces_plan(sphere):
     """rrq_plan_refit on the same surface gives bitwise identical weights."""
     import torch
-    surf, tg, dens, gpu, off, stats, keep = cfg1
+    surf, tg, dens, gpu, off, stats, keep = sphere
     plan, asm = keep
     plan.refit()
     asm.assemble()

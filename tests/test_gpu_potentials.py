@@ -73,7 +73,7 @@ def _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=True, flat_potential=F
 
 
 def test_pair_potentials_match_oracle_sphere():
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     rng = np.random.default_rng(11)
     nnz = len(tg["near_patch"])
     pairs = np.sort(rng.choice(nnz, size=min(240, nnz), replace=False))
@@ -81,7 +81,7 @@ def test_pair_potentials_match_oracle_sphere():
 
 
 def test_pair_potentials_match_oracle_star_exterior_limit():
-    surf, tg, _ = wl.config2(n=3)
+    surf, tg, _ = wl.star(n=3)
     rng = np.random.default_rng(12)
     pairs = np.sort(rng.choice(len(tg["near_patch"]), size=160, replace=False))
     _pair_potentials_vs_oracle(surf, tg, pairs, onsurf_pv=False, label="star exterior limit")
@@ -155,11 +155,11 @@ def test_potentials_match_assemble_apply(case):
     import torch
     from paper_2411_08342_amd import rrq
     if case == "sphere":
-        surf, tg, _ = wl.config1()
+        surf, tg, _ = wl.sphere_q6()
     elif case.startswith("star"):
-        surf, tg, _ = wl.config2(n=4)
+        surf, tg, _ = wl.star(n=4)
     else:
-        surf, tg, _ = wl.config3(n_ell=2, nmin=2, nmax=3, mean_targets=40)
+        surf, tg, _ = wl.ellipsoids_mixed_orders(n_ell=2, nmin=2, nmax=3, mean_targets=40)
     f = _density(surf)
     plan = rrq.Plan(rrq.DeviceSurface(surf), tile_targets=8 if case.endswith("tile8") else 0)
     dtg = rrq.DeviceTargets(tg)
@@ -203,7 +203,7 @@ def test_potentials_kernel_mask_and_empty_rows():
     """Kernels outside the mask are not written; targets without near patches get zero."""
     import torch
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     # drop the near lists of every third target
     keep = np.arange(tg["ntarget"]) % 3 != 0
     cnt = np.diff(tg["near_ptr"]) * keep
@@ -228,7 +228,7 @@ def test_potentials_kernel_mask_and_empty_rows():
 
 def test_smooth_direct_matches_host_sum():
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     f = _density(surf)
     _, sm = _evaluate(surf, tg, f, smooth=True)
     y, nu, w = surf["node_xyz"], surf["node_nrm"], surf["node_wt"]

@@ -478,7 +478,7 @@ def test_double_oracle_within_its_spread_of_stored_exact_weights():
     import _parity as pr
     from oracle.assemble import pair_block
     g = np.load(os.path.join(os.path.dirname(__file__), "golden", "exact_far_pairs_star.npz"))
-    surf, tg, _ = wl.config2()
+    surf, tg, _ = wl.star()
     owner = np.repeat(np.arange(tg["ntarget"]), np.diff(tg["near_ptr"]))
     worst = 0.0
     for n, i in enumerate(g["pairs"]):

@@ -53,7 +53,7 @@ def test_noalloc_matches_workspace_form_twice():
 def test_noalloc_rejects_near_lists_beyond_the_scratch():
     import ctypes
     from paper_2411_08342_amd import rrq
-    surf, tg, _ = wl.config1()
+    surf, tg, _ = wl.sphere_q6()
     plan = rrq.Plan(rrq.DeviceSurface(surf))
     reps = 20000
     xyz = np.repeat(tg["xyz"][:, 216:217], reps, axis=1)
