@@ -952,19 +952,28 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         double Qr[4] = {0, 0, 0, 0}, Qi[4] = {0, 0, 0, 0};
         double Dr[4] = {0, 0, 0, 0}, Di[4] = {0, 0, 0, 0};
         // the 4 PT edge points in order (edge-major); the table entries of the next point are
-        // loaded before this point's products, so that their latency overlaps them
+        // loaded before this point's products, so that their latency overlaps them.  The
+        // lanes of a wave read consecutive (j,k) of one point and component.
         constexpr int NPTS = 4 * PT;
-        const double* ob = tb + (int64_t)n * 12;
+        const double2* ob = (const double2*)tb + n;
         const double* tdb = td + t * L::TDS;
         double cur[12];
 #pragma unroll
-        for (int u = 0; u < 12; ++u) cur[u] = ob[u];
+        for (int u = 0; u < 6; ++u) {
+          const double2 v = ob[u * NJK];
+          cur[2 * u] = v.x;
+          cur[2 * u + 1] = v.y;
+        }
 #pragma unroll 2
         for (int p = 0; p < NPTS; ++p) {
-          const double* onx = ob + (int64_t)min(p + 1, NPTS - 1) * NJK * 12;
+          const double2* onx = ob + (int64_t)min(p + 1, NPTS - 1) * 6 * NJK;
           double nx[12];
 #pragma unroll
-          for (int u = 0; u < 12; ++u) nx[u] = onx[u];
+          for (int u = 0; u < 6; ++u) {
+            const double2 v = onx[u * NJK];
+            nx[2 * u] = v.x;
+            nx[2 * u + 1] = v.y;
+          }
           {
             const double* tdp = tdb + p * 8;
             const double w1 = tdp[0];

@@ -179,12 +179,12 @@ __global__ __launch_bounds__(128) void k_edge_tables(PlanDev pd, OrderDev od,
         c3[0] = tp[2] * g3[1] - tp[1] * g3[2];
         c3[1] = tp[0] * g3[2] - tp[2] * g3[0];
         c3[2] = tp[1] * g3[0] - tp[0] * g3[1];
-        double* o = base + (((int64_t)e * PT + i) * NJK + jk_index(j, k)) * 12;
+        // [edge node][component c0, c1, c2, h0, h1, h2][(j,k)] of (re, im) pairs: the (j,k)
+        // of one node and component are contiguous
+        double2* o = (double2*)base + ((int64_t)e * PT + i) * 6 * NJK + jk_index(j, k);
         for (int a = 0; a < 3; ++a) {
-          o[2 * a] = c3[a].re;
-          o[2 * a + 1] = c3[a].im;
-          o[6 + 2 * a] = h3[a].re;
-          o[6 + 2 * a + 1] = h3[a].im;
+          o[a * NJK] = make_double2(c3[a].re, c3[a].im);
+          o[(3 + a) * NJK] = make_double2(h3[a].re, h3[a].im);
         }
       }
   }

@@ -52,7 +52,7 @@ struct PlanDev {
   double* edge_coef;        // [3][E] monomial coefficients per edge
   double* maps;             // per patch: M_D [4np][q^2], M_Sp [4np][q^2], M_S [5np][q^2]
   const int64_t* map_off;
-  double* tabs;             // per patch: [4][pt][njk][12]: c (3 cplx), h (3 cplx)
+  double* tabs;             // per patch: [4 pt][6][njk] (re, im): c (3 cplx), h (3 cplx)
   const int64_t* tab_off;
   const float* mlp;         // learned-guess network, ABI parameter layout (or null)
   double* fitcond;          // [P][2]: max|R_ii| / min|R_ii| of the DLP and SLP fits

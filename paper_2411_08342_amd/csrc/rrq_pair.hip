@@ -509,9 +509,10 @@ __global__ __launch_bounds__(PNT) void k_pair_plain(PlanDev pd, OrderDev od, Tar
       for (int e = 0; e < 4; ++e)
         for (int i = 0; i < PT; ++i) {
           const int idx = e * PT + i;
-          const double* o = tb + (((int64_t)e * PT + i) * NJK + n) * 12;
-          const cplx c0 = mk(o[0], o[1]), c1 = mk(o[2], o[3]), c2 = mk(o[4], o[5]);
-          const cplx h0 = mk(o[6], o[7]), h1 = mk(o[8], o[9]), h2 = mk(o[10], o[11]);
+          const double2* o = (const double2*)tb + (int64_t)idx * 6 * NJK + n;
+          const cplx c0 = mk(o[0].x, o[0].y), c1 = mk(o[NJK].x, o[NJK].y);
+          const cplx c2 = mk(o[2 * NJK].x, o[2 * NJK].y), h0 = mk(o[3 * NJK].x, o[3 * NJK].y);
+          const cplx h1 = mk(o[4 * NJK].x, o[4 * NJK].y), h2 = mk(o[5 * NJK].x, o[5 * NJK].y);
           const double w1 = S.w1[idx];
           const double d0 = S.d[idx * 3], d1 = S.d[idx * 3 + 1], d2 = S.d[idx * 3 + 2];
           V = V + w1 * (d0 * c0 + d1 * c1 + d2 * c2);
