@@ -455,6 +455,45 @@ def cpu_baseline(pool, workers, name, surf, tg, gpu_block, seconds=10.0, seed=0,
     return allc
 
 
+PHASES = ["targets", "roots_and_target_harmonics", "effective_weights", "contraction",
+          "translation", "rows_x_maps_and_stores", "tile_fetch"]
+
+
+def phase_split(args, reps=3):
+    """Shares of the tile kernel's phases: the profiling build reads the shader clock at the
+    workgroup barriers between phases (thread 0 of each workgroup) and sums the differences
+    per phase over all workgroups.  The shares are of workgroup time, so a phase whose waves
+    wait for other workgroups' work on the same compute unit is charged that wait."""
+    import ctypes
+    import torch
+    from paper_2411_08342_amd import rrq
+    from paper_2411_08342_amd.build import LIB_PHASES
+    if not os.path.exists(LIB_PHASES):
+        raise SystemExit(f"profiling build missing: {LIB_PHASES} (run __graft_entry__.build())")
+    rrq.LIB_PATH = LIB_PHASES
+    L = rrq.lib()
+    surf, tg, desc = build_workload(args.workload)
+    plan = rrq.Plan(rrq.DeviceSurface(surf), tile_targets=args.tile)
+    asm = rrq.Assembler(plan, rrq.DeviceTargets(tg))
+    flags = rrq.RRQ_F_CORRECTION | rrq.RRQ_F_ONSURF_PV
+    tune = rrq.autotune(asm, flags)
+    asm.assemble(flags=flags)
+    torch.cuda.synchronize()
+    if L.rrq_phase_reset() != 0:
+        raise SystemExit("rrq_phase_reset failed")
+    ks = [asm.assemble(flags=flags, stats=True)["kernel_ms"] for _ in range(reps)]
+    torch.cuda.synchronize()
+    h = (ctypes.c_ulonglong * 8)()
+    if L.rrq_phase_read(h) != 0:
+        raise SystemExit("rrq_phase_read failed")
+    tot = float(sum(h[i] for i in range(len(PHASES))))
+    print(json.dumps({"phase_split": {PHASES[i]: h[i] / tot for i in range(len(PHASES))},
+                      "workgroup_cycles": {PHASES[i]: int(h[i]) for i in range(len(PHASES))},
+                      "kernel_ms": float(np.mean(ks)), "assemblies": reps,
+                      "tile_targets": tune["tile_targets"], "grid": tune["grid"],
+                      "config": {"workload": desc}}))
+
+
 def copy_probe(nbytes=1 << 30, reps=3):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -484,6 +523,9 @@ def main():
                     help="skip the plain-form and learned-guess measurements")
     ap.add_argument("--no-other-workloads", action="store_true",
                     help="skip the mixed-order ellipsoids and the forty-sphere workloads")
+    ap.add_argument("--phase-split", action="store_true",
+                    help="only time the tile kernel's phases with the profiling build "
+                         "(librrq_phases.so) and print their shares")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "known-size reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -493,6 +535,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.phase_split:
+        phase_split(args)
         return
 
     pool = None

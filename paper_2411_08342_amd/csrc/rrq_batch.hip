@@ -703,20 +703,23 @@ struct TileLds {
   static constexpr int o_dom = o_om + 4 * T;               // [T][4]
   static constexpr int o_ids = o_dom + 4 * T;              // [T][3] i64: pair, target, offset
   static constexpr int o_xg = o_ids + 3 * T;               // [T][6]: global point, normal
-  static constexpr int o_part = o_xg + 6 * T;              // [T][4][8]: edge partial sums
   // Per-target strides of the edge-point data and of the rows, padded so that the four
   // targets a wave reads at once (lanes t = 0..3 of the contraction; the target quad of the
   // MFMA operands) fall in different LDS banks: the unpadded strides are multiples of 32
   // dwords, which put all four in one bank.
   static constexpr int TDS = 4 * PT * 8 + 2;                // doubles per target of td
   static constexpr int R4 = pad_banks(4 * NP), R5 = pad_banks(5 * NP);
-  static constexpr int o_td = o_part + 32 * T;             // [T][TDS] (aliased by rows)
+  static constexpr int o_td = o_xg + 6 * T;               // [T][TDS] (aliased by rows)
   static constexpr int n_td = T * TDS;
   static constexpr int n_rows = T * (3 * R4 + R5);
   static constexpr int n_scrA = n_td > n_rows ? n_td : n_rows;
   static constexpr int o_rows = o_td;                      // rD [T][R4], rSp, rS [T][R5], rDp
-  static constexpr int o_vq = o_td + n_scrA;               // [T][NJK][18]
-  static constexpr int o_rt = o_vq + T * NJK * 18;         // [T][NR] cplx
+  // moments per (target, (j,k)): 18 values at vq_rec(n) in the target's block of VQT
+  static constexpr int VQT = vq_rec(NJK);
+  static constexpr int o_vq = o_td + n_scrA;               // [T][VQT]
+  static constexpr int o_part = o_vq;                      // [T][4][8]: edge partial sums,
+                                                           // dead before vq is written
+  static constexpr int o_rt = o_vq + T * VQT;              // [T][NR] cplx
   static constexpr int o_gs = o_rt + 2 * T * NR;           // [T][NR] cplx
   static constexpr int o_cst = o_gs + 2 * T * NR;          // gl_t, gl_w [PT] each
   static constexpr int n_dbl = o_cst + 2 * PT;
@@ -726,6 +729,30 @@ struct TileLds {
   static constexpr int n_int = i_self + T;
   static constexpr size_t bytes = (size_t)n_dbl * 8 + (size_t)n_int * 4 + 64;
 };
+
+// Phase timers of the tile kernel, in the profiling build only (-DRRQ_PHASE_TIMERS, library
+// librrq_phases.so): thread 0 reads the shader clock at the workgroup barriers that separate
+// the phases and adds the differences per phase; the sums over workgroups are read with
+// rrq_phase_read.  Slots: 0 targets, 1 roots and target harmonics, 2 effective weights,
+// 3 contraction, 4 translation, 5 rows x maps and stores, 6 tile fetch.
+#ifdef RRQ_PHASE_TIMERS
+__device__ unsigned long long g_tile_phase[8];
+#define RRQ_PHASE_INIT                                        \
+  unsigned long long ph_[8] = {0, 0, 0, 0, 0, 0, 0, 0};       \
+  unsigned long long ph_t_ = __builtin_amdgcn_s_memtime();
+#define RRQ_PHASE(i)                                          \
+  if (threadIdx.x == 0) {                                     \
+    const unsigned long long n_ = __builtin_amdgcn_s_memtime(); \
+    ph_[i] += n_ - ph_t_;                                     \
+    ph_t_ = n_;                                               \
+  }
+#define RRQ_PHASE_FLUSH \
+  if (threadIdx.x == 0) for (int i_ = 0; i_ < 8; ++i_) atomicAdd(&g_tile_phase[i_], ph_[i_]);
+#else
+#define RRQ_PHASE_INIT
+#define RRQ_PHASE(i)
+#define RRQ_PHASE_FLUSH
+#endif
 
 // Persistent workgroups take tiles of this order from a queue, so that the workgroups in
 // flight work on a narrow window of consecutive tiles (tiles of one patch are consecutive)
@@ -769,6 +796,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (input_bad(tg)) return;
+  RRQ_PHASE_INIT
   const int64_t tlo = qtile[0], thi = qtile[1];
   if (tid < PT) {
     cgl_t[tid] = od.gl_t[tid];
@@ -781,6 +809,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
   const int xcd = blockIdx.x % kXcds;
   int round = 0;
   for (;;) {
+    RRQ_PHASE(5)
     __syncthreads();
     if (tid == 0) {
       long long next = -1;
@@ -797,6 +826,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       s_ti = next;
     }
     __syncthreads();
+    RRQ_PHASE(6)
     const int64_t ti = s_ti;
     if (ti < 0) break;
     const int4 tile = tiles[ti];
@@ -806,6 +836,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
     for (int sub = 0; sub < tile.z; sub += T) {
       const int nt = min(T, tile.z - sub);
       __syncthreads();
+      RRQ_PHASE(5)
       // ---- patch data
       if (tid < kFrame) fr[tid] = pd.frame[(int64_t)P * kFrame + tid];
       __syncthreads();
@@ -838,6 +869,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
+      RRQ_PHASE(0)
       // ---- Step 5 results (root pre-pass) per (target, edge); Step 4: target harmonics
       if (tid < 4 * nt) {
         const int t = tid >> 2, e = tid & 3;
@@ -851,6 +883,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         solid_table<Q>(sx[t * 3 + 1], sx[t * 3 + 2], sx[t * 3 + 0], Rt + t * NR);
       }
       __syncthreads();
+      RRQ_PHASE(1)
       // ---- effective weights per (target, edge, node), PTP lanes per (target, edge), and
       // the Omega sums of each (target, edge) by a segmented lane reduction
       for (int idx = tid; idx < T * 4 * PTP; idx += BNT) {
@@ -920,6 +953,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
+      RRQ_PHASE(2)
       if (tid < nt) {
         const int t = tid;
         double o[4] = {0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
@@ -931,6 +965,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
         for (int c = 0; c < 4; ++c) { som[t * 4 + c] = o[c]; sdom[t * 4 + c] = d[c]; }
       }
+      __syncthreads();   // the partial sums share their LDS with the moments written next
       // ---- Step 6: contraction with the edge tables, items (j,k) x target; then the normal
       // derivatives nu'.grad S^{ab} at the targets, items (target, a, b)
       const double* tb = pd.tabs + pd.tab_off[P];
@@ -1005,7 +1040,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
 #pragma unroll
           for (int u = 0; u < 12; ++u) cur[u] = nx[u];
         }
-        double* o = vq + (t * NJK + n) * 18;
+        double* o = vq + t * L::VQT + vq_rec(n);
         o[0] = V0; o[1] = V1;
         for (int c = 0; c < 4; ++c) {
           o[2 + 2 * c] = Qr[c]; o[3 + 2 * c] = Qi[c];
@@ -1013,11 +1048,12 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
+      RRQ_PHASE(3)
       // ---- Steps 7-8: translation and rows, items (target, slot): a slot holds the term list
       // of one (l, m) or half of a long one; the two halves of a list sit on adjacent lanes
       // and are added with one lane exchange
       for (int idx = tid; idx < T * od.nslot; idx += BNT) {
-        const int t = idx / od.nslot, code = od.tslot[idx % od.nslot];
+        const int t = idx / od.nslot, slot = idx % od.nslot, code = od.tslot[slot];
         const int lm = code & 0xff, kind = code >> 8;
         const bool act = t < nt && kind != 3;
         int l = 1;
@@ -1026,27 +1062,25 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         const int tt = t < nt ? t : 0;
         const cplx* R = Rt + tt * NR;
         const cplx* G = gS + tt * NR;
-        const double* VQ = vq + tt * NJK * 18;
+        const double* VQ = vq + tt * L::VQT;
         // imaginary parts of I[alpha] (quaternion), of its normal derivative and of the
         // single-layer sum
         double Ia[4] = {0, 0, 0, 0}, dIa[4] = {0, 0, 0, 0}, sl = 0.0;
         // one pass over the (j, k) terms of this (l, m): single-layer sum (weights D_{j,l})
         // and double-layer sums (weights C_{j,l}, zero for j = 1); the signs of conjugation
         // (k < 0) and of S^{(a,b)} for b < 0 are folded into the weights
-        int it0 = od.mrg_ptr[lm], it1 = od.mrg_ptr[lm + 1];
-        const int mid = (it0 + it1) >> 1;
-        if (kind == 1) it1 = mid;
-        else if (kind == 2) it0 = mid;
-        if (!act) it1 = it0;
+        // (the slot's terms are read step-major: the lanes' entries of a step are adjacent)
+        const int len = act ? od.tlen[slot] : 0;
 #pragma unroll 1
-        for (int it = it0; it < it1; ++it) {
-          const Term2 tm = od.mrg[it];
-          const cplx s_ = R[tm.r];
-          const cplx g_ = G[tm.r];
-          const double csi = tm.cDi * s_.im, csr = tm.cDr * s_.re;
-          const double cgi = tm.cDi * g_.im, cgr = tm.cDr * g_.re;
-          const double* q = VQ + tm.n * 18;
-          sl = fma(tm.cSi * q[0], s_.im, fma(tm.cSr * q[1], s_.re, sl));
+        for (int it = 0; it < len; ++it) {
+          const int2 nr = od.tnr[it * od.nslot + slot];
+          const double4 cf = od.tcf[it * od.nslot + slot];
+          const cplx s_ = R[nr.y];
+          const cplx g_ = G[nr.y];
+          const double csi = cf.y * s_.im, csr = cf.x * s_.re;
+          const double cgi = cf.y * g_.im, cgr = cf.x * g_.re;
+          const double* q = VQ + nr.x;
+          sl = fma(cf.w * q[0], s_.im, fma(cf.z * q[1], s_.re, sl));
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const double xr = q[2 + 2 * c], xi = q[3 + 2 * c];
@@ -1122,6 +1156,7 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         }
       }
       __syncthreads();
+      RRQ_PHASE(4)
       // ---- Step 8 with the density (potentials mode): pair potentials rows . c_K with the
       // patch coefficients c_K = M_K sigma_P, minus the smooth rule over the patch nodes
       if constexpr (POT) {
@@ -1205,20 +1240,24 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             double acc[2 * TQ], acc2[2 * TQ];
 #pragma unroll
             for (int a = 0; a < 2 * TQ; ++a) acc[a] = acc2[a] = 0.0;
-            // 8 k-steps per batch: map operands loaded first (8 loads in flight), then the
-            // row operands and MFMAs of every accumulator, alternating between two partial
-            // sums so that consecutive MFMAs do not wait on each other.  Loads are
-            // unconditional, at clamped indices: the map operand is then zeroed past row KR
-            // (so the clamped row entries there add exact zeros), and rows of targets past
-            // nt read target 0's row (row m of the product depends on row m of A only, and
-            // those rows are not stored).
+            // 8 k-steps per batch: the map operands of the next batch are loaded before this
+            // batch's row operands and MFMAs (8 loads in flight behind the products), and the
+            // MFMAs alternate between two partial sums so that consecutive ones do not wait
+            // on each other.  Loads are unconditional, at clamped indices: the map operand is
+            // zeroed past row KR (so the clamped row entries there add exact zeros), and rows
+            // of targets past nt read target 0's row (row m of the product depends on row m
+            // of A only, and those rows are not stored).
+            const int bc = min(bcol, Q2 - 1);
+            double bn[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) bn[u] = M[min(4 * u + kr, KR - 1) * Q2 + bc];
             for (int kb = 0; kb < KR; kb += 32) {
               double bv[8];
 #pragma unroll
               for (int u = 0; u < 8; ++u) {
                 const int k = kb + 4 * u + kr;
-                const double b = M[min(k, KR - 1) * Q2 + min(bcol, Q2 - 1)];
-                bv[u] = (bval && k < KR) ? b : 0.0;
+                bv[u] = (bval && k < KR) ? bn[u] : 0.0;
+                bn[u] = M[min(k + 32, KR - 1) * Q2 + bc];
               }
 #pragma unroll
               for (int a = 0; a < 2 * TQ; ++a) {
@@ -1291,6 +1330,8 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       }
     }
   }
+  RRQ_PHASE(5)
+  RRQ_PHASE_FLUSH
 }
 
 #define RRQ_TILE_CASES(X) X(4, 4) X(4, 8) X(5, 4) X(5, 8) X(6, 4) X(6, 8) X(8, 4) X(8, 8) X(10, 4)
@@ -1439,3 +1480,15 @@ hipError_t launch_smooth_direct(const PlanDev& pd, const TargetsDev& tg, uint32_
 }
 
 }  // namespace rrq
+
+#ifdef RRQ_PHASE_TIMERS
+// profiling build only: the per-phase sums of the tile kernel's timers (8 values), and their
+// reset; both synchronise with the device
+extern "C" int rrq_phase_read(unsigned long long* host8) {
+  return (int)hipMemcpyFromSymbol(host8, HIP_SYMBOL(rrq::g_tile_phase), 8 * sizeof(unsigned long long));
+}
+extern "C" int rrq_phase_reset() {
+  const unsigned long long z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  return (int)hipMemcpyToSymbol(HIP_SYMBOL(rrq::g_tile_phase), z, sizeof(z));
+}
+#endif

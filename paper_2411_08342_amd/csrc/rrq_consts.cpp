@@ -203,6 +203,35 @@ OrderTables build_order_tables(int q, int pt) {
     }
   }
   if (T.tslot.size() & 1) T.tslot.push_back(3 << 8);
+  // step-major copy of each slot's terms (a half list is the first or second half of its
+  // (l, m) list, split at the midpoint, in list order)
+  const int ns = (int)T.tslot.size();
+  T.tlen.assign(ns, 0);
+  std::vector<int> tbeg(ns, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    const int lm = T.tslot[sl] & 0xff, kind = T.tslot[sl] >> 8;
+    if (kind == 3) continue;
+    int it0 = T.mrg_ptr[lm], it1 = T.mrg_ptr[lm + 1];
+    const int mid = (it0 + it1) >> 1;
+    if (kind == 1) it1 = mid;
+    else if (kind == 2) it0 = mid;
+    tbeg[sl] = it0;
+    T.tlen[sl] = it1 - it0;
+    T.tsteps = std::max(T.tsteps, it1 - it0);
+  }
+  T.tnr.assign((size_t)T.tsteps * ns * 2, 0);
+  T.tcf.assign((size_t)T.tsteps * ns * 4, 0.0);
+  for (int sl = 0; sl < ns; ++sl)
+    for (int i = 0; i < T.tlen[sl]; ++i) {
+      const Term2& t2 = T.mrg[tbeg[sl] + i];
+      const size_t e = (size_t)i * ns + sl;
+      T.tnr[2 * e] = vq_rec(t2.n);
+      T.tnr[2 * e + 1] = t2.r;
+      T.tcf[4 * e] = t2.cDr;
+      T.tcf[4 * e + 1] = t2.cDi;
+      T.tcf[4 * e + 2] = t2.cSr;
+      T.tcf[4 * e + 3] = t2.cSi;
+    }
   return T;
 }
 

@@ -14,6 +14,10 @@ constexpr int kOrders[kNumOrders] = {4, 5, 6, 8, 10};
 __host__ __device__ constexpr int np_of(int p) { return p * (p + 1) / 2; }
 __host__ __device__ constexpr int njk_of(int p) { return p * (p + 3) / 2; }   // (j,k), 1<=j<=p, 0<=k<=j
 __host__ __device__ constexpr int jk_index(int j, int k) { return j * (j + 1) / 2 - 1 + k; }
+// LDS offset (doubles) of the 18 moments of (j,k) index n within a target's block: one spare
+// double after every 8 records, so that 8-byte reads of lane-scattered records fall on all 32
+// banks (the record stride alone, 36 dwords, reaches only every fourth bank)
+__host__ __device__ constexpr int vq_rec(int n) { return 18 * n + (n >> 3); }
 
 // one term of a translation sum: out[lm] += coef * X^{(j,|k|)} (conj if neg) * S^{(a,b)}(x)
 struct Term {
@@ -56,6 +60,13 @@ struct OrderTables {
   // first / second half (the two halves sit at an even and the next odd slot), 3 = padding;
   // even length
   std::vector<int32_t> tslot;
+  // the slots' term lists step-major: entry (step, slot) at step * tslot.size() + slot, so
+  // that the lanes of a wavefront, one slot each, read consecutive entries at every step;
+  // tlen[slot] terms per slot (0 for padding), tsteps = the longest
+  int tsteps = 0;
+  std::vector<int32_t> tlen;
+  std::vector<int32_t> tnr;            // [tsteps][nslot][2]: vq_rec(n), r
+  std::vector<double> tcf;             // [tsteps][nslot][4]: cDr, cDi, cSr, cSi
 };
 
 void gauss_legendre_ld(int n, std::vector<double>& t, std::vector<double>& w);

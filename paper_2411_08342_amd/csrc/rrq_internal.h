@@ -29,6 +29,9 @@ struct OrderDev {
   const Term2* mrg;
   const int32_t* tslot;     // translation work slots (see OrderTables::tslot)
   int nslot;
+  const int32_t* tlen;      // terms per slot
+  const int2* tnr;          // [tsteps][nslot]: vq_rec(n), r (step-major, see OrderTables)
+  const double4* tcf;       // [tsteps][nslot]: cDr, cDi, cSr, cSi
 };
 
 // per-patch data layout constants
