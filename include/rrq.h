@@ -154,12 +154,13 @@ rrq_status rrq_plan_refit(rrq_plan* plan, const rrq_surface* surf, void* stream)
 rrq_status rrq_plan_destroy(rrq_plan* plan);
 
 /* Conditioning of each patch's weighted least-squares fits (Steps 1-2; the study of the
- * system matrix in Sec. 5): cond[2P'] = max|R_ii| / min|R_ii| of the Householder QR of the
- * DLP system (4q^2 x 4n_p, eq. dlpdensitylinearsystem2) of patch P', cond[2P'+1] the same for
- * the SLP system (q^2 x n_p, eq. slpdensitylinearsystem).  Each is a lower bound of the
- * 2-norm condition number of its weighted system.  The fits still produce maps whatever the
- * value; a caller flags patches against its own threshold (near 1/eps the fitted density
- * loses accuracy).  cond is a HOST array of 2P doubles, filled from the last plan_create or
+ * system matrix in Sec. 5): cond[2P'] = ||A_w||_F ||A_w^+||_F, the Frobenius-norm condition
+ * number of the weighted DLP system A_w (4q^2 x 4n_p, eq. dlpdensitylinearsystem2) of patch
+ * P', with A_w^+ taken from the computed solutions; cond[2P'+1] the same for the SLP system
+ * (q^2 x n_p, eq. slpdensitylinearsystem).  Each bounds the 2-norm condition number of its
+ * weighted system from above, by at most the system's rank (4 n_p, resp. n_p) times it.  The
+ * fits still produce maps whatever the value; a caller flags patches against its own
+ * threshold (near 1/eps the fitted density loses accuracy).  cond is a HOST array of 2P doubles, filled from the last plan_create or
  * plan_refit; the call synchronises `stream`. */
 rrq_status rrq_plan_fit_condition(const rrq_plan* plan, double* cond, void* stream);
 

@@ -468,6 +468,19 @@ __device__ __forceinline__ void hh_lsq(double* A, int m, int n, int ncols, int l
   }
 }
 
+// sum of v over the workgroup (NT threads); every thread gets it.  red: NT / 64 doubles of LDS
+__device__ __forceinline__ double fit_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
 int64_t fit_ws_doubles(int q) {
   const int np = np_of(q), q2 = q * q;
   const int64_t a = (int64_t)(4 * q2) * (4 * np + q2);
@@ -497,6 +510,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ double sX[4 * NP * kBackCols];
   __shared__ double sR[kRC * 4 * NP];
   __shared__ double sT[HNB * HNB], sG[HNB * HNB], sbeta[HNB], salpha[HNB];
+  __shared__ double sred[NT / 64];
   double* A = ws + (int64_t)blockIdx.x * ws_per_block;
   double* B = A + (int64_t)M * LDA;
   double* Hm = B + (int64_t)Q2 * LDB;
@@ -509,7 +523,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     for (int64_t i = tid; i < (int64_t)M * LDA; i += NT) A[i] = 0.0;
     for (int64_t i = tid; i < (int64_t)Q2 * LDB; i += NT) B[i] = 0.0;
     __syncthreads();
-    // basis at the nodes: one thread per node
+    // basis at the nodes: one thread per node; squared Frobenius norms of the weighted
+    // systems (the real DLP form holds each of F1, F2, F3 four times)
+    double nA = 0.0, nB = 0.0;
     for (int i = tid; i < Q2; i += NT) {
       const double x = pd.node_loc[0 * pd.N + n0 + i];
       const double y = pd.node_loc[1 * pd.N + n0 + i];
@@ -535,7 +551,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
           r1[0 * NP + lm] = F1;  r1[2 * NP + lm] = -F3; r1[3 * NP + lm] = F2;
           r2[0 * NP + lm] = F2;  r2[1 * NP + lm] = F3;  r2[3 * NP + lm] = -F1;
           r3[0 * NP + lm] = F3;  r3[1 * NP + lm] = -F2; r3[2 * NP + lm] = F1;
-          B[(int64_t)i * LDB + lm] = om * (F[0] * nu[0] + F[1] * nu[1] + F[2] * nu[2]);
+          const double b = om * (F[0] * nu[0] + F[1] * nu[1] + F[2] * nu[2]);
+          B[(int64_t)i * LDB + lm] = b;
+          nA += 4.0 * (F1 * F1 + F2 * F2 + F3 * F3);
+          nB += b * b;
         }
       A[(int64_t)i * LDA + 4 * NP + i] = om;
       B[(int64_t)i * LDB + NP + i] = om;
@@ -543,30 +562,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __syncthreads();
     hh_lsq(A, M, 4 * NP, LDA, LDA, sV, sV + M * HNB, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
     hh_lsq(B, Q2, NP, LDB, LDB, sV, sV + M * HNB, sT, sG, sbeta, salpha, sX, sR, 4 * NP);
-    // condition estimate of each fit: max|R_ii| / min|R_ii| (a lower bound of the 2-norm
-    // condition number of the weighted system), on wave 0 by lane reductions
-    if (tid < 64) {
-      double amax = 0.0, amin = 1e308, bmax = 0.0, bmin = 1e308;
-      for (int i = tid; i < 4 * NP; i += 64) {
-        const double r = fabs(A[(int64_t)i * LDA + i]);
-        amax = fmax(amax, r);
-        amin = fmin(amin, r);
-      }
-      for (int i = tid; i < NP; i += 64) {
-        const double r = fabs(B[(int64_t)i * LDB + i]);
-        bmax = fmax(bmax, r);
-        bmin = fmin(bmin, r);
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        amax = fmax(amax, __shfl_xor(amax, o, 64));
-        amin = fmin(amin, __shfl_xor(amin, o, 64));
-        bmax = fmax(bmax, __shfl_xor(bmax, o, 64));
-        bmin = fmin(bmin, __shfl_xor(bmin, o, 64));
-      }
-      if (tid == 0) {
-        pd.fitcond[2 * (int64_t)P] = amax / amin;
-        pd.fitcond[2 * (int64_t)P + 1] = bmax / bmin;
-      }
+    // condition estimates: Frobenius-norm condition numbers ||A_w||_F ||A_w^+||_F, with
+    // A_w^+ from the solutions (the maps over the weights; the three other block columns of
+    // the DLP pseudoinverse are the same quaternions times i, j, k, hence the factor 4)
+    double nAp = 0.0, nBp = 0.0;
+    for (int idx = tid; idx < 4 * NP * Q2; idx += NT) {
+      const int r = idx / Q2, j = idx % Q2;
+      const double v = A[(int64_t)r * LDA + 4 * NP + j];
+      nAp += 4.0 * v * v / (od.glq_w[j / Q] * od.glq_w[j % Q]);
+    }
+    for (int idx = tid; idx < NP * Q2; idx += NT) {
+      const int r = idx / Q2, j = idx % Q2;
+      const double v = B[(int64_t)r * LDB + NP + j];
+      nBp += v * v / (od.glq_w[j / Q] * od.glq_w[j % Q]);
+    }
+    nA = fit_block_sum(nA, sred);
+    nB = fit_block_sum(nB, sred);
+    nAp = fit_block_sum(nAp, sred);
+    nBp = fit_block_sum(nBp, sred);
+    if (tid == 0) {
+      pd.fitcond[2 * (int64_t)P] = sqrt(nA * nAp);
+      pd.fitcond[2 * (int64_t)P + 1] = sqrt(nB * nBp);
     }
     double* maps = pd.maps + pd.map_off[P];
     double* MD = maps;
@@ -636,6 +652,292 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// The DLP fit in quaternion arithmetic (orders whose system fits in LDS).  The real system
+// of eq. dlpdensitylinearsystem2 is the real form of left multiplication by the pure
+// quaternions F_{i,lm} = w_i (0, grad H^{lm}(r_i)) acting on c_lm = (c0, c1, c2, c3): block
+// row r of A c is component r of sum_lm F_{i,lm} c_lm, and |.| of a quaternion is the
+// 2-norm of its components, so the weighted least-squares problem is min ||F c - e|| over
+// quaternion vectors c, with the right-hand sides e = w_j e_j (scalar quaternions).  It is
+// solved by unpivoted Householder QR with quaternion reflectors H = I - beta v v^H (beta
+// real), in LDS: a q^2 x n_p quaternion matrix holds 1/16 of the entries of the real form.
+// Reflector of column k (entries x_i, i >= k): alpha = -u |x| with u = x_k / |x_k|,
+// v = x - alpha e_k, beta = 1 / (|x| (|x| + |x_k|)); then v^H x = 1 / beta is real and
+// H x = alpha e_k.  Column y: y - v (beta v^H y).  R_kk = alpha_k.
+// ---------------------------------------------------------------------------------------
+struct quat {
+  double w, x, y, z;
+};
+
+__device__ __forceinline__ quat qmul(const quat& a, const quat& b) {
+  return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z,
+          a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+          a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x,
+          a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+// conj(a) b
+__device__ __forceinline__ quat qcmul(const quat& a, const quat& b) {
+  return {a.w * b.w + a.x * b.x + a.y * b.y + a.z * b.z,
+          a.w * b.x - a.x * b.w - a.y * b.z + a.z * b.y,
+          a.w * b.y + a.x * b.z - a.y * b.w - a.z * b.x,
+          a.w * b.z - a.x * b.y + a.y * b.x - a.z * b.w};
+}
+__device__ __forceinline__ double qnorm2(const quat& a) {
+  return a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z;
+}
+
+// beta v^H y of a reflector v (column of F from row k) and a column y, both at row stride ld
+// (doubles): the eight lanes of a group (threadIdx.x mod 8) take rows k + g, k + g + 8, ...
+// and their partial sums are added by three lane exchanges within the group
+__device__ __forceinline__ quat reflect_coef(const double* v, int ldv, const double* y, int ldy,
+                                            int k, int m, double beta) {
+  quat a = {0.0, 0.0, 0.0, 0.0};
+  for (int i = k + (threadIdx.x & 7); i < m; i += 8) {
+    const quat t = qcmul(*(const quat*)(v + i * ldv), *(const quat*)(y + i * ldy));
+    a.w += t.w; a.x += t.x; a.y += t.y; a.z += t.z;
+  }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    a.w += __shfl_xor(a.w, o, 64);
+    a.x += __shfl_xor(a.x, o, 64);
+    a.y += __shfl_xor(a.y, o, 64);
+    a.z += __shfl_xor(a.z, o, 64);
+  }
+  return {beta * a.w, beta * a.x, beta * a.y, beta * a.z};
+}
+
+template <int Q>
+struct FitQ {
+  static constexpr int NP = np_of(Q), Q2 = Q * Q;
+  static constexpr int RB = Q2 < 32 ? Q2 : 32;          // right-hand sides per batch
+  // row strides (doubles) of the quaternion arrays: 16 bytes beyond whole quaternions, so
+  // that the 16-byte reads of eight consecutive lanes (rows) of one column cover all 32 banks
+  static constexpr int FS = 4 * NP + 2, YS = 4 * RB + 2;
+  static constexpr int o_F = 0;                          // [Q2][FS]: row i, column k at 4k
+  static constexpr int o_Y = o_F + Q2 * FS;              // [Q2][YS]
+  static constexpr int o_al = o_Y + Q2 * YS;             // [NP] quat: R_kk
+  static constexpr int o_be = o_al + 4 * NP;             // [NP]
+  static constexpr int n_quat = o_be + NP;
+  // the SLP fit afterwards reuses the same LDS: panels, back-substitution right-hand
+  // sides and R columns of hh_lsq for the Q2 x NP system, then T1 [Q2][Q2]
+  static constexpr int o_sV = 0, o_sX = o_sV + 2 * Q2 * HNB, o_sR = o_sX + NP * kBackCols;
+  static constexpr int o_sT = o_sR + kRC * NP, o_sG = o_sT + HNB * HNB,
+                       o_sb = o_sG + HNB * HNB, o_sa = o_sb + HNB;
+  static constexpr int n_slp = o_sa + HNB;
+  static constexpr int n_t1 = Q2 * Q2;
+  static constexpr int n_big = n_quat > n_slp ? (n_quat > n_t1 ? n_quat : n_t1)
+                                              : (n_slp > n_t1 ? n_slp : n_t1);
+  static constexpr int o_red = n_big;                    // [NT / 64] block sums
+  static constexpr size_t bytes = (size_t)(n_big + NT / 64) * 8;
+};
+
+template <int Q>
+__global__ __launch_bounds__(NT) void k_fit_quat(PlanDev pd, OrderDev od,
+                                                 const int32_t* patches, int count, double* ws,
+                                                 int64_t ws_per_block) {
+  using L = FitQ<Q>;
+  constexpr int NP = L::NP, Q2 = L::Q2, RB = L::RB;
+  constexpr int LDB = NP + Q2;
+  extern __shared__ double lds[];
+  constexpr int FS = L::FS, YS = L::YS;
+  auto Fq = [&](int i, int k) -> quat& { return *(quat*)(lds + L::o_F + i * FS + 4 * k); };
+  auto Yq = [&](int i, int c) -> quat& { return *(quat*)(lds + L::o_Y + i * YS + 4 * c); };
+  quat* al = (quat*)(lds + L::o_al);
+  double* be = lds + L::o_be;
+  // global workspace: the SLP system B [Q2][LDB] and Hmat [Q2][NP]
+  double* B = ws + (int64_t)blockIdx.x * ws_per_block;
+  double* Hm = B + (int64_t)Q2 * LDB;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int it = blockIdx.x; it < count; it += gridDim.x) {
+    const int P = patches[it];
+    const int64_t n0 = pd.node_off[P];
+    __syncthreads();
+    for (int64_t i = tid; i < (int64_t)Q2 * LDB; i += NT) B[i] = 0.0;
+    __syncthreads();
+    // basis at the nodes, one thread per node: F (LDS), B and Hmat (global); squared
+    // Frobenius norms of the weighted systems
+    double nF = 0.0, nB = 0.0;
+    for (int i = tid; i < Q2; i += NT) {
+      const double x = pd.node_loc[0 * pd.N + n0 + i];
+      const double y = pd.node_loc[1 * pd.N + n0 + i];
+      const double z = pd.node_loc[2 * pd.N + n0 + i];
+      const double nu[3] = {pd.node_loc[3 * pd.N + n0 + i], pd.node_loc[4 * pd.N + n0 + i],
+                            pd.node_loc[5 * pd.N + n0 + i]};
+      const double om = sqrt(od.glq_w[i / Q] * od.glq_w[i % Q]);
+      cplx R[tri(Q, Q) + 1];
+      solid_table<Q>(y, z, x, R);
+      int lm = 0;
+      for (int l = 1; l <= Q; ++l)
+        for (int m = 1; m <= l; ++m, ++lm) {
+          double Fa[3];
+          for (int a = 0; a < 3; ++a) Fa[a] = kSqrt2 * dS(R, l, m, a).im;
+          Hm[i * NP + lm] = kSqrt2 * R[tri(l, m)].im;
+          Fq(i, lm) = {0.0, om * Fa[0], om * Fa[1], om * Fa[2]};
+          const double b = om * (Fa[0] * nu[0] + Fa[1] * nu[1] + Fa[2] * nu[2]);
+          B[(int64_t)i * LDB + lm] = b;
+          nF += om * om * (Fa[0] * Fa[0] + Fa[1] * Fa[1] + Fa[2] * Fa[2]);
+          nB += b * b;
+        }
+      B[(int64_t)i * LDB + NP + i] = om;
+    }
+    double* red = lds + L::o_red;
+    nF = fit_block_sum(nF, red);
+    nB = fit_block_sum(nB, red);
+    // quaternion Householder QR of F
+    for (int k = 0; k < NP; ++k) {
+      if (wv == 0) {
+        double s2 = 0.0;
+        for (int i = k + lane; i < Q2; i += 64) s2 += qnorm2(Fq(i, k));
+        const double nrm = sqrt(wave_sum(s2));
+        if (lane == 0) {
+          const quat xk = Fq(k, k);
+          const double ak = sqrt(qnorm2(xk));
+          const quat u = ak > 0.0 ? quat{xk.w / ak, xk.x / ak, xk.y / ak, xk.z / ak}
+                                  : quat{1.0, 0.0, 0.0, 0.0};
+          if (nrm > 0.0) {
+            al[k] = {-u.w * nrm, -u.x * nrm, -u.y * nrm, -u.z * nrm};
+            be[k] = 1.0 / (nrm * (nrm + ak));
+            const double f = ak + nrm;
+            Fq(k, k) = {u.w * f, u.x * f, u.y * f, u.z * f};
+          } else {
+            al[k] = {0.0, 0.0, 0.0, 0.0};
+            be[k] = 0.0;
+          }
+        }
+      }
+      __syncthreads();
+      // later columns: threads = (column, group of rows i = k + g mod 8)
+      const double bk = be[k];
+      for (int j = k + 1 + (tid >> 3); j < NP; j += NT / 8) {
+        const quat sv = reflect_coef(lds + L::o_F + 4 * k, FS, lds + L::o_F + 4 * j, FS, k, Q2,
+                                     bk);
+        for (int i = k + (tid & 7); i < Q2; i += 8) {
+          const quat t = qmul(Fq(i, k), sv);
+          quat& f = Fq(i, j);
+          f.w -= t.w; f.x -= t.x; f.y -= t.y; f.z -= t.z;
+        }
+      }
+      __syncthreads();
+    }
+    double nFp = 0.0;   // squared Frobenius norm of F^+ (maps over the weights), this thread's
+    double* maps = pd.maps + pd.map_off[P];
+    double* MD = maps;
+    double* MSp = maps + 4 * NP * Q2;
+    // right-hand sides w_j e_j in batches of RB: reflectors, then back substitution with R
+    for (int j0 = 0; j0 < Q2; j0 += RB) {
+      for (int idx = tid; idx < Q2 * RB; idx += NT) {
+        const int i = idx / RB, c = idx % RB;
+        Yq(i, c) = {i == j0 + c ? sqrt(od.glq_w[i / Q] * od.glq_w[i % Q]) : 0.0, 0.0, 0.0, 0.0};
+      }
+      __syncthreads();
+      for (int k = 0; k < NP; ++k) {
+        const double bk = be[k];
+        for (int c = tid >> 3; c < RB; c += NT / 8) {
+          const quat sv = reflect_coef(lds + L::o_F + 4 * k, FS, lds + L::o_Y + 4 * c, YS, k,
+                                       Q2, bk);
+          for (int i = k + (tid & 7); i < Q2; i += 8) {
+            const quat t = qmul(Fq(i, k), sv);
+            quat& yv = Yq(i, c);
+            yv.w -= t.w; yv.x -= t.x; yv.y -= t.y; yv.z -= t.z;
+          }
+        }
+        __syncthreads();
+      }
+      // R c = y (rows 0..NP-1): c_k = R_kk^{-1} y_k, then y_i -= R_ik c_k for i < k
+      for (int k = NP - 1; k >= 0; --k) {
+        if (tid < RB) {
+          const quat a = al[k];
+          const double inv = 1.0 / qnorm2(a);
+          const quat ai = {a.w * inv, -a.x * inv, -a.y * inv, -a.z * inv};
+          Yq(k, tid) = qmul(ai, Yq(k, tid));
+        }
+        __syncthreads();
+        for (int idx = tid; idx < k * RB; idx += NT) {
+          const int i = idx / RB, c = idx % RB;
+          const quat t = qmul(Fq(i, k), Yq(k, c));
+          quat& yv = Yq(i, c);
+          yv.w -= t.w; yv.x -= t.x; yv.y -= t.y; yv.z -= t.z;
+        }
+        __syncthreads();
+      }
+      // M_D columns (component-major rows b NP + lm) and M_Sp columns: c (0, nu_j); the
+      // last batch may reach past column Q2 - 1 (its extra columns are zero and not stored)
+      for (int idx = tid; idx < NP * RB; idx += NT) {
+        const int lm = idx / RB, c = idx % RB, j = j0 + c;
+        if (j >= Q2) continue;
+        const quat v = Yq(lm, c);
+        nFp += qnorm2(v) / (od.glq_w[j / Q] * od.glq_w[j % Q]);
+        MD[(0 * NP + lm) * Q2 + j] = v.w;
+        MD[(1 * NP + lm) * Q2 + j] = v.x;
+        MD[(2 * NP + lm) * Q2 + j] = v.y;
+        MD[(3 * NP + lm) * Q2 + j] = v.z;
+        const double v1 = pd.node_loc[3 * pd.N + n0 + j];
+        const double v2 = pd.node_loc[4 * pd.N + n0 + j];
+        const double v3 = pd.node_loc[5 * pd.N + n0 + j];
+        MSp[(0 * NP + lm) * Q2 + j] = -(v.x * v1 + v.y * v2 + v.z * v3);
+        MSp[(1 * NP + lm) * Q2 + j] = v.w * v1 + (v.y * v3 - v.z * v2);
+        MSp[(2 * NP + lm) * Q2 + j] = v.w * v2 + (v.z * v1 - v.x * v3);
+        MSp[(3 * NP + lm) * Q2 + j] = v.w * v3 + (v.x * v2 - v.y * v1);
+      }
+      __syncthreads();
+    }
+    // SLP fit (real, Q2 x NP): blocked Householder in the same LDS
+    hh_lsq(B, Q2, NP, LDB, LDB, lds + L::o_sV, lds + L::o_sV + Q2 * HNB, lds + L::o_sT,
+           lds + L::o_sG, lds + L::o_sb, lds + L::o_sa, lds + L::o_sX, lds + L::o_sR, NP);
+    double* MS = maps + 8 * NP * Q2;
+    double nBp = 0.0;
+    for (int idx = tid; idx < NP * Q2; idx += NT) {
+      const int r = idx / Q2, j = idx % Q2;
+      const double v = B[(int64_t)r * LDB + NP + j];
+      MS[idx] = v;
+      nBp += v * v / (od.glq_w[j / Q] * od.glq_w[j % Q]);
+    }
+    // condition estimates: Frobenius-norm condition numbers ||A_w||_F ||A_w^+||_F of the
+    // weighted systems (the real DLP form has 4x the squared norms of the quaternion ones)
+    nFp = fit_block_sum(nFp, red);
+    nBp = fit_block_sum(nBp, red);
+    if (tid == 0) {
+      pd.fitcond[2 * (int64_t)P] = 4.0 * sqrt(nF * nFp);
+      pd.fitcond[2 * (int64_t)P + 1] = sqrt(nB * nBp);
+    }
+    // T1 = Hmat (Q2 x NP) B^+ (NP x Q2) in LDS; M_S lower block = M_D T1 (M_D from the maps
+    // just written: this workgroup's own stores)
+    double* T1 = lds;
+    for (int it2 = tid; it2 < ((Q2 + kRB - 1) / kRB) * Q2; it2 += NT) {
+      const int i0 = (it2 / Q2) * kRB, j = it2 % Q2;
+      double acc[kRB];
+#pragma unroll
+      for (int u = 0; u < kRB; ++u) acc[u] = 0.0;
+      for (int n = 0; n < NP; ++n) {
+        const double b = B[(int64_t)n * LDB + NP + j];
+#pragma unroll
+        for (int u = 0; u < kRB; ++u)
+          if (i0 + u < Q2) acc[u] = fma(Hm[(i0 + u) * NP + n], b, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kRB; ++u)
+        if (i0 + u < Q2) T1[(i0 + u) * Q2 + j] = acc[u];
+    }
+    __syncthreads();
+    for (int it2 = tid; it2 < ((4 * NP + kRB - 1) / kRB) * Q2; it2 += NT) {
+      const int r0 = (it2 / Q2) * kRB, j = it2 % Q2;
+      double acc[kRB];
+#pragma unroll
+      for (int u = 0; u < kRB; ++u) acc[u] = 0.0;
+      for (int i = 0; i < Q2; ++i) {
+        const double t = T1[i * Q2 + j];
+#pragma unroll
+        for (int u = 0; u < kRB; ++u)
+          if (r0 + u < 4 * NP) acc[u] = fma(MD[(r0 + u) * Q2 + i], t, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kRB; ++u)
+        if (r0 + u < 4 * NP) MS[NP * Q2 + (r0 + u) * Q2 + j] = acc[u];
+    }
+    __syncthreads();
+  }
+}
+
 #define RRQ_FOR_ORDERS(X) X(4) X(5) X(6) X(8) X(10)
 
 hipError_t launch_geometry(const PlanDev& pd, const rrq_surface& s, const OrderDev& od,
@@ -666,14 +968,34 @@ hipError_t launch_edge_tables(const PlanDev& pd, const OrderDev& od, const int32
   return hipGetLastError();
 }
 
+// Orders whose quaternion DLP system fits in LDS take k_fit_quat; order 10 takes the real QR
+// in global memory (k_fit).
+template <int Q>
+static hipError_t launch_fit_quat(const PlanDev& pd, const OrderDev& od, const int32_t* patches,
+                                  int count, double* ws, int64_t ws_per_block, int grid,
+                                  hipStream_t st) {
+  const size_t lds = FitQ<Q>::bytes;
+  static_assert(FitQ<Q>::bytes <= 160 * 1024, "quaternion fit exceeds the LDS");
+  hipError_t e = hipFuncSetAttribute((const void*)k_fit_quat<Q>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fit_quat<Q>, dim3(grid), dim3(NT), lds, st, pd, od, patches, count, ws,
+                     ws_per_block);
+  return hipGetLastError();
+}
+
 hipError_t launch_fit(const PlanDev& pd, const OrderDev& od, const int32_t* patches, int count,
                       double* ws, int64_t ws_per_block, int blocks, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const int grid = count < blocks ? count : blocks;
   switch (od.q) {
-#define X(q) case q: hipLaunchKernelGGL(k_fit<q>, dim3(grid), dim3(NT), 0, st, pd, od, patches, count, ws, ws_per_block); break;
-    RRQ_FOR_ORDERS(X)
+#define X(q) case q: return launch_fit_quat<q>(pd, od, patches, count, ws, ws_per_block, grid, st);
+    X(4) X(5) X(6) X(8)
 #undef X
+    case 10:
+      hipLaunchKernelGGL(k_fit<10>, dim3(grid), dim3(NT), 0, st, pd, od, patches, count, ws,
+                         ws_per_block);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -58,7 +58,7 @@ struct PlanDev {
   double* tabs;             // per patch: [4 pt][6][njk] (re, im): c (3 cplx), h (3 cplx)
   const int64_t* tab_off;
   const float* mlp;         // learned-guess network, ABI parameter layout (or null)
-  double* fitcond;          // [P][2]: max|R_ii| / min|R_ii| of the DLP and SLP fits
+  double* fitcond;          // [P][2]: ||A_w||_F ||A_w^+||_F of the DLP and SLP fits
 };
 
 struct TargetsDev {

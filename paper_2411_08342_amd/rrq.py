@@ -233,7 +233,8 @@ class Plan:
                                       _stream()))
 
     def fit_condition(self):
-        """(P, 2) host array: max|R_ii| / min|R_ii| of the DLP and SLP fits of every patch."""
+        """(P, 2) host array: Frobenius-norm condition numbers ||A_w||_F ||A_w^+||_F of the
+        weighted DLP and SLP systems of every patch."""
         out = np.zeros((self.dsurf.npatch, 2))
         _check(lib().rrq_plan_fit_condition(self.handle, out.ctypes.data, _stream()))
         return out
