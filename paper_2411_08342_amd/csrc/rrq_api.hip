@@ -45,6 +45,7 @@ struct rrq_plan {
   double* edge_loc_d = nullptr;
   double* edge_tan_d = nullptr;
   double* edge_coef_d = nullptr;
+  double* edge_chord_d = nullptr;  // [P][4][6]
   double* maps_d = nullptr;
   int64_t* map_off_d = nullptr;
   double* tabs_d = nullptr;
@@ -82,6 +83,7 @@ struct rrq_plan {
     d.edge_loc = edge_loc_d;
     d.edge_tan = edge_tan_d;
     d.edge_coef = edge_coef_d;
+    d.edge_chord = edge_chord_d;
     d.maps = maps_d;
     d.map_off = map_off_d;
     d.tabs = tabs_d;
@@ -97,7 +99,7 @@ static void plan_free(rrq_plan* p) {
   void* ptrs[] = {p->order_d, p->node_off_d, p->edge_off_d, p->node_xyz_d, p->node_nrm_d,
                   p->node_wt_d, p->frame_d, p->node_loc_d, p->edge_loc_d, p->edge_tan_d,
                   p->edge_coef_d, p->maps_d, p->map_off_d, p->tabs_d, p->tab_off_d,
-                  p->fit_ws_d, p->perm_d, p->mlp_d, p->fitcond_d};
+                  p->fit_ws_d, p->perm_d, p->mlp_d, p->fitcond_d, p->edge_chord_d};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int q = 0; q <= kMaxQ; ++q)
@@ -332,6 +334,7 @@ rrq_status rrq_plan_create(const rrq_surface* s, const rrq_options* opts, void* 
   ok &= dalloc(&p->edge_loc_d, 3 * p->E) == hipSuccess;
   ok &= dalloc(&p->edge_tan_d, 3 * p->E) == hipSuccess;
   ok &= dalloc(&p->edge_coef_d, 3 * p->E) == hipSuccess;
+  ok &= dalloc(&p->edge_chord_d, 24 * (size_t)p->P) == hipSuccess;
   ok &= dalloc(&p->maps_d, map_off[p->P]) == hipSuccess;
   ok &= dalloc(&p->map_off_d, p->P + 1) == hipSuccess;
   ok &= dalloc(&p->tabs_d, tab_off[p->P]) == hipSuccess;
@@ -433,12 +436,13 @@ static TargetsDev tdev(const rrq_targets* tg, const unsigned* bad = nullptr) {
 // cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders][xcds] u64 |
 // sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
-// nearf[4 nnz] u8 | pairpot[nnz][4] f64 | pcoef[P][kCoefStride] f64 | nlist[4 nnz] i64 |
+// nearf[4 nnz] u8 | pairpot[nnz][4] f64 | plocal[nnz][9] f64 | pcoef[P][kCoefStride] f64 |
+// nlist[4 nnz] i64 |
 // lamg[4 nnz][lam_stride] f64 (near-edge moments; lam_stride = 2 ptilde_max + 1 >= 5; before
 // them, the root passes' Newton and retry lists, 4 nnz i64 each)
 struct WsLayout {
   size_t owner, counters, bad, pflags, cnt, fill, start, tstart, ntiles, queue, sorted, tiles,
-      part, root, nearf, pairpot, pcoef, nlist, lamg, total;
+      part, root, nearf, pairpot, plocal, pcoef, nlist, lamg, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P, int lam_stride) {
@@ -461,6 +465,7 @@ static WsLayout ws_layout(int64_t nnz, int P, int lam_stride) {
   w.root = o; o = al(o + 4 * n * 16);
   w.nearf = o; o = al(o + 4 * n);
   w.pairpot = o; o = al(o + 4 * n * 8);
+  w.plocal = o; o = al(o + 9 * n * 8);
   w.pcoef = o; o = al(o + (size_t)P * kCoefStride * 8);
   w.nlist = o; o = al(o + 4 * n * 8);
   w.lamg = o; o = al(o + 4 * n * (size_t)lam_stride * 8);
@@ -650,6 +655,7 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
   ao.root = nullptr;
   ao.nearf = nullptr;
   ao.lamg = nullptr;
+  ao.plocal = nullptr;
   ao.lam_stride = 0;
   ao.dens = density;
   ao.pcoef = pot ? (const double*)(wb + wl.pcoef) : nullptr;
@@ -696,6 +702,10 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
     if (launch_binning(td, p->P, p->order_d, p->perm_d, bo, cnt, fill, start, tstart, ntiles,
                        sorted, tiles, qtile, qctr, st) != hipSuccess)
       return RRQ_ERR_DEVICE;
+    double* plocal = (double*)(wb + wl.plocal);
+    if (launch_pair_local(pd, td, owner, sorted, plocal, st) != hipSuccess)
+      return RRQ_ERR_DEVICE;
+    ao.plocal = plocal;
     {
       RootOpts ro;
       for (int q = 0; q <= kMaxQ; ++q) ro.rho_far[q] = p->rho_far[q];
@@ -716,7 +726,7 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       for (int qi = 0; qi < kNumOrders; ++qi) {
         const int q = kOrders[qi];
         if (p->patches_h[q].empty()) continue;
-        if (launch_lambda(q, pd, p->od[q], td, owner, root, nlist, counters, pflags, lamg,
+        if (launch_lambda(q, pd, p->od[q], td, owner, root, nlist, plocal, counters, pflags, lamg,
                           lam_stride, p->rho_far[q], st) != hipSuccess)
           return RRQ_ERR_DEVICE;
       }
@@ -1263,9 +1273,11 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   if (r == RRQ_OK && (hipEventRecord(fork, cs) != hipSuccess ||
                       hipStreamWaitEvent(ms, fork, 0) != hipSuccess))
     r = RRQ_ERR_DEVICE;
+  // the maps and the edge tables, which only the tile kernels read, on the second branch;
+  // the pair offsets, binning, roots and near-edge moments on this one
   if (r == RRQ_OK) r = run_fits(p, ms);
+  if (r == RRQ_OK) r = run_edge_tables(p, ms);
   if (r == RRQ_OK && hipEventRecord(join, ms) != hipSuccess) r = RRQ_ERR_DEVICE;
-  if (r == RRQ_OK) r = run_edge_tables(p, cs);
   if (r == RRQ_OK) r = rrq_pair_offsets(p, tg, pair_off, workspace, workspace_bytes, nullptr, cs);
   if (r == RRQ_OK) {
     double* outs[4] = {out_S, out_D, out_Sp, out_Dp};

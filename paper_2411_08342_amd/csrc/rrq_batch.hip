@@ -261,7 +261,7 @@ __device__ int wave_graded_panels(double a, double b, double rho, double* wpan, 
 // pass: classification (chord root of every slot; Newton list), Newton from the chord start
 // or from the learned start (near list; learned form: retry list of the rejected guesses),
 // and, in the learned form, plain Newton over the retry list.  List entries are reserved
-// once per wavefront.  Counters: near edges, iterations, failures, learned accepts, largest
+// once per 1024-slot chunk (classification) or per wavefront (Newton passes).  Counters: near edges, iterations, failures, learned accepts, largest
 // count, the sum over wavefronts of their largest count, and the count histogram.
 // ---------------------------------------------------------------------------------------
 constexpr int kLearnedMaxit = 8;
@@ -274,6 +274,7 @@ struct RootSlot {
   int q, PT;
   double xl[3];
   const double* cf;
+  const double* chord;      // m[3], d[3]
 };
 
 __device__ __forceinline__ RootSlot root_slot(const PlanDev& pd, const TargetsDev& tg,
@@ -288,6 +289,7 @@ __device__ __forceinline__ RootSlot root_slot(const PlanDev& pd, const TargetsDe
   const double xg[3] = {tg.xyz[g], tg.xyz[tg.T + g], tg.xyz[2 * tg.T + g]};
   frame_point(pd.frame + (int64_t)P * kFrame, xg, r.xl);
   r.cf = pd.edge_coef + pd.edge_off[P] + (int64_t)e * r.PT;
+  r.chord = pd.edge_chord + ((int64_t)P * 4 + e) * 6;
   return r;
 }
 
@@ -351,24 +353,36 @@ __global__ __launch_bounds__(256) void k_root_classify(PlanDev pd, TargetsDev tg
                                                        double2* root, uint8_t* nearf,
                                                        int64_t* qlist,
                                                        unsigned long long* counters) {
+  // chunks of kC slots per workgroup: the chunk's Newton slots are gathered in LDS and the
+  // list is reserved once per chunk (one counter atomic per kC slots, not per wavefront)
+  constexpr int kC = 1024;
+  __shared__ int64_t qs[kC];
+  __shared__ int qn;
+  __shared__ long long qbase;
   if (input_bad(tg)) return;
+  const int tid = threadIdx.x;
   const int64_t nslot = 4 * tg.nnz;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x; s0 < nslot; s0 += stride) {
-    const int64_t slot = s0 + threadIdx.x;
-    bool queue = false;
-    if (slot < nslot) {
+  for (int64_t base = (int64_t)blockIdx.x * kC; base < nslot; base += (int64_t)gridDim.x * kC) {
+    __syncthreads();
+    if (tid == 0) qn = 0;
+    __syncthreads();
+    for (int i = tid; i < kC; i += blockDim.x) {
+      const int64_t slot = base + i;
+      if (slot >= nslot) break;
       const RootSlot r = root_slot(pd, tg, owner, slot);
-      double m[3], dv[3];
-      edge_chord(r.cf, r.PT, m, dv, 1, pd.E);
-      const cplx ts = chord_root(m, dv, r.xl);
-      queue = bernstein_rho(ts) <= ro.rho_far[r.q];
-      if (!queue) {
+      const cplx ts = chord_root(r.chord, r.chord + 3, r.xl);
+      if (bernstein_rho(ts) <= ro.rho_far[r.q]) {
+        qs[atomicAdd(&qn, 1)] = slot;
+      } else {
         root[slot] = make_double2(ts.re, ts.im);
         nearf[slot] = 0;
       }
     }
-    wave_append(queue, slot, qlist, &counters[kCQueueList]);
+    __syncthreads();
+    if (tid == 0)
+      qbase = qn > 0 ? (long long)atomicAdd(&counters[kCQueueList], (unsigned long long)qn) : 0;
+    __syncthreads();
+    for (int i = tid; i < qn; i += blockDim.x) qlist[qbase + i] = qs[i];
   }
 }
 
@@ -443,9 +457,7 @@ __global__ __launch_bounds__(256) void k_root_newton(PlanDev pd, TargetsDev tg,
         }
       } else {
         const int its0 = MODE == 2 ? (int)(ent >> kItsShift) : 0;
-        double m[3], dv[3];
-        edge_chord(r.cf, r.PT, m, dv, 1, pd.E);
-        cplx tp = chord_root(m, dv, r.xl);
+        cplx tp = chord_root(r.chord, r.chord + 3, r.xl);
         const int conv = newton_solve(r.cf, r.PT, r.xl, &tp, ro.newton_tol, ro.newton_maxit,
                                       &its, 1, pd.E);
         if (tp.im < 0) tp.im = -tp.im;
@@ -473,9 +485,9 @@ hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* o
                        int64_t* qlist, int64_t* rlist, int64_t* nlist,
                        unsigned long long* counters, uint32_t* pflags, hipStream_t st) {
   const int64_t nslot = 4 * tg.nnz;
-  int64_t g = (nslot + 255) / 256;
+  int64_t g = (nslot + 1023) / 1024;
   if (g < 1) g = 1;
-  const dim3 gc((unsigned)(g < 8192 ? g : 8192)), gn(1024), b(256);
+  const dim3 gc((unsigned)(g < 4096 ? g : 4096)), gn(1024), b(256);
   const float* mw = (const float*)pd.mlp;
   hipLaunchKernelGGL(k_root_classify, gc, b, 0, st, pd, tg, owner, ro, root, nearf, qlist,
                      counters);
@@ -494,16 +506,13 @@ hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* o
 // ---------------------------------------------------------------------------------------
 // LDS layout of one tile (doubles, then ints)
 // ---------------------------------------------------------------------------------------
-// One wave: local coordinates xl and normal nl of a target in the frame fr of a patch whose
-// nodes start at n0, and the vector u of the solid-angle integrand: the target normal for a
-// self target, else the normal of the nearest node (lowest index on ties, wave argmin)
-// oriented toward the target.  Every lane returns the same values.
-template <int Q>
-__device__ __forceinline__ void wave_target_local(const PlanDev& pd, const double* fr, int64_t n0,
-                                                  int self, const double* xg, const double* nv,
-                                                  double* xl, double* nl, double* u) {
-  constexpr int Q2 = Q * Q;
-  const int lane = threadIdx.x & 63;
+// Local coordinates xl and normal nl of a target in the frame fr of a patch (q2 nodes from
+// n0), and the vector u of the solid-angle integrand: the target normal for a self target,
+// else the normal of the nearest node (lowest index on ties; a scan in index order keeps the
+// first of equal distances) oriented toward the target.
+__device__ __forceinline__ void pair_local(const PlanDev& pd, const double* fr, int64_t n0,
+                                           int q2, int self, const double* xg, const double* nv,
+                                           double* xl, double* nl, double* u) {
   frame_point(fr, xg, xl);
   for (int a = 0; a < 3; ++a) {
     const double* ax = fr + 3 + 3 * a;
@@ -516,19 +525,13 @@ __device__ __forceinline__ void wave_target_local(const PlanDev& pd, const doubl
   // bi starts at a valid node, so that non-finite distances still select a node
   double bd = 1e300;
   int bi = 0;
-  for (int i = lane; i < Q2; i += 64) {
+  for (int i = 0; i < q2; ++i) {
     double d2 = 0;
     for (int c = 0; c < 3; ++c) {
       const double dd = xl[c] - pd.node_loc[c * pd.N + n0 + i];
       d2 += dd * dd;
     }
     if (d2 < bd) { bd = d2; bi = i; }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ob = __shfl_xor(bd, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ob < bd || (ob == bd && oi < bi)) { bd = ob; bi = oi; }
   }
   double dd = 0, nn[3];
   for (int c = 0; c < 3; ++c) {
@@ -537,6 +540,46 @@ __device__ __forceinline__ void wave_target_local(const PlanDev& pd, const doubl
   }
   const double sg = dd >= 0.0 ? 1.0 : -1.0;
   for (int c = 0; c < 3; ++c) u[c] = sg * nn[c];
+}
+
+// Per-pair pre-pass: pair_local of every (target, patch) pair into plocal[9 k ..].
+__global__ __launch_bounds__(256) void k_pair_local(PlanDev pd, TargetsDev tg,
+                                                    const int64_t* owner, const int64_t* sorted,
+                                                    double* plocal) {
+  if (input_bad(tg)) return;
+  // pairs in patch order (the binning's permutation), so that the lanes of a wavefront
+  // mostly scan the nodes of one patch
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tg.nnz;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = sorted[i];
+    const int P = tg.near_patch[k];
+    const int64_t g = owner[k];
+    const double* fr = pd.frame + (int64_t)P * kFrame;
+    const int64_t n0 = pd.node_off[P];
+    const int q2 = pd.order[P] * pd.order[P];
+    const int self = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
+    double xg[3], nv[3], xl[3], nl[3], u[3];
+    for (int c = 0; c < 3; ++c) {
+      xg[c] = tg.xyz[c * tg.T + g];
+      nv[c] = tg.nrm[c * tg.T + g];
+    }
+    pair_local(pd, fr, n0, q2, self, xg, nv, xl, nl, u);
+    double* o = plocal + 9 * k;
+    for (int c = 0; c < 3; ++c) {
+      o[c] = xl[c];
+      o[3 + c] = nl[c];
+      o[6 + c] = u[c];
+    }
+  }
+}
+
+hipError_t launch_pair_local(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
+                             const int64_t* sorted, double* plocal, hipStream_t st) {
+  int64_t g = (tg.nnz + 255) / 256;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_pair_local, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, st, pd,
+                     tg, owner, sorted, plocal);
+  return hipGetLastError();
 }
 
 // Step 5 on a near edge (the singularity-swap class): the Lagrange-basis moments of the two
@@ -550,13 +593,12 @@ constexpr int kLamWaves = 4;
 template <int Q>
 __global__ __launch_bounds__(64 * kLamWaves) __attribute__((amdgpu_waves_per_eu(3)))
 void k_lambda(PlanDev pd, OrderDev od, TargetsDev tg, const int64_t* owner, const double2* root,
-              const int64_t* nlist, unsigned long long* counters, uint32_t* pflags,
-              double* lamg, int lam_stride, double rho_far) {
+              const int64_t* nlist, const double* plocal, unsigned long long* counters,
+              uint32_t* pflags, double* lamg, int lam_stride, double rho_far) {
   constexpr int PT = 2 * Q;
   constexpr int NB8 = (PT + 7) / 8;
   constexpr int NPAN = wave_panel_cap(Q);
   __shared__ double cgl_t[PT], cgl_w[PT], cbary[PT];
-  __shared__ double sfr[kLamWaves][kFrame];
   __shared__ double scoef[kLamWaves][PT * 3];
   __shared__ double span[kLamWaves][NPAN * 2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -569,7 +611,6 @@ void k_lambda(PlanDev pd, OrderDev od, TargetsDev tg, const int64_t* owner, cons
   if (input_bad(tg)) return;
   const int64_t nitems = (int64_t)counters[kCNearList];
   unsigned long long c_over = 0;
-  double* fr = sfr[wv];
   double* ecoef = scoef[wv];
   double* wpan = span[wv];
   for (int64_t it = (int64_t)blockIdx.x * kLamWaves + wv; it < nitems;
@@ -579,21 +620,16 @@ void k_lambda(PlanDev pd, OrderDev od, TargetsDev tg, const int64_t* owner, cons
     const int e = (int)(slot & 3);
     const int P = tg.near_patch[k];
     if (pd.order[P] != Q) continue;
-    const int64_t g = owner[k];
-    const int64_t n0 = pd.node_off[P];
     const int64_t e0 = pd.edge_off[P] + (int64_t)e * PT;
-    if (lane < kFrame) fr[lane] = pd.frame[(int64_t)P * kFrame + lane];
     for (int i = lane; i < PT * 3; i += 64)
       ecoef[i] = pd.edge_coef[(i % 3) * pd.E + e0 + i / 3];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int self = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
-    double xg[3], nv[3], xl[3], nl[3], u[3];
+    double xl[3], u[3];
     for (int c = 0; c < 3; ++c) {
-      xg[c] = tg.xyz[c * tg.T + g];
-      nv[c] = tg.nrm[c * tg.T + g];
+      xl[c] = plocal[9 * k + c];
+      u[c] = plocal[9 * k + 6 + c];
     }
-    wave_target_local<Q>(pd, fr, n0, self, xg, nv, xl, nl, u);
     const double2 r0 = root[slot];
     const double a = r0.x, b = r0.y;
     bool over;
@@ -674,12 +710,12 @@ void k_lambda(PlanDev pd, OrderDev od, TargetsDev tg, const int64_t* owner, cons
 
 hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
                          const int64_t* owner, const double2* root, const int64_t* nlist,
-                         unsigned long long* counters, uint32_t* pflags, double* lamg,
-                         int lam_stride, double rho_far, hipStream_t st) {
+                         const double* plocal, unsigned long long* counters, uint32_t* pflags,
+                         double* lamg, int lam_stride, double rho_far, hipStream_t st) {
   if (tg.nnz <= 0) return hipSuccess;
   const int grid = 2048;
   switch (q) {
-#define X(Q) case Q: hipLaunchKernelGGL(k_lambda<Q>, dim3(grid), dim3(64 * kLamWaves), 0, st, pd, od, tg, owner, root, nlist, counters, pflags, lamg, lam_stride, rho_far); break;
+#define X(Q) case Q: hipLaunchKernelGGL(k_lambda<Q>, dim3(grid), dim3(64 * kLamWaves), 0, st, pd, od, tg, owner, root, nlist, plocal, counters, pflags, lamg, lam_stride, rho_far); break;
     X(4) X(5) X(6) X(8) X(10)
 #undef X
     default: return hipErrorInvalidValue;
@@ -837,36 +873,27 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       const int nt = min(T, tile.z - sub);
       __syncthreads();
       RRQ_PHASE(5)
-      // ---- patch data
+      // ---- patch frame, and the targets' data (32 threads per target, one value each): local
+      // point, normal and u from the per-pair pre-pass; global point and normal; ids
       if (tid < kFrame) fr[tid] = pd.frame[(int64_t)P * kFrame + tid];
-      __syncthreads();
-      // ---- targets (one wave each): local coordinates; u from the nearest node, lowest
-      // index on ties (wave argmin)
-      for (int t = wv; t < nt; t += BNT / 64) {
+      for (int it = tid; it < nt * 32; it += BNT) {
+        const int t = it >> 5, f = it & 31;
+        if (f >= 19) continue;
         const int64_t k = sorted[tile.y + sub + t];
+        if (f < 9) {
+          const double v = out.plocal[9 * k + f];
+          if (f < 3) sx[t * 3 + f] = v;
+          else if (f < 6) snu[t * 3 + f - 3] = v;
+          else su[t * 3 + f - 6] = v;
+          continue;
+        }
         const int64_t g = out.owner[k];
-        const int self = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
-        double xg[3], nv[3], xl[3], nl[3], u[3];
-        for (int c = 0; c < 3; ++c) {
-          xg[c] = tg.xyz[c * tg.T + g];
-          nv[c] = tg.nrm[c * tg.T + g];
-        }
-        wave_target_local<Q>(pd, fr, fresh(n0), self, xg, nv, xl, nl, u);
-        if (lane == 0) {
-          sself[t] = self;
-          sids[t * 3] = k;
-          sids[t * 3 + 1] = g;
-          sids[t * 3 + 2] = POT ? 0 : out.pair_off[k];
-          for (int c = 0; c < 3; ++c) {
-            sxg[t * 6 + c] = xg[c];
-            sxg[t * 6 + 3 + c] = nv[c];
-          }
-          for (int a = 0; a < 3; ++a) {
-            sx[t * 3 + a] = xl[a];
-            snu[t * 3 + a] = nl[a];
-            su[t * 3 + a] = u[a];
-          }
-        }
+        if (f < 12) sxg[t * 6 + f - 9] = tg.xyz[(f - 9) * tg.T + g];
+        else if (f < 15) sxg[t * 6 + f - 9] = tg.nrm[(f - 12) * tg.T + g];
+        else if (f == 15) sself[t] = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
+        else if (f == 16) sids[t * 3] = k;
+        else if (f == 17) sids[t * 3 + 1] = g;
+        else sids[t * 3 + 2] = POT ? 0 : out.pair_off[k];
       }
       __syncthreads();
       RRQ_PHASE(0)

@@ -131,6 +131,17 @@ __global__ __launch_bounds__(NT) void k_geometry(PlanDev pd, rrq_surface s, Orde
       sm_coef[(e * PT + k) * 3 + c] = acc;
     }
     __syncthreads();
+    // chord of each edge (the start of the singularity-swap root search), by the same
+    // arithmetic as from the global coefficients
+    if (tid < 4) {
+      double m[3], d[3];
+      edge_chord(sm_coef + tid * PT * 3, PT, m, d, 3, 1);
+      double* o = pd.edge_chord + ((int64_t)P * 4 + tid) * 6;
+      for (int c = 0; c < 3; ++c) {
+        o[c] = m[c];
+        o[3 + c] = d[c];
+      }
+    }
     // tangent r'(t_i) = sum_k c_k P_k'(t_i)
     for (int idx = tid; idx < 4 * PT * 3; idx += NT) {
       const int c = idx % 3, i = (idx / 3) % PT, e = idx / (3 * PT);

@@ -52,7 +52,8 @@ struct PlanDev {
   double* node_loc;         // [6][N] local coordinates and normals
   double* edge_loc;         // [3][E]
   double* edge_tan;         // [3][E]
-  double* edge_coef;        // [3][E] monomial coefficients per edge
+  double* edge_coef;        // [3][E] Legendre coefficients per edge
+  double* edge_chord;       // [P][4][6]: chord midpoint m and half-vector d of each edge
   double* maps;             // per patch: M_D [4np][q^2], M_Sp [4np][q^2], M_S [5np][q^2]
   const int64_t* map_off;
   double* tabs;             // per patch: [4 pt][6][njk] (re, im): c (3 cplx), h (3 cplx)
@@ -117,6 +118,7 @@ struct AssembleOut {
   const uint8_t* nearf;     // [4 nnz] 1: singularity-swap class, 0: plain rule
   const double* lamg;       // [4 nnz][lam_stride] near-edge moments (near slots only)
   int lam_stride;
+  const double* plocal;     // [nnz][9] per pair: target and its normal in the patch frame, u
   // potentials mode
   const double* dens;       // [N] nodal density
   const double* pcoef;      // [P][kCoefStride] c_D, c_S', c_S of every patch
@@ -202,8 +204,13 @@ hipError_t launch_root(const PlanDev& pd, const TargetsDev& tg, const int64_t* o
 // of them), for the patches of order q
 hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const TargetsDev& tg,
                          const int64_t* owner, const double2* root, const int64_t* nlist,
-                         unsigned long long* counters, uint32_t* pflags, double* lamg,
-                         int lam_stride, double rho_far, hipStream_t st);
+                         const double* plocal, unsigned long long* counters, uint32_t* pflags,
+                         double* lamg, int lam_stride, double rho_far, hipStream_t st);
+// per pair k: plocal[9k ..] = target in the patch frame (3), its normal there (3), and u of
+// the solid-angle integrand (3): the target normal for a self target, else the normal of the
+// patch node nearest to the target (lowest index on ties) oriented toward it
+hipError_t launch_pair_local(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
+                             const int64_t* sorted, double* plocal, hipStream_t st);
 
 // learned initial guess: sample collection and training
 struct CollectOpts {
