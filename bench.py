@@ -96,7 +96,7 @@ def _newton_summary(st, ms, nweights):
             "learned_accept": st["learned_accept"], "newton_fail": st["newton_fail"]}
 
 
-def learned_form(rrq, reps=3, train_per_patch=110):
+def learned_form(rrq, reps=8, train_per_patch=110):
     """The learned Newton start on the star surface plus the 2048-patch torus: trained on
     about 2M samples the method produces on its own seeded training geometry (a deformed
     sphere and a torus with off-surface targets, kept apart from the evaluation surfaces),
@@ -125,12 +125,23 @@ def learned_form(rrq, reps=3, train_per_patch=110):
     out["train_loss_first_last"] = [float(c[:10].mean()), float(c[-100:].mean())]
     sp = asm.assemble(flags=flags, stats=True)
     w_plain = {k: asm.out[k].clone() for k in rrq.KERNELS}
-    plain_ms = assemble_ms(asm, flags, reps)
     plan.set_mlp(params)
     sl = asm.assemble(flags=flags | rrq.RRQ_F_LEARNED, stats=True)
-    learned_ms = assemble_ms(asm, flags | rrq.RRQ_F_LEARNED, reps)
-    out["plain"] = _newton_summary(sp, plain_ms, asm.nweights)
-    out["learned"] = _newton_summary(sl, learned_ms, asm.nweights)
+    # the two forms alternate, so that slow drifts of the clock affect both alike; the tile
+    # kernels are the same work in both, the forms differ in the root passes before them
+    t = {"plain": [], "learned": []}
+    pre = {"plain": [], "learned": []}
+    for _ in range(reps):
+        for name, fl in (("plain", flags), ("learned", flags | rrq.RRQ_F_LEARNED)):
+            ms = assemble_ms(asm, fl, 1)
+            st = asm.assemble(flags=fl, stats=True)
+            t[name].append(ms)
+            pre[name].append(ms - st["kernel_ms"])
+    out["plain"] = _newton_summary(sp, float(np.mean(t["plain"])), asm.nweights)
+    out["learned"] = _newton_summary(sl, float(np.mean(t["learned"])), asm.nweights)
+    for name in ("plain", "learned"):
+        out[name]["assemble_ms_runs"] = [round(v, 3) for v in t[name]]
+        out[name]["outside_tile_kernel_ms"] = float(np.mean(pre[name]))
     out["max_rel_weight_dev_learned_vs_plain"] = max(
         ((asm.out[k] - w_plain[k]).abs().max() / w_plain[k].abs().max()).item()
         for k in rrq.KERNELS)

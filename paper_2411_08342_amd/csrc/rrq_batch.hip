@@ -389,6 +389,14 @@ __global__ __launch_bounds__(256) void k_root_classify(PlanDev pd, TargetsDev tg
 // MODE 0: plain Newton from the chord start over the Newton list; 1: Newton from the learned
 // start over the Newton list, rejected slots to the retry list; 2: plain Newton over the retry
 // list, with the learned iterations added to the slot's count.
+// tanh for the learned start only: 1 - 2 / (1 + e^{2x}) with the hardware base-2 exponential
+// and reciprocal (absolute error about 1e-7; the network's output only seeds Newton, whose
+// converged root does not depend on it).  Saturates to +-1 for large |x|.
+__device__ __forceinline__ float guess_tanh(float x) {
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);   // e^{2x} = 2^{2x log2 e}
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_root_newton(PlanDev pd, TargetsDev tg,
                                                      const int64_t* owner, RootOpts ro,
@@ -426,7 +434,7 @@ __global__ __launch_bounds__(256) void k_root_newton(PlanDev pd, TargetsDev tg,
           float a = mw[kMlpB1 + u];
 #pragma unroll
           for (int cc = 0; cc < kMlpIn; ++cc) a += mw[kMlpW1 + u * kMlpIn + cc] * x[cc];
-          h1[u] = tanhf(a);
+          h1[u] = guess_tanh(a);
           __builtin_amdgcn_sched_barrier(0);
         }
         float y0 = mw[kMlpB3], y1 = mw[kMlpB3 + 1];
@@ -435,7 +443,7 @@ __global__ __launch_bounds__(256) void k_root_newton(PlanDev pd, TargetsDev tg,
           float a = mw[kMlpB2 + u];
 #pragma unroll
           for (int kk = 0; kk < kMlpH; ++kk) a += mw[kMlpW2 + u * kMlpH + kk] * h1[kk];
-          const float h2 = tanhf(a);
+          const float h2 = guess_tanh(a);
           y0 += mw[kMlpW3 + u] * h2;
           y1 += mw[kMlpW3 + kMlpH + u] * h2;
         }

@@ -720,13 +720,12 @@ __device__ __forceinline__ quat reflect_coef(const double* v, int ldv, const dou
 template <int Q>
 struct FitQ {
   static constexpr int NP = np_of(Q), Q2 = Q * Q;
-  static constexpr int RB = Q2 < 32 ? Q2 : 32;          // right-hand sides per batch
   // row strides (doubles) of the quaternion arrays: 16 bytes beyond whole quaternions, so
   // that the 16-byte reads of eight consecutive lanes (rows) of one column cover all 32 banks
-  static constexpr int FS = 4 * NP + 2, YS = 4 * RB + 2;
+  static constexpr int FS = 4 * NP + 2;
   static constexpr int o_F = 0;                          // [Q2][FS]: row i, column k at 4k
-  static constexpr int o_Y = o_F + Q2 * FS;              // [Q2][YS]
-  static constexpr int o_al = o_Y + Q2 * YS;             // [NP] quat: R_kk
+  static constexpr int o_Z = o_F + Q2 * FS;              // [Q2][FS]: Q_1, then the maps
+  static constexpr int o_al = o_Z + Q2 * FS;             // [NP] quat: R_kk
   static constexpr int o_be = o_al + 4 * NP;             // [NP]
   static constexpr int n_quat = o_be + NP;
   // the SLP fit afterwards reuses the same LDS: panels, back-substitution right-hand
@@ -747,12 +746,12 @@ __global__ __launch_bounds__(NT) void k_fit_quat(PlanDev pd, OrderDev od,
                                                  const int32_t* patches, int count, double* ws,
                                                  int64_t ws_per_block) {
   using L = FitQ<Q>;
-  constexpr int NP = L::NP, Q2 = L::Q2, RB = L::RB;
+  constexpr int NP = L::NP, Q2 = L::Q2;
   constexpr int LDB = NP + Q2;
   extern __shared__ double lds[];
-  constexpr int FS = L::FS, YS = L::YS;
+  constexpr int FS = L::FS;
   auto Fq = [&](int i, int k) -> quat& { return *(quat*)(lds + L::o_F + i * FS + 4 * k); };
-  auto Yq = [&](int i, int c) -> quat& { return *(quat*)(lds + L::o_Y + i * YS + 4 * c); };
+  auto Zq = [&](int i, int c) -> quat& { return *(quat*)(lds + L::o_Z + i * FS + 4 * c); };
   quat* al = (quat*)(lds + L::o_al);
   double* be = lds + L::o_be;
   // global workspace: the SLP system B [Q2][LDB] and Hmat [Q2][NP]
@@ -834,64 +833,70 @@ __global__ __launch_bounds__(NT) void k_fit_quat(PlanDev pd, OrderDev od,
     double* maps = pd.maps + pd.map_off[P];
     double* MD = maps;
     double* MSp = maps + 4 * NP * Q2;
-    // right-hand sides w_j e_j in batches of RB: reflectors, then back substitution with R
-    for (int j0 = 0; j0 < Q2; j0 += RB) {
-      for (int idx = tid; idx < Q2 * RB; idx += NT) {
-        const int i = idx / RB, c = idx % RB;
-        Yq(i, c) = {i == j0 + c ? sqrt(od.glq_w[i / Q] * od.glq_w[i % Q]) : 0.0, 0.0, 0.0, 0.0};
-      }
-      __syncthreads();
-      for (int k = 0; k < NP; ++k) {
-        const double bk = be[k];
-        for (int c = tid >> 3; c < RB; c += NT / 8) {
-          const quat sv = reflect_coef(lds + L::o_F + 4 * k, FS, lds + L::o_Y + 4 * c, YS, k,
-                                       Q2, bk);
-          for (int i = k + (tid & 7); i < Q2; i += 8) {
-            const quat t = qmul(Fq(i, k), sv);
-            quat& yv = Yq(i, c);
-            yv.w -= t.w; yv.x -= t.x; yv.y -= t.y; yv.z -= t.z;
-          }
+    // F^+ = R^{-1} Q_1^H with Q_1 the first NP columns of Q = H_0 ... H_{NP-1}: Q_1 is
+    // accumulated backwards (H_{NP-1} first) from [I; 0]; at step k the columns j < k are
+    // still unit vectors with zeros in rows >= k, so only the columns j >= k change
+    for (int idx = tid; idx < Q2 * NP; idx += NT) {
+      const int i = idx / NP, j = idx % NP;
+      Zq(i, j) = {i == j ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+    }
+    __syncthreads();
+    for (int k = NP - 1; k >= 0; --k) {
+      const double bk = be[k];
+      for (int j = k + (tid >> 3); j < NP; j += NT / 8) {
+        const quat sv = reflect_coef(lds + L::o_F + 4 * k, FS, lds + L::o_Z + 4 * j, FS, k, Q2,
+                                     bk);
+        for (int i = k + (tid & 7); i < Q2; i += 8) {
+          const quat t = qmul(Fq(i, k), sv);
+          quat& z = Zq(i, j);
+          z.w -= t.w; z.x -= t.x; z.y -= t.y; z.z -= t.z;
         }
-        __syncthreads();
-      }
-      // R c = y (rows 0..NP-1): c_k = R_kk^{-1} y_k, then y_i -= R_ik c_k for i < k
-      for (int k = NP - 1; k >= 0; --k) {
-        if (tid < RB) {
-          const quat a = al[k];
-          const double inv = 1.0 / qnorm2(a);
-          const quat ai = {a.w * inv, -a.x * inv, -a.y * inv, -a.z * inv};
-          Yq(k, tid) = qmul(ai, Yq(k, tid));
-        }
-        __syncthreads();
-        for (int idx = tid; idx < k * RB; idx += NT) {
-          const int i = idx / RB, c = idx % RB;
-          const quat t = qmul(Fq(i, k), Yq(k, c));
-          quat& yv = Yq(i, c);
-          yv.w -= t.w; yv.x -= t.x; yv.y -= t.y; yv.z -= t.z;
-        }
-        __syncthreads();
-      }
-      // M_D columns (component-major rows b NP + lm) and M_Sp columns: c (0, nu_j); the
-      // last batch may reach past column Q2 - 1 (its extra columns are zero and not stored)
-      for (int idx = tid; idx < NP * RB; idx += NT) {
-        const int lm = idx / RB, c = idx % RB, j = j0 + c;
-        if (j >= Q2) continue;
-        const quat v = Yq(lm, c);
-        nFp += qnorm2(v) / (od.glq_w[j / Q] * od.glq_w[j % Q]);
-        MD[(0 * NP + lm) * Q2 + j] = v.w;
-        MD[(1 * NP + lm) * Q2 + j] = v.x;
-        MD[(2 * NP + lm) * Q2 + j] = v.y;
-        MD[(3 * NP + lm) * Q2 + j] = v.z;
-        const double v1 = pd.node_loc[3 * pd.N + n0 + j];
-        const double v2 = pd.node_loc[4 * pd.N + n0 + j];
-        const double v3 = pd.node_loc[5 * pd.N + n0 + j];
-        MSp[(0 * NP + lm) * Q2 + j] = -(v.x * v1 + v.y * v2 + v.z * v3);
-        MSp[(1 * NP + lm) * Q2 + j] = v.w * v1 + (v.y * v3 - v.z * v2);
-        MSp[(2 * NP + lm) * Q2 + j] = v.w * v2 + (v.z * v1 - v.x * v3);
-        MSp[(3 * NP + lm) * Q2 + j] = v.w * v3 + (v.x * v2 - v.y * v1);
       }
       __syncthreads();
     }
+    // maps: column j of M_D is c = R^{-1} conj(Q_1[j, :])^T w_j, solved in place in row j of
+    // Z for all j at once: c_k = R_kk^{-1} y_k, then y_l -= R_lk c_k for l < k
+    for (int idx = tid; idx < Q2 * NP; idx += NT) {
+      const int i = idx / NP, j = idx % NP;
+      const double w = sqrt(od.glq_w[i / Q] * od.glq_w[i % Q]);
+      quat& z = Zq(i, j);
+      z = {w * z.w, -w * z.x, -w * z.y, -w * z.z};
+    }
+    __syncthreads();
+    for (int k = NP - 1; k >= 0; --k) {
+      if (tid < Q2) {
+        const quat a = al[k];
+        const double inv = 1.0 / qnorm2(a);
+        const quat ai = {a.w * inv, -a.x * inv, -a.y * inv, -a.z * inv};
+        Zq(tid, k) = qmul(ai, Zq(tid, k));
+      }
+      __syncthreads();
+      for (int idx = tid; idx < k * Q2; idx += NT) {
+        const int l = idx / Q2, j = idx % Q2;
+        const quat t = qmul(Fq(l, k), Zq(j, k));
+        quat& z = Zq(j, l);
+        z.w -= t.w; z.x -= t.x; z.y -= t.y; z.z -= t.z;
+      }
+      __syncthreads();
+    }
+    // M_D columns (component-major rows b NP + lm) and M_Sp columns: c (0, nu_j)
+    for (int idx = tid; idx < NP * Q2; idx += NT) {
+      const int lm = idx / Q2, j = idx % Q2;
+      const quat v = Zq(j, lm);
+      nFp += qnorm2(v) / (od.glq_w[j / Q] * od.glq_w[j % Q]);
+      MD[(0 * NP + lm) * Q2 + j] = v.w;
+      MD[(1 * NP + lm) * Q2 + j] = v.x;
+      MD[(2 * NP + lm) * Q2 + j] = v.y;
+      MD[(3 * NP + lm) * Q2 + j] = v.z;
+      const double v1 = pd.node_loc[3 * pd.N + n0 + j];
+      const double v2 = pd.node_loc[4 * pd.N + n0 + j];
+      const double v3 = pd.node_loc[5 * pd.N + n0 + j];
+      MSp[(0 * NP + lm) * Q2 + j] = -(v.x * v1 + v.y * v2 + v.z * v3);
+      MSp[(1 * NP + lm) * Q2 + j] = v.w * v1 + (v.y * v3 - v.z * v2);
+      MSp[(2 * NP + lm) * Q2 + j] = v.w * v2 + (v.z * v1 - v.x * v3);
+      MSp[(3 * NP + lm) * Q2 + j] = v.w * v3 + (v.x * v2 - v.y * v1);
+    }
+    __syncthreads();
     // SLP fit (real, Q2 x NP): blocked Householder in the same LDS
     hh_lsq(B, Q2, NP, LDB, LDB, lds + L::o_sV, lds + L::o_sV + Q2 * HNB, lds + L::o_sT,
            lds + L::o_sG, lds + L::o_sb, lds + L::o_sa, lds + L::o_sX, lds + L::o_sR, NP);
