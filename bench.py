@@ -23,8 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": "8f8d22ce8d25613e2c644f860e889d97d3a18b2611ea5fd8a5808eca016e09d0",
-           "fetch_bytes": 1785462638, "write_bytes": 3601301248}
+TRAFFIC = {"src_sha256": "4492dce489cbc5d67b864c353f93927137365ad072db1bfda7e915d15caf0143",
+           "fetch_bytes": 2174463072, "write_bytes": 3605689576}
 
 
 def flops_per_pair(q):
