@@ -36,15 +36,18 @@ __global__ void k_bin_count(TargetsDev tg, int32_t* cnt) {
 
 // exclusive scans of cnt and of ceil(cnt / tile) over patches taken in the order perm
 // (patches grouped by order; tile = the targets per tile of the patch's order), one workgroup
-__global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, const int32_t* perm,
-                                                   BinOrders bo, int P,
-                                                   int64_t* start, int64_t* tstart,
-                                                   int64_t* ntiles, int64_t* qtile) {
-  __shared__ int64_t s1[1024], s2[1024];
+// of kBS threads with 4 KB of LDS, so that it fits on a compute unit beside a fit workgroup
+// of the captured step's other branch (a 1024-thread, 16 KB version waited for one to end)
+constexpr int kBS = 256;
+__global__ __launch_bounds__(kBS) void k_bin_scan(const int32_t* cnt, const int32_t* perm,
+                                                  BinOrders bo, int P,
+                                                  int64_t* start, int64_t* tstart,
+                                                  int64_t* ntiles, int64_t* qtile) {
+  __shared__ int64_t s1[kBS], s2[kBS];
   __shared__ int64_t c1, c2;
   if (threadIdx.x == 0) { c1 = 0; c2 = 0; }
   __syncthreads();
-  for (int base = 0; base < P; base += 1024) {
+  for (int base = 0; base < P; base += kBS) {
     const int i = base + threadIdx.x;
     const int pp = i < P ? perm[i] : 0;
     int tile = 1;
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, const int
     s1[threadIdx.x] = a;
     s2[threadIdx.x] = b;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
+    for (int o = 1; o < kBS; o <<= 1) {
       const int64_t x = threadIdx.x >= o ? s1[threadIdx.x - o] : 0;
       const int64_t y = threadIdx.x >= o ? s2[threadIdx.x - o] : 0;
       __syncthreads();
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* cnt, const int
         if (bo.off[qi] == i) qtile[qi] = c2 + s2[threadIdx.x] - b;
     }
     __syncthreads();
-    if (threadIdx.x == 1023) { c1 += s1[1023]; c2 += s2[1023]; }
+    if (threadIdx.x == kBS - 1) { c1 += s1[kBS - 1]; c2 += s2[kBS - 1]; }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -118,7 +121,7 @@ hipError_t launch_binning(const TargetsDev& tg, int P, const int32_t* order,
   const unsigned gkk = (unsigned)(gk < 65535 ? gk : 65535);
   hipLaunchKernelGGL(k_bin_clear, dim3(gp), dim3(256), 0, st, cnt, fill, P, qctr);
   hipLaunchKernelGGL(k_bin_count, dim3(gkk), dim3(256), 0, st, tg, cnt);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, cnt, perm, bo, P, start, tstart,
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBS), 0, st, cnt, perm, bo, P, start, tstart,
                      ntiles, qtile);
   hipLaunchKernelGGL(k_bin_scatter, dim3(gkk), dim3(256), 0, st, tg, start, fill, sorted);
   hipLaunchKernelGGL(k_bin_tiles, dim3(gp), dim3(256), 0, st, cnt, P, order, bo, start, tstart,
@@ -356,7 +359,7 @@ __global__ __launch_bounds__(256) void k_root_classify(PlanDev pd, TargetsDev tg
   // chunks of kC slots per workgroup: the chunk's Newton slots are gathered in LDS and the
   // list is reserved once per chunk (one counter atomic per kC slots, not per wavefront)
   constexpr int kC = 1024;
-  __shared__ int64_t qs[kC];
+  __shared__ int16_t qs[kC];   // offsets in the chunk (2 KB: shares a CU with a fit workgroup)
   __shared__ int qn;
   __shared__ long long qbase;
   if (input_bad(tg)) return;
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(256) void k_root_classify(PlanDev pd, TargetsDev tg
       const RootSlot r = root_slot(pd, tg, owner, slot);
       const cplx ts = chord_root(r.chord, r.chord + 3, r.xl);
       if (bernstein_rho(ts) <= ro.rho_far[r.q]) {
-        qs[atomicAdd(&qn, 1)] = slot;
+        qs[atomicAdd(&qn, 1)] = (int16_t)i;
       } else {
         root[slot] = make_double2(ts.re, ts.im);
         nearf[slot] = 0;
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(256) void k_root_classify(PlanDev pd, TargetsDev tg
     if (tid == 0)
       qbase = qn > 0 ? (long long)atomicAdd(&counters[kCQueueList], (unsigned long long)qn) : 0;
     __syncthreads();
-    for (int i = tid; i < qn; i += blockDim.x) qlist[qbase + i] = qs[i];
+    for (int i = tid; i < qn; i += blockDim.x) qlist[qbase + i] = base + qs[i];
   }
 }
 

@@ -995,6 +995,15 @@ static hipError_t launch_fit_quat(const PlanDev& pd, const OrderDev& od, const i
   hipError_t e = hipFuncSetAttribute((const void*)k_fit_quat<Q>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  // at most one workgroup per compute unit: with more, the extra ones start only when a first
+  // one has worked through all its patches, and the launch takes more rounds of patches
+  if (lds > 80 * 1024) {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu > 0 && grid > ncu)
+      grid = ncu;
+  }
   hipLaunchKernelGGL(k_fit_quat<Q>, dim3(grid), dim3(NT), lds, st, pd, od, patches, count, ws,
                      ws_per_block);
   return hipGetLastError();
