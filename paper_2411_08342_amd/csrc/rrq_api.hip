@@ -595,6 +595,8 @@ struct OrderBranches {
   hipStream_t stream[kNumOrders];
   hipEvent_t fork;
   hipEvent_t join[kNumOrders];
+  // the root passes on stream[0] beside the binning and the per-pair target data
+  hipEvent_t root_fork, root_join;
 };
 
 // Timing events around each order's tile kernel (autotuner and statistics).
@@ -699,13 +701,13 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
     int4* tiles = (int4*)(wb + wl.tiles);
     int64_t* qtile = (int64_t*)(wb + wl.queue);
     unsigned long long* qctr = (unsigned long long*)(wb + wl.queue + 8 * (kNumOrders + 1));
-    if (launch_binning(td, p->P, p->order_d, p->perm_d, bo, cnt, fill, start, tstart, ntiles,
-                       sorted, tiles, qtile, qctr, st) != hipSuccess)
+    // captured step: the root passes (which need only the owner map) run on a branch of their
+    // own beside the binning and the per-pair target data; the near-edge moments need both
+    const bool fork_roots = branches != nullptr && branches->root_fork && branches->root_join;
+    hipStream_t rs = fork_roots ? branches->stream[0] : st;
+    if (fork_roots && (hipEventRecord(branches->root_fork, st) != hipSuccess ||
+                       hipStreamWaitEvent(rs, branches->root_fork, 0) != hipSuccess))
       return RRQ_ERR_DEVICE;
-    double* plocal = (double*)(wb + wl.plocal);
-    if (launch_pair_local(pd, td, owner, sorted, plocal, st) != hipSuccess)
-      return RRQ_ERR_DEVICE;
-    ao.plocal = plocal;
     {
       RootOpts ro;
       for (int q = 0; q <= kMaxQ; ++q) ro.rho_far[q] = p->rho_far[q];
@@ -721,7 +723,18 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
       int64_t* qlist = (int64_t*)(wb + wl.lamg);
       int64_t* rlist = qlist + 4 * (tg->nnz > 0 ? tg->nnz : 1);
       if (launch_root(pd, td, owner, ro, (flags & RRQ_F_LEARNED) != 0, root, nearf, qlist,
-                      rlist, nlist, counters, pflags, st) != hipSuccess)
+                      rlist, nlist, counters, pflags, rs) != hipSuccess)
+        return RRQ_ERR_DEVICE;
+      if (fork_roots && hipEventRecord(branches->root_join, rs) != hipSuccess)
+        return RRQ_ERR_DEVICE;
+      if (launch_binning(td, p->P, p->order_d, p->perm_d, bo, cnt, fill, start, tstart, ntiles,
+                         sorted, tiles, qtile, qctr, st) != hipSuccess)
+        return RRQ_ERR_DEVICE;
+      double* plocal = (double*)(wb + wl.plocal);
+      if (launch_pair_local(pd, td, owner, sorted, plocal, st) != hipSuccess)
+        return RRQ_ERR_DEVICE;
+      ao.plocal = plocal;
+      if (fork_roots && hipStreamWaitEvent(st, branches->root_join, 0) != hipSuccess)
         return RRQ_ERR_DEVICE;
       for (int qi = 0; qi < kNumOrders; ++qi) {
         const int q = kOrders[qi];
@@ -1268,7 +1281,9 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   for (int qi = 0; ok && qi < kNumOrders; ++qi)
     ok = hipStreamCreateWithFlags(&br.stream[qi], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&br.join[qi], hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&br.fork, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&br.fork, hipEventDisableTiming) == hipSuccess &&
+       hipEventCreateWithFlags(&br.root_fork, hipEventDisableTiming) == hipSuccess &&
+       hipEventCreateWithFlags(&br.root_join, hipEventDisableTiming) == hipSuccess;
   r = ok ? run_geometry(p, s, cs) : RRQ_ERR_DEVICE;
   if (r == RRQ_OK && (hipEventRecord(fork, cs) != hipSuccess ||
                       hipStreamWaitEvent(ms, fork, 0) != hipSuccess))
@@ -1289,6 +1304,8 @@ extern "C" rrq_status rrq_graph_create(rrq_plan* p, const rrq_surface* s, const 
   if (fork) (void)hipEventDestroy(fork);
   if (ms) (void)hipStreamDestroy(ms);
   if (br.fork) (void)hipEventDestroy(br.fork);
+  if (br.root_fork) (void)hipEventDestroy(br.root_fork);
+  if (br.root_join) (void)hipEventDestroy(br.root_join);
   for (int qi = 0; qi < kNumOrders; ++qi) {
     if (br.join[qi]) (void)hipEventDestroy(br.join[qi]);
     if (br.stream[qi]) (void)hipStreamDestroy(br.stream[qi]);
