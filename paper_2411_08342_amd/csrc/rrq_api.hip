@@ -159,7 +159,7 @@ static rrq_status upload_consts(rrq_plan* p, int q) {
   if (!up(T.tlen.data(), T.tlen.size() * 4, &b)) return RRQ_ERR_OOM;
   o.tlen = (const int32_t*)b;
   if (!up(T.tnr.data(), T.tnr.size() * 4, &b)) return RRQ_ERR_OOM;
-  o.tnr = (const int2*)b;
+  o.tnr = (const int4*)b;
   if (!up(T.tcf.data(), T.tcf.size() * 8, &b)) return RRQ_ERR_OOM;
   o.tcf = (const double4*)b;
   return RRQ_OK;

@@ -1088,12 +1088,11 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       __syncthreads();
       RRQ_PHASE(3)
       // ---- Steps 7-8: translation and rows, items (target, slot): a slot holds the term list
-      // of one (l, m) or half of a long one; the two halves of a list sit on adjacent lanes
-      // and are added with one lane exchange
+      // of one (l, m) or one of the 2 or 4 pieces of a long one, on adjacent lanes
       for (int idx = tid; idx < T * od.nslot; idx += BNT) {
         const int t = idx / od.nslot, slot = idx % od.nslot, code = od.tslot[slot];
-        const int lm = code & 0xff, kind = code >> 8;
-        const bool act = t < nt && kind != 3;
+        const int lm = code & 0xff, piece = (code >> 8) & 0xf, lg = code >> 12;
+        const bool act = t < nt && code != kPadSlot;
         int l = 1;
         while (np_of(l) <= lm) ++l;
         const int m = lm - np_of(l - 1) + 1;
@@ -1107,38 +1106,56 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
         // one pass over the (j, k) terms of this (l, m): single-layer sum (weights D_{j,l})
         // and double-layer sums (weights C_{j,l}, zero for j = 1); the signs of conjugation
         // (k < 0) and of S^{(a,b)} for b < 0 are folded into the weights
-        // (the slot's terms are read step-major: the lanes' entries of a step are adjacent)
-        const int len = act ? od.tlen[slot] : 0;
+        // (the slot's terms are read in chunks of 4 steps: one int4 of operand offsets per
+        // chunk, read one chunk ahead, and the chunk's coefficients, whose addresses do not
+        // depend on a load, so that a chunk waits on one memory latency)
+        const int nch = act ? (od.tlen[slot] + 3) >> 2 : 0;
+        const int ns = od.nslot;
+        int4 nr4 = od.tnr[slot];
 #pragma unroll 1
-        for (int it = 0; it < len; ++it) {
-          const int2 nr = od.tnr[it * od.nslot + slot];
-          const double4 cf = od.tcf[it * od.nslot + slot];
-          const cplx s_ = R[nr.y];
-          const cplx g_ = G[nr.y];
-          const double csi = cf.y * s_.im, csr = cf.x * s_.re;
-          const double cgi = cf.y * g_.im, cgr = cf.x * g_.re;
-          const double* q = VQ + nr.x;
-          sl = fma(cf.w * q[0], s_.im, fma(cf.z * q[1], s_.re, sl));
+        for (int ch = 0; ch < nch; ++ch) {
+          const int4 nr4n = od.tnr[(ch + 1) * ns + slot];
+          const double4* cfp = od.tcf + (4 * ch) * ns + slot;
+          double4 cf[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const double xr = q[2 + 2 * c], xi = q[3 + 2 * c];
-            const double dxr = q[10 + 2 * c], dxi = q[11 + 2 * c];
-            Ia[c] = fma(xr, csi, fma(xi, csr, Ia[c]));
-            dIa[c] = fma(dxr, csi, fma(dxi, csr, dIa[c]));
-            dIa[c] = fma(xr, cgi, fma(xi, cgr, dIa[c]));
+          for (int u = 0; u < 4; ++u) cf[u] = cfp[u * ns];
+          const int nrs[4] = {nr4.x, nr4.y, nr4.z, nr4.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ro = nrs[u] & 0xff;
+            const cplx s_ = R[ro];
+            const cplx g_ = G[ro];
+            const double* q = VQ + (nrs[u] >> 8);
+            const double csi = cf[u].y * s_.im, csr = cf[u].x * s_.re;
+            const double cgi = cf[u].y * g_.im, cgr = cf[u].x * g_.re;
+            sl = fma(cf[u].w * q[0], s_.im, fma(cf[u].z * q[1], s_.re, sl));
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const double xr = q[2 + 2 * c], xi = q[3 + 2 * c];
+              const double dxr = q[10 + 2 * c], dxi = q[11 + 2 * c];
+              Ia[c] = fma(xr, csi, fma(xi, csr, Ia[c]));
+              dIa[c] = fma(dxr, csi, fma(dxi, csr, dIa[c]));
+              dIa[c] = fma(xr, cgi, fma(xi, cgr, dIa[c]));
+            }
           }
+          nr4 = nr4n;
         }
-        // first half += second half (the partner lane is idx ^ 1)
+        // the 1 << lg pieces of a list sit on aligned adjacent lanes (the partner at distance d
+        // is idx ^ d): their partial sums are added with lg lane exchanges
         {
           double o;
-#define RRQ_ADD_HALF(v) o = __shfl_xor(v, 1, 64); if (kind == 1) v += o;
+#define RRQ_ADD_PIECES(v)                    \
+  o = __shfl_xor(v, 1, 64);                  \
+  if (lg == 1 || lg == 2) v += o;            \
+  o = __shfl_xor(v, 2, 64);                  \
+  if (lg == 2) v += o;
           for (int c = 0; c < 4; ++c) {
-            RRQ_ADD_HALF(Ia[c]) RRQ_ADD_HALF(dIa[c])
+            RRQ_ADD_PIECES(Ia[c]) RRQ_ADD_PIECES(dIa[c])
           }
-          RRQ_ADD_HALF(sl)
-#undef RRQ_ADD_HALF
+          RRQ_ADD_PIECES(sl)
+#undef RRQ_ADD_PIECES
         }
-        if (!act || kind == 2) continue;
+        if (!act || piece != 0) continue;
         const double* nu = snu + t * 3;
         // gradient of S^{lm} and its normal derivative: nu'.grad (d_a S^{lm}) is the same
         // ladder combination applied to the table nu'.grad S^{ab}

@@ -188,45 +188,70 @@ OrderTables build_order_tables(int q, int pt) {
     T.mrg_ptr.push_back((int32_t)T.mrg.size());
     if (d != T.dlp_ptr[lm + 1]) T.mrg_ptr.back() = -1;   // not a subset: flagged for the caller
   }
-  // translation slots: term lists longer than half of the longest are split in two halves,
-  // so that no slot carries much more than half of the longest list
-  int maxlen = 0;
-  for (int lm = 0; lm < T.np; ++lm) maxlen = std::max(maxlen, T.mrg_ptr[lm + 1] - T.mrg_ptr[lm]);
-  for (int lm = 0; lm < T.np; ++lm) {
-    const int len = T.mrg_ptr[lm + 1] - T.mrg_ptr[lm];
-    if (2 * len > maxlen + 1) {
-      if (T.tslot.size() & 1) T.tslot.push_back(3 << 8);
-      T.tslot.push_back(lm | (1 << 8));
-      T.tslot.push_back(lm | (2 << 8));
-    } else {
-      T.tslot.push_back(lm);
+  // translation slots: the term list of each (l, m) is split evenly into g = 1, 2 or 4
+  // pieces, one slot each; the g slots of a list are adjacent and start at a multiple of g.
+  // The bound M on a piece's length (a multiple of the chunk) is the one for which the slots
+  // of 4 targets take the fewest passes of a 256-lane workgroup times chunks per piece (ties:
+  // fewer slots).  The slot count is a multiple of 4, so that a list's pieces sit on lanes of
+  // one aligned group of the wavefront whichever target they belong to.
+  auto pieces = [&](int len, int M) {
+    int g = 1;
+    while ((len + g - 1) / g > M && g < 4) g *= 2;
+    return (len + g - 1) / g > M ? 0 : g;
+  };
+  int bestM = 0;
+  long best_cost = 0, best_n = 0;
+  for (int M = kTermChunk; M <= 1024; M += kTermChunk) {
+    long n = 0;
+    bool ok = true;
+    for (int lm = 0; lm < T.np && ok; ++lm) {
+      const int g = pieces(T.mrg_ptr[lm + 1] - T.mrg_ptr[lm], M);
+      ok = g > 0;
+      n += g;
+    }
+    if (!ok) continue;
+    n += (4 - n % 4) % 4;
+    const long cost = ((4 * n + 255) / 256) * (M / kTermChunk);
+    if (bestM == 0 || cost < best_cost || (cost == best_cost && n < best_n)) {
+      bestM = M;
+      best_cost = cost;
+      best_n = n;
     }
   }
-  if (T.tslot.size() & 1) T.tslot.push_back(3 << 8);
-  // step-major copy of each slot's terms (a half list is the first or second half of its
-  // (l, m) list, split at the midpoint, in list order)
+  std::vector<int> tbeg, tend;
+  for (int lg = 2; lg >= 0; --lg)   // groups of 4 first, then pairs, then single lists
+    for (int lm = 0; lm < T.np; ++lm) {
+      const int it0 = T.mrg_ptr[lm], len = T.mrg_ptr[lm + 1] - it0;
+      const int g = pieces(len, bestM);
+      if (g != 1 << lg) continue;
+      for (int pc = 0; pc < g; ++pc) {
+        T.tslot.push_back(lm | pc << 8 | lg << 12);
+        tbeg.push_back(it0 + len * pc / g);
+        tend.push_back(it0 + len * (pc + 1) / g);
+      }
+    }
+  while (T.tslot.size() % 4) {
+    T.tslot.push_back(kPadSlot);
+    tbeg.push_back(0);
+    tend.push_back(0);
+  }
   const int ns = (int)T.tslot.size();
   T.tlen.assign(ns, 0);
-  std::vector<int> tbeg(ns, 0);
   for (int sl = 0; sl < ns; ++sl) {
-    const int lm = T.tslot[sl] & 0xff, kind = T.tslot[sl] >> 8;
-    if (kind == 3) continue;
-    int it0 = T.mrg_ptr[lm], it1 = T.mrg_ptr[lm + 1];
-    const int mid = (it0 + it1) >> 1;
-    if (kind == 1) it1 = mid;
-    else if (kind == 2) it0 = mid;
-    tbeg[sl] = it0;
-    T.tlen[sl] = it1 - it0;
-    T.tsteps = std::max(T.tsteps, it1 - it0);
+    T.tlen[sl] = tend[sl] - tbeg[sl];
+    T.tsteps = std::max(T.tsteps, T.tlen[sl]);
   }
-  T.tnr.assign((size_t)T.tsteps * ns * 2, 0);
-  T.tcf.assign((size_t)T.tsteps * ns * 4, 0.0);
+  for (int sl = 0; sl < ns; ++sl)
+    T.tchunks = std::max(T.tchunks, (T.tlen[sl] + kTermChunk - 1) / kTermChunk);
+  const int npad = T.tchunks * kTermChunk;
+  T.tnr.assign((size_t)(T.tchunks + 1) * ns * kTermChunk, 0);
+  T.tcf.assign((size_t)npad * ns * 4, 0.0);
   for (int sl = 0; sl < ns; ++sl)
     for (int i = 0; i < T.tlen[sl]; ++i) {
       const Term2& t2 = T.mrg[tbeg[sl] + i];
+      T.tnr[((size_t)(i / kTermChunk) * ns + sl) * kTermChunk + i % kTermChunk] =
+          vq_rec(t2.n) << 8 | t2.r;
       const size_t e = (size_t)i * ns + sl;
-      T.tnr[2 * e] = vq_rec(t2.n);
-      T.tnr[2 * e + 1] = t2.r;
       T.tcf[4 * e] = t2.cDr;
       T.tcf[4 * e + 1] = t2.cDi;
       T.tcf[4 * e + 2] = t2.cSr;

@@ -56,20 +56,26 @@ struct OrderTables {
   std::vector<Term> dlp, slp;
   std::vector<int32_t> mrg_ptr;        // [np+1]
   std::vector<Term2> mrg;
-  // work slots of the translation step: lm | kind << 8, kind 0 = whole term list, 1 / 2 =
-  // first / second half (the two halves sit at an even and the next odd slot), 3 = padding;
-  // even length
+  // work slots of the translation step: lm | piece << 8 | lg << 12, the piece-th of the
+  // 1 << lg pieces of the term list of lm (lg = 0, 1, 2; the pieces of a list sit on
+  // adjacent slots starting at a multiple of 1 << lg), or kPadSlot; a multiple of 4 slots
   std::vector<int32_t> tslot;
   // the slots' term lists step-major: entry (step, slot) at step * tslot.size() + slot, so
-  // that the lanes of a wavefront, one slot each, read consecutive entries at every step;
-  // tlen[slot] terms per slot (0 for padding), tsteps = the longest
-  int tsteps = 0;
+  // that the lanes of a wavefront, one slot each, read consecutive entries at every step.
+  // tlen[slot] terms per slot (0 for padding); a slot's list is processed in chunks of
+  // kTermChunk steps, the last one padded with zero coefficients (operands at record 0,
+  // r = 0); tchunks = the most chunks of a slot.  The operand indices of a chunk are one
+  // int4, each entry vq_rec(n) << 8 | r, with one more all-zero chunk row at the end so that
+  // the next chunk can always be read ahead.
+  int tsteps = 0, tchunks = 0;
   std::vector<int32_t> tlen;
-  std::vector<int32_t> tnr;            // [tsteps][nslot][2]: vq_rec(n), r
-  std::vector<double> tcf;             // [tsteps][nslot][4]: cDr, cDi, cSr, cSi
+  std::vector<int32_t> tnr;            // [tchunks + 1][nslot][kTermChunk]: vq_rec(n) << 8 | r
+  std::vector<double> tcf;             // [tchunks * kTermChunk][nslot][4]: cDr, cDi, cSr, cSi
 };
 
 void gauss_legendre_ld(int n, std::vector<double>& t, std::vector<double>& w);
+constexpr int kTermChunk = 4;
+constexpr int32_t kPadSlot = 3 << 12;   // a translation slot with no terms
 OrderTables build_order_tables(int q, int ptilde);
 
 }  // namespace rrq

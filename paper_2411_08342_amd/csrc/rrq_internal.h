@@ -30,8 +30,8 @@ struct OrderDev {
   const int32_t* tslot;     // translation work slots (see OrderTables::tslot)
   int nslot;
   const int32_t* tlen;      // terms per slot
-  const int2* tnr;          // [tsteps][nslot]: vq_rec(n), r (step-major, see OrderTables)
-  const double4* tcf;       // [tsteps][nslot]: cDr, cDi, cSr, cSi
+  const int4* tnr;          // [tchunks + 1][nslot]: 4 steps of vq_rec(n) << 8 | r (see OrderTables)
+  const double4* tcf;       // [4 tchunks][nslot]: cDr, cDi, cSr, cSi (step-major)
 };
 
 // per-patch data layout constants
