@@ -1047,6 +1047,9 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
             nx[2 * u] = v.x;
             nx[2 * u + 1] = v.y;
           }
+          // keeps these loads ahead of this point's products (the scheduler would otherwise
+          // sink them to the end of the loop body, next to their use)
+          __builtin_amdgcn_sched_barrier(0);
           {
             const double* tdp = tdb + p * 8;
             const double w1 = tdp[0];
