@@ -23,8 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": "4492dce489cbc5d67b864c353f93927137365ad072db1bfda7e915d15caf0143",
-           "fetch_bytes": 2174463072, "write_bytes": 3605689576}
+TRAFFIC = {"src_sha256": "883fb49b9d8bf88095a6f12fd6cfa8c3636aaad11f1a91d6c6f1ddf1c380dced",
+           "fetch_bytes": 2139713404, "write_bytes": 3603655496}
 
 
 def flops_per_pair(q):
