@@ -220,7 +220,7 @@ rrq_status rrq_assemble(const rrq_plan* plan, const rrq_targets* tg, uint32_t km
  * same computation and the same output, with the workspace taken from a device array inside
  * the library, RRQ_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, held from the first call on that
  * GPU until the process ends.  Near lists whose rrq_workspace_size exceeds that return
- * RRQ_ERR_BUFFER before any launch (about 50,000 pairs when the largest order is 8).  The call
+ * RRQ_ERR_BUFFER before any launch (about 46,000 pairs when the largest order is 8).  The call
  * issues no hipMalloc, hipFree or memset, takes no statistics, and needs pair_off from
  * rrq_pair_offsets; out_len and pair_flags as for rrq_assemble.  All calls on one GPU share that GPU's array: calls that overlap in time
  * on one GPU (other streams, other threads) race and must be serialised by the caller. */

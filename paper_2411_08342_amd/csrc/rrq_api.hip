@@ -436,13 +436,14 @@ static TargetsDev tdev(const rrq_targets* tg, const unsigned* bad = nullptr) {
 // cnt[P] i32 | fill[P] i32 |
 // start[P+1] i64 | tstart[P+1] i64 | ntiles i64 | qtile[orders+1] i64, qctr[orders][xcds] u64 |
 // sorted[nnz] i64 | tiles[nnz/4 + P + 1] int4 | scan partials | root[4 nnz] double2 |
-// nearf[4 nnz] u8 | pairpot[nnz][4] f64 | plocal[nnz][9] f64 | pcoef[P][kCoefStride] f64 |
+// nearf[4 nnz] u8 | pairpot[nnz][4] f64 | plocal[nnz][9] f64 | ptd[nnz][16] f64 |
+// pti[nnz][4] i64 | pcoef[P][kCoefStride] f64 |
 // nlist[4 nnz] i64 |
 // lamg[4 nnz][lam_stride] f64 (near-edge moments; lam_stride = 2 ptilde_max + 1 >= 5; before
 // them, the root passes' Newton and retry lists, 4 nnz i64 each)
 struct WsLayout {
   size_t owner, counters, bad, pflags, cnt, fill, start, tstart, ntiles, queue, sorted, tiles,
-      part, root, nearf, pairpot, plocal, pcoef, nlist, lamg, total;
+      part, root, nearf, pairpot, plocal, ptd, pti, pcoef, nlist, lamg, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(int64_t nnz, int P, int lam_stride) {
@@ -466,6 +467,8 @@ static WsLayout ws_layout(int64_t nnz, int P, int lam_stride) {
   w.nearf = o; o = al(o + 4 * n);
   w.pairpot = o; o = al(o + 4 * n * 8);
   w.plocal = o; o = al(o + 9 * n * 8);
+  w.ptd = o; o = al(o + 16 * n * 8);
+  w.pti = o; o = al(o + 4 * n * 8);
   w.pcoef = o; o = al(o + (size_t)P * kCoefStride * 8);
   w.nlist = o; o = al(o + 4 * n * 8);
   w.lamg = o; o = al(o + 4 * n * (size_t)lam_stride * 8);
@@ -657,7 +660,8 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
   ao.root = nullptr;
   ao.nearf = nullptr;
   ao.lamg = nullptr;
-  ao.plocal = nullptr;
+  ao.ptd = nullptr;
+  ao.pti = nullptr;
   ao.lam_stride = 0;
   ao.dens = density;
   ao.pcoef = pot ? (const double*)(wb + wl.pcoef) : nullptr;
@@ -731,9 +735,13 @@ static rrq_status run_pairs(const rrq_plan* p, const rrq_targets* tg, uint32_t k
                          sorted, tiles, qtile, qctr, st) != hipSuccess)
         return RRQ_ERR_DEVICE;
       double* plocal = (double*)(wb + wl.plocal);
-      if (launch_pair_local(pd, td, owner, sorted, plocal, st) != hipSuccess)
+      double* ptd = (double*)(wb + wl.ptd);
+      int64_t* pti = (int64_t*)(wb + wl.pti);
+      if (launch_pair_local(pd, td, owner, sorted, pot ? nullptr : pair_off, plocal, ptd, pti,
+                            st) != hipSuccess)
         return RRQ_ERR_DEVICE;
-      ao.plocal = plocal;
+      ao.ptd = ptd;
+      ao.pti = pti;
       if (fork_roots && hipStreamWaitEvent(st, branches->root_join, 0) != hipSuccess)
         return RRQ_ERR_DEVICE;
       for (int qi = 0; qi < kNumOrders; ++qi) {

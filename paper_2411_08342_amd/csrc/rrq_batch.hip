@@ -553,10 +553,13 @@ __device__ __forceinline__ void pair_local(const PlanDev& pd, const double* fr, 
   for (int c = 0; c < 3; ++c) u[c] = sg * nn[c];
 }
 
-// Per-pair pre-pass: pair_local of every (target, patch) pair into plocal[9 k ..].
+// Per-pair pre-pass: pair_local of every (target, patch) pair into plocal[9 k ..], and the
+// pair's tile record (ptd, pti) at its position i in patch order, so that a tile reads its
+// targets' data from consecutive records with no dependent loads.
 __global__ __launch_bounds__(256) void k_pair_local(PlanDev pd, TargetsDev tg,
                                                     const int64_t* owner, const int64_t* sorted,
-                                                    double* plocal) {
+                                                    const int64_t* pair_off, double* plocal,
+                                                    double* ptd, int64_t* pti) {
   if (input_bad(tg)) return;
   // pairs in patch order (the binning's permutation), so that the lanes of a wavefront
   // mostly scan the nodes of one patch
@@ -576,20 +579,30 @@ __global__ __launch_bounds__(256) void k_pair_local(PlanDev pd, TargetsDev tg,
     }
     pair_local(pd, fr, n0, q2, self, xg, nv, xl, nl, u);
     double* o = plocal + 9 * k;
+    double* r = ptd + 16 * i;
     for (int c = 0; c < 3; ++c) {
-      o[c] = xl[c];
-      o[3 + c] = nl[c];
-      o[6 + c] = u[c];
+      o[c] = r[c] = xl[c];
+      o[3 + c] = r[3 + c] = nl[c];
+      o[6 + c] = r[6 + c] = u[c];
+      r[9 + c] = xg[c];
+      r[12 + c] = nv[c];
     }
+    r[15] = (double)self;
+    int64_t* ri = pti + 4 * i;
+    ri[0] = k;
+    ri[1] = g;
+    ri[2] = pair_off ? pair_off[k] : 0;
+    ri[3] = 0;
   }
 }
 
 hipError_t launch_pair_local(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
-                             const int64_t* sorted, double* plocal, hipStream_t st) {
+                             const int64_t* sorted, const int64_t* pair_off, double* plocal,
+                             double* ptd, int64_t* pti, hipStream_t st) {
   int64_t g = (tg.nnz + 255) / 256;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_pair_local, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, st, pd,
-                     tg, owner, sorted, plocal);
+                     tg, owner, sorted, pair_off, plocal, ptd, pti);
   return hipGetLastError();
 }
 
@@ -884,27 +897,25 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
       const int nt = min(T, tile.z - sub);
       __syncthreads();
       RRQ_PHASE(5)
-      // ---- patch frame, and the targets' data (32 threads per target, one value each): local
-      // point, normal and u from the per-pair pre-pass; global point and normal; ids
+      // ---- patch frame, and the targets' data from their tile records (32 threads per
+      // target, one value each): local point, normal and u; global point and normal; self
+      // node; pair, target and output offset
       if (tid < kFrame) fr[tid] = pd.frame[(int64_t)P * kFrame + tid];
       for (int it = tid; it < nt * 32; it += BNT) {
         const int t = it >> 5, f = it & 31;
         if (f >= 19) continue;
-        const int64_t k = sorted[tile.y + sub + t];
-        if (f < 9) {
-          const double v = out.plocal[9 * k + f];
+        const int64_t i = tile.y + sub + t;
+        if (f < 16) {
+          const double v = out.ptd[16 * i + f];
           if (f < 3) sx[t * 3 + f] = v;
           else if (f < 6) snu[t * 3 + f - 3] = v;
-          else su[t * 3 + f - 6] = v;
+          else if (f < 9) su[t * 3 + f - 6] = v;
+          else if (f < 15) sxg[t * 6 + f - 9] = v;
+          else sself[t] = (int)v;
           continue;
         }
-        const int64_t g = out.owner[k];
-        if (f < 12) sxg[t * 6 + f - 9] = tg.xyz[(f - 9) * tg.T + g];
-        else if (f < 15) sxg[t * 6 + f - 9] = tg.nrm[(f - 12) * tg.T + g];
-        else if (f == 15) sself[t] = (tg.self_patch[g] == P) ? tg.self_node[g] : -1;
-        else if (f == 16) sids[t * 3] = k;
-        else if (f == 17) sids[t * 3 + 1] = g;
-        else sids[t * 3 + 2] = POT ? 0 : out.pair_off[k];
+        const int64_t v = out.pti[4 * i + f - 16];
+        sids[t * 3 + f - 16] = (f == 18 && POT) ? 0 : v;
       }
       __syncthreads();
       RRQ_PHASE(0)

@@ -118,7 +118,11 @@ struct AssembleOut {
   const uint8_t* nearf;     // [4 nnz] 1: singularity-swap class, 0: plain rule
   const double* lamg;       // [4 nnz][lam_stride] near-edge moments (near slots only)
   int lam_stride;
-  const double* plocal;     // [nnz][9] per pair: target and its normal in the patch frame, u
+  // per pair at its position in patch order (the binning's permutation), the tile kernel's
+  // target data: ptd[16 i ..] = target and its normal in the patch frame, u, global point,
+  // global normal, self node (or -1); pti[4 i ..] = pair k, target, output offset, 0
+  const double* ptd;
+  const int64_t* pti;
   // potentials mode
   const double* dens;       // [N] nodal density
   const double* pcoef;      // [P][kCoefStride] c_D, c_S', c_S of every patch
@@ -208,9 +212,12 @@ hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const Tar
                          double* lamg, int lam_stride, double rho_far, hipStream_t st);
 // per pair k: plocal[9k ..] = target in the patch frame (3), its normal there (3), and u of
 // the solid-angle integrand (3): the target normal for a self target, else the normal of the
-// patch node nearest to the target (lowest index on ties) oriented toward it
+// patch node nearest to the target (lowest index on ties) oriented toward it; and the tile
+// records ptd, pti of AssembleOut at the pair's position in patch order (pair_off may be null:
+// offset 0)
 hipError_t launch_pair_local(const PlanDev& pd, const TargetsDev& tg, const int64_t* owner,
-                             const int64_t* sorted, double* plocal, hipStream_t st);
+                             const int64_t* sorted, const int64_t* pair_off, double* plocal,
+                             double* ptd, int64_t* pti, hipStream_t st);
 
 // learned initial guess: sample collection and training
 struct CollectOpts {
