@@ -23,8 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": "883fb49b9d8bf88095a6f12fd6cfa8c3636aaad11f1a91d6c6f1ddf1c380dced",
-           "fetch_bytes": 2139713404, "write_bytes": 3603655496}
+TRAFFIC = {"src_sha256": "4f028f703cca42ea54ce0bc2a661436d1f7814a4686a660bdb4cb8fe379b621c",
+           "fetch_bytes": 1638022543, "write_bytes": 3599471744}
 
 
 def flops_per_pair(q):
