@@ -751,6 +751,28 @@ hipError_t launch_lambda(int q, const PlanDev& pd, const OrderDev& od, const Tar
 // so the 8-dword spans of four consecutive targets use disjoint LDS banks
 __host__ __device__ constexpr int pad_banks(int n) { return n + ((4 - n) % 8 + 8) % 8; }
 
+// A double moved between lanes by a DPP permutation of each 16-lane row (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// v = sum of v over the aligned group of N lanes (N = 8, 16 or 32), in every lane of the
+// group: quad swaps (lanes i ^ 1, i ^ 2), then the mirror within 8 lanes and within 16, which
+// pair each partial sum with a disjoint one; across rows by a lane exchange.
+template <int N>
+__device__ __forceinline__ void row_sum(double& v) {
+  static_assert(N == 8 || N == 16 || N == 32, "group of 8, 16 or 32 lanes");
+  v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  if constexpr (N >= 16) v += dpp_f64<0x140>(v);   // row_mirror
+  if constexpr (N == 32) v += __shfl_xor(v, 16, 64);
+}
+
 template <int Q, int T>
 struct TileLds {
   static constexpr int PT = 2 * Q, NP = np_of(Q), NJK = njk_of(Q), NR = tri(Q, Q) + 1;
@@ -984,15 +1006,14 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
           const double cz = rp[0] * d[1] - rp[1] * d[0];
           dom0 = -w3 * (cx * nl[0] + cy * nl[1] + cz * nl[2]);
         }
+        // sums over the PTP lanes of (target, edge): DPP lane moves within rows of 16 lanes,
+        // then lane exchanges across rows (PTP = 32)
+        row_sum<PTP>(om0);
+        row_sum<PTP>(dom0);
 #pragma unroll
-        for (int o = PTP / 2; o > 0; o >>= 1) {
-          om0 += __shfl_xor(om0, o, 64);
-          dom0 += __shfl_xor(dom0, o, 64);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            ov[c] += __shfl_xor(ov[c], o, 64);
-            dv[c] += __shfl_xor(dv[c], o, 64);
-          }
+        for (int c = 0; c < 3; ++c) {
+          row_sum<PTP>(ov[c]);
+          row_sum<PTP>(dv[c]);
         }
         if (i == 0 && t < nt) {
           double* pp = part + te * 8;
