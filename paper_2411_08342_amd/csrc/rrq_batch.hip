@@ -1176,13 +1176,13 @@ void k_pair_tile(PlanDev pd, OrderDev od, TargetsDev tg,
           nr4 = nr4n;
         }
         // the 1 << lg pieces of a list sit on aligned adjacent lanes (the partner at distance d
-        // is idx ^ d): their partial sums are added with lg lane exchanges
+        // is idx ^ d): their partial sums are added with lg DPP quad swaps (lanes i ^ 1, i ^ 2)
         {
           double o;
 #define RRQ_ADD_PIECES(v)                    \
-  o = __shfl_xor(v, 1, 64);                  \
+  o = dpp_f64<0xB1>(v);                      \
   if (lg == 1 || lg == 2) v += o;            \
-  o = __shfl_xor(v, 2, 64);                  \
+  o = dpp_f64<0x4E>(v);                      \
   if (lg == 2) v += o;
           for (int c = 0; c < 4; ++c) {
             RRQ_ADD_PIECES(Ia[c]) RRQ_ADD_PIECES(dIa[c])
