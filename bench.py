@@ -23,8 +23,8 @@ FP64_VALU_PEAK = 78.6   # TFLOP/s, MI355X vector FP64 (256 CU x 2.4 GHz x 128 fl
 # WRITE_SIZE runs of this benchmark, scaled by the same counters for a 1 GiB copy
 # (bench.py --copy-probe: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # source it was measured on (sha256 of csrc/rrq_batch.hip); null otherwise.
-TRAFFIC = {"src_sha256": "4f028f703cca42ea54ce0bc2a661436d1f7814a4686a660bdb4cb8fe379b621c",
-           "fetch_bytes": 1638022543, "write_bytes": 3599471744}
+TRAFFIC = {"src_sha256": "90dfa7d221b8c7d25c5335b5f5ce7865dc75141df4643b54e0ac330ca982db8f",
+           "fetch_bytes": 1641407026, "write_bytes": 3599471744}
 
 
 def flops_per_pair(q):
